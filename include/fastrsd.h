@@ -1,0 +1,166 @@
+/*
+ * fastrsd -- FFT multipole estimators for redshift-space clustering on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Implements the power-spectrum and bispectrum multipole estimators of
+ * R. Scoccimarro, "Fast Estimators for Redshift-Space Clustering",
+ * arXiv:1506.02729:
+ *
+ *   F_0(k)   = (sum_g - alpha sum_r) w_j exp(i k.x_j)               Sec. III.A eq. (F0)
+ *   Q^{ab}   = (sum_g - alpha sum_r) xhat^a xhat^b w_j exp(i k.x_j)  Sec. III.A eq. (Qab)
+ *   F_2      = 3/2 khat_a khat_b Q^{ab} - 1/2 F_0                    Sec. III.A eq. (F2)
+ *   F_4      = 35/8 khat^4 Q^{abcd} - 5/2 F_2 - 7/8 F_0              Sec. II.B eqs. (delta4),(delta4b)
+ *   P_ell    = (2 ell + 1) <F_ell F_0^*>_shell / I22  (- N_0 for ell=0)  Sec. III.A eqs. (P0_impl)-(P4_impl)
+ *   B_ell    = (2 ell + 1) <F_ell F_0 F_0>_T / (N^T I33) - N^(ell)   Sec. III.B eqs. (BispMono),(BispQuad)
+ *
+ * with the triangle sum done by shell-filtered inverse FFTs and a grid sum
+ * of triple products (Sec. III.B eqs. (Factorize),(F_k)).
+ *
+ * Conventions shared by every call:
+ *  - Positions are in the box frame [0, L)^3 (Mpc/h).  An object outside the
+ *    box, or exactly at the observer, is rejected: it contributes nothing and
+ *    is counted (see frsd_status), never wrapped.
+ *  - Integer wave-vectors n use the fftfreq convention; k = (2 pi / L) n.
+ *  - A bin b covers [kmin + b dk, kmin + (b+1) dk); membership is decided on
+ *    the integer |n|^2 against squared edges in units of k_f = 2 pi / L,
+ *    snapped to the nearest integer when within 1e-9 relative.  DC is never
+ *    binned.  Mode counts are over the full grid (n and -n both counted).
+ *  - All device memory is owned by the caller.  The library never allocates
+ *    device memory: every call works inside the caller's workspace `ws`
+ *    (device pointer, 256-byte aligned, at least frsd_plan_workspace_bytes).
+ *  - `stream` is a hipStream_t passed as void*.  Device calls only enqueue
+ *    work on it and return; results are valid once the stream is
+ *    synchronised.  Calls on one workspace must be ordered on one stream.
+ *  - Every call returns FRSD_OK (0) or a negative error code, and then
+ *    frsd_last_error() describes the failure (thread-local).  No call
+ *    throws or exits.
+ */
+#ifndef FASTRSD_H
+#define FASTRSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FRSD_OK = 0,
+  FRSD_EINVAL = -1,  /* invalid parameter, size or pointer              */
+  FRSD_EDOM = -2,    /* objects outside the box or at the observer       */
+  FRSD_ENOMEM = -3,  /* workspace or catalogue capacity too small        */
+  FRSD_EHIP = -4,    /* a HIP runtime call failed                        */
+  FRSD_ESTATE = -5   /* calls out of order (e.g. bk before pk)           */
+};
+
+enum { FRSD_F32 = 32, FRSD_F64 = 64 };
+
+typedef struct frsd_plan frsd_plan;
+
+/* Estimator parameters (host struct, copied by frsd_plan_create). */
+typedef struct {
+  int32_t n_grid;      /* N, FFT mesh side: 2^a 3^b, multiple of 16, 16..1024          */
+  int32_t order;       /* mass assignment order p: 1 NGP, 2 CIC, 3 TSC                 */
+  int32_t interlace;   /* 1: interlaced twin grid at half-cell offset (Sec. III.A)    */
+  int32_t compensate;  /* 1: divide by prod_d sinc(pi n_d / N)^p                      */
+  int32_t ell_max;     /* 0, 2 or 4: multipoles computed (1, 7 or 22 moment meshes)   */
+  int32_t precision;   /* FRSD_F32 (served) or FRSD_F64 (plain) arithmetic            */
+  double box;          /* L, box side (Mpc/h)                                         */
+  double observer[3];  /* observer position in the box frame (may lie outside)        */
+  double pk_kmin, pk_dk; /* power-spectrum bins (h/Mpc); top edge <= k_Nyquist        */
+  int32_t pk_nbins;      /* >= 1                                                      */
+  double bk_kmin, bk_dk; /* bispectrum bins (h/Mpc); top edge <= k_Nyquist            */
+  int32_t bk_nbins;      /* 0: no bispectrum                                          */
+  int32_t bk_grid;       /* M, real-space grid of the triangle search; 0: smallest
+                            2^a 3^b with M > 3 n_c (n_c = largest integer below the
+                            top bispectrum edge in k_f units), which makes the grid
+                            sum equal to the exact closed-triangle sum              */
+  int64_t max_objects;   /* capacity: galaxies + randoms per frsd_mesh_assign call    */
+} frsd_params;
+
+/* A catalogue in device memory.  pos is n x 3 interleaved (x, y, z);
+ * w and nbar have n entries.  nbar may be NULL for galaxies (it only enters
+ * I22 and I33 through the randoms).  dtype is FRSD_F32 or FRSD_F64 and
+ * applies to all three arrays. */
+typedef struct {
+  const void *pos;
+  const void *w;
+  const void *nbar;
+  int64_t n;
+  int32_t dtype;
+} frsd_catalog;
+
+/* Power-spectrum outputs: caller-owned DEVICE arrays of pk_nbins entries
+ * (scalars: 4 entries).  Written by frsd_pk_multipoles. */
+typedef struct {
+  int64_t *n_modes;  /* N_b, full-grid mode count                                  */
+  double *k_eff;     /* mean |k| over the modes of the bin                          */
+  double *p0, *p2, *p4;   /* P_ell of eqs. (P0_impl)-(P4_impl); NaN if I22 == 0   */
+  double *s00, *s20, *s40; /* raw shell sums sum_b Re[F_ell F_0^*]                */
+  double *scalars;   /* [I22, N_0, I33, W3]: I22 = alpha sum_r nbar w^2 (eq. I22def),
+                        N_0 = (sum_g + alpha^2 sum_r) w^2 (eq. N0true),
+                        I33 = alpha sum_r nbar^2 w^3, W3 = (sum_g - alpha^3 sum_r) w^3 */
+} frsd_pk_out;
+
+/* Bispectrum outputs: caller-owned DEVICE arrays of ntri entries, one per
+ * triangle of frsd_bk_triangles (in that order). */
+typedef struct {
+  double *nt;             /* N^T, exact count of closed lattice triangles (eq. NT)  */
+  double *t0, *t2, *t4;   /* raw triangle sums sum_T Re F_ell(q1) F_0(q2) F_0(q3)   */
+  double *b0, *b2, *b4;   /* (2 ell + 1) T_ell / (N^T I33); NaN when N^T == 0        */
+  double *sn0, *sn2, *sn4;/* thin-shell shot noise (eq. SNbisp2thin): sn0 complete,
+                             sn2/sn4 the q1 term only.  B_ell = b_ell - sn_ell      */
+} frsd_bk_out;
+
+/* Validates parameters and builds the host-side plan: bins, triangle list,
+ * FFT radix schedules and the workspace layout.  Host only. */
+int frsd_plan_create(const frsd_params *params, frsd_plan **plan);
+void frsd_plan_destroy(frsd_plan *plan);
+
+/* Exact device workspace size for this plan (bytes). */
+int frsd_plan_workspace_bytes(const frsd_plan *plan, size_t *bytes);
+
+/* Uploads tables into ws and, with a bispectrum, computes N^T for every
+ * listed triangle (FP64, exact to rounding).  Required once per workspace
+ * before any other device call.  Asynchronous on `stream`. */
+int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Steps a1-a4: line of sight, sort by cell, interlaced B-spline assignment
+ * of the moment meshes (weights w, w xhat_i xhat_j, w xhat_i xhat_j xhat_k
+ * xhat_l and, with a bispectrum, the w^2 mesh of F_0^w) and their forward
+ * FFTs (Sec. III.A eq. (mapFFT)).  Galaxies enter with sign +1, randoms
+ * with -alpha; ran may have n == 0.  alpha is explicit (the paper's
+ * N_g / N_r is the usual choice).  Also reduces I22, N_0, I33, W3.
+ * FRSD_ENOMEM if gal->n + ran->n > max_objects. */
+int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *gal,
+                     const frsd_catalog *ran, double alpha, void *stream);
+
+/* Steps a5-a6: multipole combination and shell binning into P_0, P_2, P_4.
+ * Requires a preceding frsd_mesh_assign on ws.  Also extracts the low-k
+ * multipole fields that frsd_bk_multipoles uses. */
+int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *out, void *stream);
+
+/* Number of listed triangles and the list itself (host array of 3*ntri
+ * int32: b1 >= b2 >= b3 with lo(b1) < hi(b2) + hi(b3), lexicographic). */
+int frsd_bk_ntriangles(const frsd_plan *plan, int64_t *ntri);
+int frsd_bk_triangles(const frsd_plan *plan, int32_t *b123);
+
+/* Steps a7-a9: shell-filtered inverse FFTs of F_0, F_2, F_4 on the M^3 grid,
+ * triple-product contraction over all listed triangles and normalisation
+ * (Sec. III.B).  Requires a preceding frsd_pk_multipoles on ws. */
+int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *stream);
+
+/* Synchronises `stream` and reports the number of objects rejected by the
+ * last frsd_mesh_assign (outside [0, L)^3 or at the observer).  Returns
+ * FRSD_EDOM when that number is non-zero. */
+int frsd_status(frsd_plan *plan, void *ws, int64_t *n_rejected, void *stream);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *frsd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTRSD_H */

@@ -1,0 +1,106 @@
+// C ABI entry points (include/fastrsd.h): argument validation, call order,
+// and dispatch to the FP32 or FP64 kernel instantiations.
+#include <cstring>
+
+#include "frsd_internal.h"
+
+using namespace frsd;
+
+static int check_ws(const frsd_plan *pl, const void *ws) {
+  if (!pl) return fail(FRSD_EINVAL, "null plan");
+  if (!ws) return fail(FRSD_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(FRSD_EINVAL, "workspace must be 256-byte aligned");
+  return FRSD_OK;
+}
+
+static int check_catalog(const frsd_catalog *c, bool need_nbar, const char *what) {
+  if (!c) return fail(FRSD_EINVAL, std::string("null catalogue: ") + what);
+  if (c->n < 0) return fail(FRSD_EINVAL, std::string("negative size: ") + what);
+  if (c->n == 0) return FRSD_OK;
+  if (c->dtype != FRSD_F32 && c->dtype != FRSD_F64) return fail(FRSD_EINVAL, std::string("dtype must be 32 or 64: ") + what);
+  if (!c->pos || !c->w) return fail(FRSD_EINVAL, std::string("null pos or w: ") + what);
+  if (need_nbar && !c->nbar) return fail(FRSD_EINVAL, std::string("randoms need nbar: ") + what);
+  return FRSD_OK;
+}
+
+extern "C" int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (ws_bytes < plan->L.total) return fail(FRSD_ENOMEM, "workspace smaller than frsd_plan_workspace_bytes");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = upload_tables(plan, ws, s);
+  if (rc) return rc;
+  if (plan->p.bk_nbins > 0) {
+    rc = run_nt(plan, ws, s);
+    if (rc) return rc;
+  }
+  plan->state = 1;
+  plan->init_ws = ws;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *gal, const frsd_catalog *ran,
+                                double alpha, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (plan->state < 1 || plan->init_ws != ws) return fail(FRSD_ESTATE, "workspace not initialised by frsd_plan_init");
+  if ((rc = check_catalog(gal, false, "galaxies"))) return rc;
+  if ((rc = check_catalog(ran, true, "randoms"))) return rc;
+  if (!std::isfinite(alpha)) return fail(FRSD_EINVAL, "alpha must be finite");
+  if (gal->n + ran->n > plan->p.max_objects)
+    return fail(FRSD_ENOMEM, "galaxies + randoms exceed max_objects of the plan");
+  if (gal->n + ran->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->p.precision == FRSD_F64) rc = run_mesh_assign<double>(plan, ws, gal, ran, alpha, s);
+  else rc = run_mesh_assign<float>(plan, ws, gal, ran, alpha, s);
+  if (rc) return rc;
+  plan->state = 2;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *out, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (plan->state < 2 || plan->init_ws != ws) return fail(FRSD_ESTATE, "frsd_pk_multipoles needs frsd_mesh_assign first");
+  if (!out || !out->n_modes || !out->k_eff || !out->p0 || !out->p2 || !out->p4 || !out->s00 || !out->s20 ||
+      !out->s40 || !out->scalars)
+    return fail(FRSD_EINVAL, "null output array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->p.precision == FRSD_F64) rc = run_pk<double>(plan, ws, out, s);
+  else rc = run_pk<float>(plan, ws, out, s);
+  if (rc) return rc;
+  plan->state = 3;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (plan->p.bk_nbins == 0) return fail(FRSD_EINVAL, "plan has no bispectrum bins");
+  if (plan->state < 3 || plan->init_ws != ws) return fail(FRSD_ESTATE, "frsd_bk_multipoles needs frsd_pk_multipoles first");
+  if (!out || !out->nt || !out->t0 || !out->t2 || !out->t4 || !out->b0 || !out->b2 || !out->b4 || !out->sn0 ||
+      !out->sn2 || !out->sn4)
+    return fail(FRSD_EINVAL, "null output array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->p.precision == FRSD_F64) rc = run_bk<double>(plan, ws, out, s);
+  else rc = run_bk<float>(plan, ws, out, s);
+  return rc;
+}
+
+extern "C" int frsd_status(frsd_plan *plan, void *ws, int64_t *n_rejected, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (!n_rejected) return fail(FRSD_EINVAL, "null output");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FRSD_HIP(hipStreamSynchronize(s));
+  unsigned long long v = 0;
+  FRSD_HIP(hipMemcpy(&v, ws_ptr<void>(ws, plan->L.reject), sizeof(v), hipMemcpyDeviceToHost));
+  *n_rejected = (int64_t)v;
+  if (v) return fail(FRSD_EDOM, "objects outside [0, L)^3 or at the observer were rejected");
+  return FRSD_OK;
+}

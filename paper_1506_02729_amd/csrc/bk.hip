@@ -1,0 +1,415 @@
+// Steps a7-a9: bispectrum multipoles by the FFT triangle search
+// (Sec. III.B eqs. Factorize, F_k, BispMono, BispQuad, SNbisp2thin).
+//
+// For every bispectrum bin b and multipole field F_ell (ell = 0, 2, 4) the
+// shell field F_{ell,b}(x) = sum_{n in b} F_ell(n) exp(+2 pi i n.x / M) is
+// built on an M^3 grid by a pruned 3D inverse FFT: the input is non-zero
+// only on |n_d| <= n_c, so the z pass runs on the (2 n_c + 1)^2 columns of
+// the low-k cube, the y pass on (2 n_c + 1) x M rows and only the x pass on
+// all M^2 rows.  Two real shell fields are packed in one complex transform
+// (their spectra are Hermitian, so the real and imaginary parts of the
+// output separate them).
+//
+// The triangle sums T_ell(b1,b2,b3) = M^-3 sum_x F_{ell,b1} F_{0,b2} F_{0,b3}
+// equal the sums over closed triangles when M > 3 n_c.  N^T is the same sum
+// of indicator fields, done once per plan in FP64 and rounded.
+#include <cmath>
+#include <vector>
+
+#include "device.h"
+#include "frsd_internal.h"
+
+namespace frsd {
+
+constexpr int kShThreads = 256;
+constexpr int kShPN = 4096;
+constexpr int kTriThreads = 256;
+constexpr int kTriKO = 32;     // outputs per thread
+constexpr int kTriChunk = 64;  // cells staged per step
+
+struct ShellArgs {
+  int M, D, nc, nb, nfield;
+  int pair0, npair;
+  int lut_len;
+};
+
+static StageList stage_list(const FftLen &f) {
+  StageList s{};
+  s.nstage = f.nstage;
+  for (int i = 0; i < f.nstage; ++i) s.radix[i] = f.radix[i];
+  return s;
+}
+
+// z pass: pencils (pair, ix, iy) of the low-k cube, output buf1[pair][ix][iy][z]
+template <typename T, bool IND>
+__global__ __launch_bounds__(kShThreads) void k_shell_z(const cplx_t<T> *__restrict__ lowk,
+                                                        const int16_t *__restrict__ lut, ShellArgs a, int P,
+                                                        StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + a.M;
+  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const long long DD = (long long)D * D;
+  const long long npen_all = (long long)a.npair * DD;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  __syncthreads();
+  const long long DDD = DD * D;
+  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+    const int p = f / D, kz = f - p * D;
+    const long long q = q0 + p;
+    const int pair = (int)(q / DD);
+    const int col = (int)(q - (long long)pair * DD);
+    const int ix = col / D, iy = col - ix * D;
+    const int nx = ix - nc, ny = iy - nc, nz = kz - nc;
+    const long long m2 = (long long)nx * nx + (long long)ny * ny + (long long)nz * nz;
+    const int b = (m2 > 0 && m2 < a.lut_len) ? lut[m2] : -1;
+    const int fa = 2 * (a.pair0 + pair), fb = fa + 1;
+    T ar = 0, ai = 0, br = 0, bi = 0;
+    if (b >= 0) {
+      if (fa % a.nb == b) {
+        if (IND) ar = T(1);
+        else { const C v = lowk[(fa / a.nb) * DDD + ((long long)ix * D + iy) * D + kz]; ar = v.x; ai = v.y; }
+      }
+      if (fb < a.nfield && fb % a.nb == b) {
+        if (IND) br = T(1);
+        else { const C v = lowk[(fb / a.nb) * DDD + ((long long)ix * D + iy) * D + kz]; br = v.x; bi = v.y; }
+      }
+    }
+    // Z = A + i B
+    lds[p * ld + (nz + M) % M] = cmake<C>(ar - bi, ai + br);
+  }
+  __syncthreads();
+  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
+  C *dst = buf1 + q0 * M;
+  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+    const int p = f / M, e = f - p * M;
+    dst[f] = lds[p * ld + e];
+  }
+}
+
+// y pass: pencils (pair, ix, z); input buf1[pair][ix][iy][z], output buf2[pair][ix][y][z]
+template <typename T>
+__global__ __launch_bounds__(kShThreads) void k_shell_y(const cplx_t<T> *__restrict__ buf1, ShellArgs a, int P,
+                                                        StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + a.M;
+  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const long long npen_all = (long long)a.npair * D * M;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  __syncthreads();
+  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+    const int iy = f / npen, p = f - iy * npen;
+    const long long q = q0 + p;               // q = (pair * D + ix) * M + z
+    const long long pix = q / M;
+    const int z = (int)(q - pix * M);
+    lds[p * ld + (iy - nc + M) % M] = buf1[(pix * D + iy) * M + z];
+  }
+  __syncthreads();
+  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
+  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+    const int y = f / npen, p = f - y * npen;
+    const long long q = q0 + p;
+    const long long pix = q / M;
+    const int z = (int)(q - pix * M);
+    buf2[(pix * M + y) * M + z] = lds[p * ld + y];
+  }
+}
+
+// x pass: pencils (pair, y, z); input buf2[pair][ix][y][z]; output the two
+// real shell fields of the pair, shells[f][x][y][z]
+template <typename T, typename TO>
+__global__ __launch_bounds__(kShThreads) void k_shell_x(const cplx_t<T> *__restrict__ buf2, ShellArgs a, int P,
+                                                        StageList st, const cplx_t<T> *tw_g, TO *shells) {
+  using C = cplx_t<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + a.M;
+  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const long long MM = (long long)M * M;
+  const long long npen_all = (long long)a.npair * MM;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  __syncthreads();
+  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+    const int ix = f / npen, p = f - ix * npen;
+    const long long q = q0 + p;               // q = pair * M^2 + (y * M + z)
+    const long long pair = q / MM;
+    const long long yz = q - pair * MM;
+    lds[p * ld + (ix - nc + M) % M] = buf2[(pair * D + ix) * MM + yz];
+  }
+  __syncthreads();
+  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
+  const long long MMM = MM * M;
+  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+    const int x = f / npen, p = f - x * npen;
+    const long long q = q0 + p;
+    const long long pair = q / MM;
+    const long long yz = q - pair * MM;
+    const int fa = 2 * (a.pair0 + (int)pair), fb = fa + 1;
+    const C v = lds[p * ld + x];
+    shells[(long long)fa * MMM + x * MM + yz] = (TO)v.x;
+    if (fb < a.nfield) shells[(long long)fb * MMM + x * MM + yz] = (TO)v.y;
+  }
+}
+
+template <typename T, typename TO, bool IND>
+static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
+  using C = cplx_t<T>;
+  const Layout &L = pl->L;
+  ShellArgs a{};
+  a.M = pl->M; a.D = pl->D; a.nc = pl->nc_b; a.nb = pl->p.bk_nbins; a.nfield = nfield;
+  a.lut_len = pl->bk_lut_len;
+  const int M = a.M, D = a.D;
+  const int P = kShPN / M;
+  const StageList st = stage_list(pl->fft_m);
+  const size_t shmem = sizeof(C) * ((size_t)M + (size_t)P * (M + 1));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z<T, IND>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int npairs = (nfield + 1) / 2;
+  for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
+    a.pair0 = p0;
+    a.npair = std::min(kPairBatch, npairs - p0);
+    const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * M,
+                    nx = (long long)a.npair * M * M;
+    hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(kShThreads), shmem, s,
+                       ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, P, st, (const C *)tw,
+                       ws_ptr<C>(ws, L.buf1));
+    hipLaunchKernelGGL((k_shell_y<T>), dim3((unsigned)((ny + P - 1) / P)), dim3(kShThreads), shmem, s,
+                       ws_ptr<const C>(ws, L.buf1), a, P, st, (const C *)tw, ws_ptr<C>(ws, L.buf2));
+    hipLaunchKernelGGL((k_shell_x<T, TO>), dim3((unsigned)((nx + P - 1) / P)), dim3(kShThreads), shmem, s,
+                       ws_ptr<const C>(ws, L.buf2), a, P, st, (const C *)tw, shells);
+    FRSD_LAUNCH_CHECK();
+  }
+  return FRSD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Triple-product contraction (vector FMA version): out[o] = sum_x
+// F[ta](x) F[tb](x) F[tc](x) for every output o = (ta, tb, tc), as per-block
+// FP64 partials over grid-strided chunks of cells.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kTriThreads) void k_triple(const T *__restrict__ f, long long ncell, int nfield,
+                                                        const int4 *__restrict__ otab, int nout, double *part) {
+  extern __shared__ unsigned char smem_raw[];
+  T *st = reinterpret_cast<T *>(smem_raw);  // [nfield][kTriChunk]
+  int ta[kTriKO], tb[kTriKO], tc[kTriKO];
+  double acc[kTriKO];
+  const int obase = blockIdx.y * (kTriThreads * kTriKO);
+#pragma unroll
+  for (int j = 0; j < kTriKO; ++j) {
+    const int o = obase + threadIdx.x + j * kTriThreads;
+    acc[j] = 0.0;
+    if (o < nout) { const int4 e = otab[o]; ta[j] = e.x; tb[j] = e.y; tc[j] = e.z; }
+    else { ta[j] = 0; tb[j] = 0; tc[j] = 0; }
+  }
+  for (long long c0 = (long long)blockIdx.x * kTriChunk; c0 < ncell; c0 += (long long)gridDim.x * kTriChunk) {
+    const int len = (int)((c0 + kTriChunk <= ncell) ? kTriChunk : (ncell - c0));
+    __syncthreads();
+    for (int i = threadIdx.x; i < nfield * kTriChunk; i += kTriThreads) {
+      const int fl = i / kTriChunk, c = i - fl * kTriChunk;
+      st[i] = (c < len) ? f[(long long)fl * ncell + c0 + c] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTriKO; ++j) {
+      if (obase + threadIdx.x + j * kTriThreads < nout) {
+        const T *pa = st + ta[j] * kTriChunk, *pb = st + tb[j] * kTriChunk, *pc = st + tc[j] * kTriChunk;
+        T sacc = T(0);
+        for (int c = 0; c < kTriChunk; ++c) sacc += pa[c] * pb[c] * pc[c];
+        acc[j] += (double)sacc;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kTriKO; ++j) {
+    const int o = obase + threadIdx.x + j * kTriThreads;
+    if (o < nout) part[(long long)o * gridDim.x + blockIdx.x] = acc[j];
+  }
+}
+
+__global__ void k_sum_part(const double *part, int nblk, int nvals, double *sum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvals) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[(long long)i * nblk + b];
+  sum[i] = s;
+}
+
+__global__ void k_nt_final(const double *sum, int ntri, double inv_m3, double *nt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntri) nt[t] = rint(sum[t] * inv_m3);
+}
+
+struct BkFinalArgs {
+  int ntri, n_ell, pk_nb;
+  double inv_m3;
+};
+
+__global__ void k_bk_final(const int *tri, const double *tsum, const double *nt, const double *bin_sum,
+                           const double *scal, BkFinalArgs a, frsd_bk_out out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ntri) return;
+  const double I33 = scal[2], W3 = scal[3];
+  const double NT = nt[t];
+  const int b[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+  const double nan = __builtin_nan("");
+  double *tp[3] = {out.t0, out.t2, out.t4};
+  double *bp[3] = {out.b0, out.b2, out.b4};
+  double *sp[3] = {out.sn0, out.sn2, out.sn4};
+  out.nt[t] = NT;
+  for (int li = 0; li < 3; ++li) {
+    const double ell = 2.0 * li;
+    if (li < a.n_ell) {
+      const double T = tsum[t * a.n_ell + li] * a.inv_m3;
+      tp[li][t] = T;
+      bp[li][t] = NT > 0 ? (2 * ell + 1) * T / (NT * I33) : nan;
+    } else {
+      tp[li][t] = nan; bp[li][t] = nan;
+    }
+  }
+  // bin sums of the bispectrum bins: [count, sum|k|, S00, S20, S40, S0w, S2w, S4w]
+  auto bs = [&](int bin, int q) { return bin_sum[(a.pk_nb + bin) * kBinSums + q]; };
+  double sn0 = 0;
+  for (int i = 0; i < 3; ++i) sn0 += bs(b[i], 5) / bs(b[i], 0);
+  sp[0][t] = sn0 / I33 - 2.0 * W3 / I33;
+  sp[1][t] = a.n_ell > 1 ? 5.0 * bs(b[0], 6) / (bs(b[0], 0) * I33) : nan;
+  sp[2][t] = a.n_ell > 2 ? 9.0 * bs(b[0], 7) / (bs(b[0], 0) * I33) : nan;
+}
+
+template <typename T>
+static int contract(frsd_plan *pl, void *ws, const T *fields, int nfield, const int4 *otab, int nout,
+                    hipStream_t s) {
+  const Layout &L = pl->L;
+  const long long M3 = (long long)pl->M * pl->M * pl->M;
+  const size_t shmem = sizeof(T) * (size_t)nfield * kTriChunk;
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_triple<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const unsigned ny = (unsigned)((nout + kTriThreads * kTriKO - 1) / (kTriThreads * kTriKO));
+  hipLaunchKernelGGL(k_triple<T>, dim3(kTriBlocks, ny), dim3(kTriThreads), shmem, s, fields, M3, nfield, otab, nout,
+                     ws_ptr<double>(ws, L.tri_part));
+  hipLaunchKernelGGL(k_sum_part, dim3((nout + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.tri_part),
+                     kTriBlocks, nout, ws_ptr<double>(ws, L.tri_sum));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+// N^T of every listed triangle from FP64 indicator fields.
+int run_nt(frsd_plan *pl, void *ws, hipStream_t s) {
+  const Layout &L = pl->L;
+  double *shells = ws_ptr<double>(ws, L.shells);
+  int rc = shell_pipeline<double, double, true>(pl, ws, pl->p.bk_nbins, ws_ptr<void>(ws, L.tw_inv64), shells, s);
+  if (rc) return rc;
+  const int4 *otab = ws_ptr<const int4>(ws, L.tri_tab) + pl->n_out;
+  rc = contract<double>(pl, ws, shells, pl->p.bk_nbins, otab, (int)pl->ntri, s);
+  if (rc) return rc;
+  const double inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
+  hipLaunchKernelGGL(k_nt_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s,
+                     ws_ptr<const double>(ws, L.tri_sum), (int)pl->ntri, inv_m3, ws_ptr<double>(ws, L.nt));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+template <typename T>
+int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s) {
+  const Layout &L = pl->L;
+  const int nfield = pl->n_ell * pl->p.bk_nbins;
+  T *shells = ws_ptr<T>(ws, L.shells);
+  int rc = shell_pipeline<T, T, false>(pl, ws, nfield, ws_ptr<void>(ws, L.tw_inv), shells, s);
+  if (rc) return rc;
+  rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+  if (rc) return rc;
+  BkFinalArgs a{};
+  a.ntri = (int)pl->ntri; a.n_ell = pl->n_ell; a.pk_nb = pl->p.pk_nbins;
+  a.inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
+  // the triangle list is kept in the tail of the table region as int32 triples
+  const int *tri = reinterpret_cast<const int *>(ws_ptr<const int4>(ws, L.tri_tab) + pl->n_out + pl->ntri);
+  hipLaunchKernelGGL(k_bk_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s, tri,
+                     ws_ptr<const double>(ws, L.tri_sum), ws_ptr<const double>(ws, L.nt),
+                     ws_ptr<const double>(ws, L.bin_sum), ws_ptr<const double>(ws, L.scal), a, *out);
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+template int run_bk<float>(frsd_plan *, void *, const frsd_bk_out *, hipStream_t);
+template int run_bk<double>(frsd_plan *, void *, const frsd_bk_out *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Tables uploaded by frsd_plan_init.
+// ---------------------------------------------------------------------------
+template <typename T>
+static std::vector<T> twiddles(int n) {
+  // W_n^e = exp(-2 pi i e / n), interleaved (re, im)
+  std::vector<T> t(2 * (size_t)n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int e = 0; e < n; ++e) {
+    const long double a = two_pi * (long double)e / (long double)n;
+    t[2 * e] = (T)cosl(a);
+    t[2 * e + 1] = (T)(-sinl(a));
+  }
+  return t;
+}
+
+static std::vector<int16_t> bin_lut(const std::vector<double> &e2, int len) {
+  std::vector<int16_t> lut(len, -1);
+  const int nb = (int)e2.size() - 1;
+  for (int m = 1; m < len; ++m) {
+    for (int b = 0; b < nb; ++b)
+      if ((double)m >= e2[b] && (double)m < e2[b + 1]) { lut[m] = (int16_t)b; break; }
+  }
+  return lut;
+}
+
+int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
+  const Layout &L = pl->L;
+  FRSD_HIP(hipStreamSynchronize(s));
+  const bool f64 = pl->p.precision == FRSD_F64;
+  if (f64) {
+    auto t = twiddles<double>(pl->N);
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_fwd), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    auto t = twiddles<float>(pl->N);
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_fwd), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  auto lp = bin_lut(pl->pk_e2, pl->pk_lut_len);
+  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.pk_lut), lp.data(), lp.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  if (pl->p.bk_nbins > 0) {
+    if (f64) {
+      auto t = twiddles<double>(pl->M);
+      FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      auto t = twiddles<float>(pl->M);
+      FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    auto t64 = twiddles<double>(pl->M);
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv64), t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    auto lb = bin_lut(pl->bk_e2, pl->bk_lut_len);
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.bk_lut), lb.data(), lb.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    // contraction tables: data outputs (field of b1 for each ell, b2, b3), then
+    // indicator outputs (b1, b2, b3), then the raw int32 triangle list
+    const int nb = pl->p.bk_nbins;
+    std::vector<int4> tab((size_t)pl->n_out + (size_t)pl->ntri);
+    for (int64_t t = 0; t < pl->ntri; ++t) {
+      const int b1 = pl->tri[3 * t], b2 = pl->tri[3 * t + 1], b3 = pl->tri[3 * t + 2];
+      for (int li = 0; li < pl->n_ell; ++li) tab[t * pl->n_ell + li] = make_int4(li * nb + b1, b2, b3, 0);
+      tab[pl->n_out + t] = make_int4(b1, b2, b3, 0);
+    }
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tri_tab), tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice));
+    FRSD_HIP(hipMemcpy(ws_ptr<int4>(ws, L.tri_tab) + tab.size(), pl->tri.data(), pl->tri.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+  }
+  return FRSD_OK;
+}
+
+}  // namespace frsd

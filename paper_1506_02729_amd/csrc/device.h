@@ -1,0 +1,170 @@
+// Device helpers: complex arithmetic, wavefront reductions and the
+// LDS-resident mixed-radix Stockham FFT used by every transform in the
+// library (forward moment-mesh FFTs and shell-filtered inverse FFTs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace frsd {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+template <typename T> using cplx_t = typename Cplx<T>::type;
+
+template <typename C> __device__ __forceinline__ C cmake(decltype(C{}.x) a, decltype(C{}.x) b) {
+  C r; r.x = a; r.y = b; return r;
+}
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return cmake<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return cmake<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return cmake<C>(a.x, -a.y); }
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) {
+  return cmake<C>(a.x * s, a.y * s);
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename C, bool INV> __device__ __forceinline__ C cmul_mi(C a) {
+  return INV ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront (64-lane) sum of a double.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs.  Forward uses exp(-2 pi i r k / R); INV uses exp(+...).
+// ---------------------------------------------------------------------------
+template <typename C, bool INV> __device__ __forceinline__ void dft2(C &a, C &b) {
+  C t = a; a = cadd(t, b); b = csub(t, b);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft4(C &x0, C &x1, C &x2, C &x3) {
+  C t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3);
+  C t3 = cmul_mi<C, INV>(csub(x1, x3));
+  x0 = cadd(t0, t2); x2 = csub(t0, t2); x1 = cadd(t1, t3); x3 = csub(t1, t3);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft3(C &x0, C &x1, C &x2) {
+  using S = decltype(C{}.x);
+  const S h = S(0.8660254037844386467637231707529361834714);  // sqrt(3)/2
+  C t = cadd(x1, x2);
+  C m = csub(x0, cscale(t, S(0.5)));
+  C d = csub(x1, x2);
+  // s = d * (-i sqrt3/2) forward, d * (+i sqrt3/2) inverse
+  C s = cscale(cmul_mi<C, INV>(d), h);
+  x0 = cadd(x0, t); x1 = cadd(m, s); x2 = csub(m, s);
+}
+
+template <typename C, bool INV> __device__ __forceinline__ void dft8(C *v) {
+  using S = decltype(C{}.x);
+  const S r = S(0.7071067811865475244008443621048490392848);  // 1/sqrt(2)
+  // even / odd 4-point transforms
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<C, INV>(e0, e1, e2, e3);
+  dft4<C, INV>(o0, o1, o2, o3);
+  // twiddles W8^k, k = 1, 2, 3 (conjugated for INV)
+  C w1 = INV ? cmake<C>(r * (o1.x - o1.y), r * (o1.x + o1.y))
+             : cmake<C>(r * (o1.x + o1.y), r * (o1.y - o1.x));
+  C w2 = cmul_mi<C, INV>(o2);
+  C w3 = INV ? cmake<C>(-r * (o3.x + o3.y), r * (o3.x - o3.y))
+             : cmake<C>(r * (o3.y - o3.x), -r * (o3.x + o3.y));
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, w1); v[5] = csub(e1, w1);
+  v[2] = cadd(e2, w2); v[6] = csub(e2, w2);
+  v[3] = cadd(e3, w3); v[7] = csub(e3, w3);
+}
+
+template <typename C, int R, bool INV> __device__ __forceinline__ void dftR(C *v) {
+  if constexpr (R == 2) dft2<C, INV>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<C, INV>(v[0], v[1], v[2]);
+  else if constexpr (R == 4) dft4<C, INV>(v[0], v[1], v[2], v[3]);
+  else dft8<C, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham stage of radix R on P pencils of length n held in LDS
+// (pencil p at lds[p * ld .. p * ld + n)).  Ns is the product of the radices
+// already applied.  Each butterfly j reads x[j + r n/R], applies the twiddle
+// W_{Ns R}^{r (j mod Ns)}, does an R-point DFT and writes the results to
+// (j / Ns) Ns R + (j mod Ns) + r Ns.  All reads of the stage complete
+// (barrier) before any write, so the stage runs in place.
+// tw holds W_n^e = exp(-2 pi i e / n), e in [0, n), in LDS.
+// ---------------------------------------------------------------------------
+template <typename C, int R, bool INV, int THREADS, int PN>
+__device__ __forceinline__ void stockham_stage(C *lds, int ld, int n, int P, int Ns, const C *tw) {
+  constexpr int MAXB = (PN + R * THREADS - 1) / (R * THREADS);
+  const int nbf = n / R;
+  const int total = P * nbf;
+  const int tstride = n / (Ns * R);
+  C v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const int k = j % Ns;
+      const C *src = lds + p * ld + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * k * tstride];
+          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+        }
+      }
+      dftR<C, R, INV>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const int k = j % Ns;
+      C *dst = lds + p * ld + (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+struct StageList {
+  int nstage;
+  int radix[12];
+};
+
+// Full transform of P pencils in LDS.  Caller synchronises before the call
+// (data loaded) and may read results right after it returns.
+template <typename C, bool INV, int THREADS, int PN>
+__device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const C *tw) {
+  int Ns = 1;
+  for (int s = 0; s < st.nstage; ++s) {
+    const int R = st.radix[s];
+    if (R == 8) stockham_stage<C, 8, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    else if (R == 4) stockham_stage<C, 4, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    else if (R == 2) stockham_stage<C, 2, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    else stockham_stage<C, 3, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    Ns *= R;
+  }
+}
+
+}  // namespace frsd

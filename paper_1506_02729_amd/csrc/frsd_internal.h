@@ -1,0 +1,162 @@
+// Internal declarations of the fastrsd HIP library (gfx950).
+//
+// Layout of the device workspace, the host-side plan, and the kernel launch
+// wrappers shared by the translation units.  Nothing here is part of the
+// C ABI in include/fastrsd.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fastrsd.h"
+
+namespace frsd {
+
+// ---------------------------------------------------------------------------
+// Moments.  IDs 0..21 are the monopole, the 6 independent components of the
+// rank-2 tensor and the 15 of the rank-4 tensor (Sec. II.B eqs. delta2b,
+// delta4b); ID 22 is the w^2-weighted monopole F_0^w (Sec. III.B, the
+// definition below eq. SNbisp2).
+// ---------------------------------------------------------------------------
+constexpr int kMomW = 22;
+constexpr int kMaxMom = 23;
+constexpr int kMaxSlots = 23;
+
+// Component indices (x=0, y=1, z=2) of each moment, -1 padded, and the
+// multiplicity of the independent component in the full contraction.
+struct MomentTable {
+  int8_t idx[kMaxMom][4];
+  int8_t rank[kMaxMom];
+  float mult[kMaxMom];
+};
+const MomentTable &moment_table();
+
+// ---------------------------------------------------------------------------
+// FFT plan for one length: radix schedule (factors 8, 4, 2, 3).
+// ---------------------------------------------------------------------------
+struct FftLen {
+  int n = 0;
+  int nstage = 0;
+  int radix[12] = {0};
+};
+bool make_fft_len(int n, FftLen *out);
+
+// Device-visible kernel arguments describing the mesh planes.
+struct SlotDesc {
+  int n_slot;                 // complex meshes
+  int re_mom[kMaxSlots];      // moment position (index into mom list) in the real part
+  int im_mom[kMaxSlots];      // moment position in the imaginary part, -1 if empty
+  int im_shift[kMaxSlots];    // 1: imaginary part is the interlaced twin (nodes at +1/2)
+  int mom_id[kMaxMom];        // moment ID of each position
+  int n_mom;
+};
+
+// Byte offsets of the workspace regions (all 256-byte aligned).
+struct Layout {
+  size_t tw_fwd = 0, tw_inv = 0, tw_inv64 = 0;  // twiddle tables
+  size_t scal_part = 0, scal = 0, reject = 0;    // scalar reductions
+  size_t cnt = 0, scan_blk = 0;                  // per-cell counts / offsets, scan partials
+  size_t slot = 0, cellkey = 0;                  // per-object rank within its cell, cell id
+  size_t sorted = 0;                             // sorted object records
+  size_t mesh = 0;                               // n_slot complex N^3 meshes
+  size_t bin_part = 0, bin_sum = 0;              // shell-sum partials and totals
+  size_t lowk = 0;                               // A_0, A_2, A_4 on |n| < top bk edge
+  size_t buf1 = 0, buf2 = 0;                     // inverse-FFT intermediates
+  size_t shells = 0;                             // shell fields on M^3
+  size_t tri_tab = 0, tri_part = 0, tri_sum = 0; // contraction tables and partials
+  size_t nt = 0;                                 // N^T per triangle
+  size_t pk_lut = 0, bk_lut = 0;                 // |n|^2 -> bin index (int16, -1 outside)
+  size_t total = 0;
+};
+
+// Sorted object records, structure of arrays inside the `sorted` region:
+// cell id (int32), then 8 arrays of T: fx, fy, fz (fraction of the grid
+// coordinate inside its cell), t0 (signed weight s w), tw (w^2 weight of
+// F_0^w), xhat_x, xhat_y, xhat_z.
+inline size_t sorted_stride(size_t nobj, size_t tbytes) { return ((nobj * tbytes) + 255) & ~(size_t)255; }
+inline size_t sorted_bytes(size_t nobj, size_t tbytes) {
+  return sorted_stride(nobj, 4) + 8 * sorted_stride(nobj, tbytes);
+}
+
+constexpr int kBinSums = 8;     // per bin: count, sum|k|, S00, S20, S40, S0w, S2w, S4w
+constexpr int kScalars = 4;     // I22, N0, I33, W3
+constexpr int kIngestBlocks = 1024;
+constexpr int kBinBlocks = 2048;
+constexpr int kTriBlocks = 1024;
+constexpr int kPairBatch = 8;   // shell-field pairs per inverse-FFT batch
+
+}  // namespace frsd
+
+struct frsd_plan {
+  frsd_params p{};
+  int N = 0;
+  double h = 0, kf = 0;
+  frsd::SlotDesc slots{};
+  // bins (squared edges in k_f units)
+  std::vector<double> pk_e2, bk_e2;
+  int nc_p = 0, nc_b = 0, nmax = 0;   // largest integer component inside the P / B spheres
+  int pk_lut_len = 0, bk_lut_len = 0; // entries of the |n|^2 -> bin tables
+  int M = 0;                          // real-space triangle-search grid
+  int D = 0;                          // low-k cube side 2 nc_b + 1
+  std::vector<int32_t> tri;           // 3 * ntri
+  int64_t ntri = 0;
+  int n_out = 0;                      // contraction outputs (ntri * n_ell)
+  int n_ell = 0;                      // multipoles in the bispectrum (1 or 3)
+  frsd::FftLen fft_n, fft_m;
+  frsd::Layout L;
+  int state = 0;                      // 0 created, 1 initialised, 2 assigned, 3 pk done
+  void *init_ws = nullptr;
+};
+
+namespace frsd {
+
+// error handling ------------------------------------------------------------
+int fail(int code, const std::string &msg);
+void clear_error();
+
+#define FRSD_HIP(call)                                                       \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::frsd::fail(FRSD_EHIP, std::string(#call) + ": " +            \
+                                         hipGetErrorString(e_));             \
+  } while (0)
+
+#define FRSD_LAUNCH_CHECK()                                                  \
+  do {                                                                       \
+    hipError_t e_ = hipGetLastError();                                       \
+    if (e_ != hipSuccess)                                                    \
+      return ::frsd::fail(FRSD_EHIP, std::string("kernel launch: ") +        \
+                                         hipGetErrorString(e_));             \
+  } while (0)
+
+template <typename T>
+inline T *ws_ptr(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// launch wrappers (defined in the .hip translation units) --------------------
+template <typename T>
+int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
+                    const frsd_catalog *ran, double alpha, hipStream_t s);
+template <typename T>
+int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+template <typename T>
+int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s);
+int run_nt(frsd_plan *pl, void *ws, hipStream_t s);
+int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
+
+// FFT passes (fft.hip) --------------------------------------------------------
+// Forward c2c FFT in place over n_batch contiguous N^3 complex meshes.
+template <typename T>
+int fft3d_forward(const FftLen &f, const void *tw, void *mesh, int n_batch, hipStream_t s);
+
+// Shell-filtered inverse FFTs on the M^3 grid (bk.hip).
+template <typename T>
+int shell_fields(frsd_plan *pl, void *ws, bool indicators, hipStream_t s);
+
+}  // namespace frsd

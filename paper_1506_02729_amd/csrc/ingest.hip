@@ -1,0 +1,284 @@
+// Steps a1-a2: catalogue ingest, line of sight, counting sort by cell, and
+// the FP64 scalar reductions I22, N_0, I33, W3 (Sec. III.A eqs. I22def,
+// N0true; Sec. III.B eq. Noise0).
+//
+// Pass 1 (k_count) validates every object, finds its cell floor(x / h) and
+// takes a rank inside that cell with an atomic increment of the cell count.
+// An exclusive scan of the counts gives each cell's first slot; pass 2
+// (k_scatter) re-reads the catalogue and writes the object's record at
+// offset[cell] + rank, so objects end up grouped by cell in row-major cell
+// order (x slowest, z fastest).
+#include "device.h"
+#include "frsd_internal.h"
+
+namespace frsd {
+
+constexpr int kIngestThreads = 256;
+constexpr int kScanChunk = 4096;   // elements per scan block (256 threads x 16)
+
+__global__ void k_fill_i32(int *p, long long n, int v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
+
+struct GeomArgs {
+  double inv_h, L, ox, oy, oz;
+  int N;
+};
+
+// Cell of an in-box position; u = x / h rounded up to N near the upper edge
+// is folded back into the last cell.
+__device__ __forceinline__ int cell_coord(double u, int N) {
+  int c = (int)floor(u);
+  return c < 0 ? 0 : (c > N - 1 ? N - 1 : c);
+}
+
+template <typename TIN>
+__device__ __forceinline__ bool load_pos(const TIN *pos, long long i, const GeomArgs &g, double &x,
+                                         double &y, double &z) {
+  x = (double)pos[3 * i];
+  y = (double)pos[3 * i + 1];
+  z = (double)pos[3 * i + 2];
+  const bool inbox = (x >= 0.0) && (x < g.L) && (y >= 0.0) && (y < g.L) && (z >= 0.0) && (z < g.L);
+  const double rx = x - g.ox, ry = y - g.oy, rz = z - g.oz;
+  return inbox && (rx * rx + ry * ry + rz * rz > 0.0);
+}
+
+// Block sum of up to four doubles into part[col * nblk + blockIdx.x].
+__device__ void block_sum4(double v0, double v1, double v2, double v3, double *part, int col0, int ncol) {
+  __shared__ double red[4][kIngestThreads / 64];
+  v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2); v3 = wave_sum(v3);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) { red[0][w] = v0; red[1][w] = v1; red[2][w] = v2; red[3][w] = v3; }
+  __syncthreads();
+  if (threadIdx.x < ncol) {
+    double s = 0;
+    for (int k = 0; k < kIngestThreads / 64; ++k) s += red[threadIdx.x][k];
+    part[(col0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Pass 1.  Galaxies write partial columns 0,1 (sum w^2, sum w^3); randoms
+// write columns 2..5 (sum nbar w^2, sum nbar^2 w^3, sum w^2, sum w^3).
+template <typename TIN>
+__global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const TIN *w, const TIN *nbar,
+                                                           long long n, int is_ran, long long obj_off,
+                                                           GeomArgs g, int *cnt, int *slot, int *cellkey,
+                                                           double *part, unsigned long long *reject) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double x, y, z;
+    const bool ok = load_pos(pos, i, g, x, y, z);
+    if (ok) {
+      const int cx = cell_coord(x * g.inv_h, g.N), cy = cell_coord(y * g.inv_h, g.N),
+                cz = cell_coord(z * g.inv_h, g.N);
+      const int cell = (cx * g.N + cy) * g.N + cz;
+      slot[obj_off + i] = atomicAdd(&cnt[cell], 1);
+      cellkey[obj_off + i] = cell;
+      const double wi = (double)w[i];
+      const double w2 = wi * wi, w3 = w2 * wi;
+      if (is_ran) {
+        const double nb = (double)nbar[i];
+        s0 += nb * w2; s1 += nb * nb * w3; s2 += w2; s3 += w3;
+      } else {
+        s0 += w2; s1 += w3;
+      }
+    } else {
+      cellkey[obj_off + i] = -1;
+      atomicAdd(reject, 1ull);
+    }
+  }
+  if (is_ran) block_sum4(s0, s1, s2, s3, part, 2, 4);
+  else block_sum4(s0, s1, 0.0, 0.0, part, 0, 2);
+}
+
+// Pass 2: write the record of each accepted object at its sorted slot.
+template <typename TIN, typename T>
+__global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, const TIN *w, long long n, int is_ran,
+                                                             long long obj_off, double alpha, GeomArgs g,
+                                                             const int *offs, const int *slot, const int *cellkey,
+                                                             int *r_cell, T *r_f, size_t fstride) {
+  T *fx = r_f, *fy = r_f + fstride, *fz = r_f + 2 * fstride, *t0 = r_f + 3 * fstride, *tw = r_f + 4 * fstride,
+    *hx = r_f + 5 * fstride, *hy = r_f + 6 * fstride, *hz = r_f + 7 * fstride;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int cell = cellkey[obj_off + i];
+    if (cell < 0) continue;
+    const long long dst = (long long)offs[cell] + slot[obj_off + i];
+    const double x = (double)pos[3 * i], y = (double)pos[3 * i + 1], z = (double)pos[3 * i + 2];
+    const double ux = x * g.inv_h, uy = y * g.inv_h, uz = z * g.inv_h;
+    const int cx = cell_coord(ux, g.N), cy = cell_coord(uy, g.N), cz = cell_coord(uz, g.N);
+    const double one_minus = 1.0 - 1e-15;
+    double f0 = ux - cx, f1 = uy - cy, f2 = uz - cz;
+    f0 = f0 < 0 ? 0 : (f0 > one_minus ? one_minus : f0);
+    f1 = f1 < 0 ? 0 : (f1 > one_minus ? one_minus : f1);
+    f2 = f2 < 0 ? 0 : (f2 > one_minus ? one_minus : f2);
+    const double rx = x - g.ox, ry = y - g.oy, rz = z - g.oz;
+    const double ir = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
+    const double wi = (double)w[i];
+    r_cell[dst] = cell;
+    fx[dst] = (T)f0; fy[dst] = (T)f1; fz[dst] = (T)f2;
+    t0[dst] = (T)(is_ran ? -alpha * wi : wi);
+    tw[dst] = (T)(is_ran ? alpha * alpha * wi * wi : wi * wi);
+    hx[dst] = (T)(rx * ir); hy[dst] = (T)(ry * ir); hz[dst] = (T)(rz * ir);
+  }
+}
+
+// I22 = alpha S_r[nbar w^2], N0 = S_g[w^2] + alpha^2 S_r[w^2],
+// I33 = alpha S_r[nbar^2 w^3], W3 = S_g[w^3] - alpha^3 S_r[w^3].
+__global__ void k_scal_final(const double *part, int nblk, double alpha, double *scal) {
+  __shared__ double col[6];
+  if (threadIdx.x < 6) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += part[threadIdx.x * nblk + b];
+    col[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    scal[0] = alpha * col[2];
+    scal[1] = col[0] + alpha * alpha * col[4];
+    scal[2] = alpha * col[3];
+    scal[3] = col[1] - alpha * alpha * alpha * col[5];
+    for (int k = 0; k < 6; ++k) scal[4 + k] = col[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 counts, in place (three kernels).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_reduce(const int *a, long long n, int *blk) {
+  const long long base = (long long)blockIdx.x * kScanChunk;
+  int s = 0;
+  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+    const long long i = base + k;
+    if (i < n) s += a[i];
+  }
+  __shared__ int red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk[blockIdx.x] = red[0];
+}
+
+// block-wide exclusive scan of one int per thread (256 threads); returns total
+__device__ int block_exscan256(int v, int *tmp, int &total) {
+  tmp[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int t = (threadIdx.x >= o) ? tmp[threadIdx.x - o] : 0;
+    __syncthreads();
+    tmp[threadIdx.x] += t;
+    __syncthreads();
+  }
+  total = tmp[255];
+  const int incl = tmp[threadIdx.x];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb) {
+  __shared__ int tmp[256];
+  int carry = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + threadIdx.x;
+    const int v = (i < nb) ? blk[i] : 0;
+    int total;
+    const int ex = block_exscan256(v, tmp, total);
+    if (i < nb) blk[i] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const int *blk) {
+  __shared__ int tmp[256];
+  const long long base = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * 16;
+  int v[16];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const long long i = base + k;
+    v[k] = (i < n) ? a[i] : 0;
+    s += v[k];
+  }
+  int total;
+  int run = block_exscan256(s, tmp, total) + blk[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const long long i = base + k;
+    if (i < n) a[i] = run;
+    run += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename TIN>
+static void launch_count(const frsd_catalog *c, int is_ran, long long off, const GeomArgs &g, void *ws,
+                         const frsd_plan *pl, hipStream_t s) {
+  const Layout &L = pl->L;
+  hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
+                     (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
+                     ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
+                     ws_ptr<double>(ws, L.scal_part), ws_ptr<unsigned long long>(ws, L.reject));
+}
+
+template <typename TIN, typename T>
+static void launch_scatter(const frsd_catalog *c, int is_ran, long long off, double alpha, const GeomArgs &g,
+                           void *ws, const frsd_plan *pl, hipStream_t s) {
+  const Layout &L = pl->L;
+  const size_t nobj = (size_t)(pl->p.max_objects > 0 ? pl->p.max_objects : 1);
+  const size_t cstride = sorted_stride(nobj, 4);
+  const size_t fstride = sorted_stride(nobj, sizeof(T)) / sizeof(T);
+  hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
+                     (const TIN *)c->pos, (const TIN *)c->w, (long long)c->n, is_ran, off, alpha, g,
+                     ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
+                     ws_ptr<int>(ws, L.sorted), ws_ptr<T>(ws, L.sorted + cstride), fstride);
+}
+
+template <typename T>
+int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
+                    hipStream_t s) {
+  const Layout &L = pl->L;
+  const int N = pl->N;
+  const long long ncell = (long long)N * N * N;
+  GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N};
+
+  hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject));
+  const frsd_catalog *cats[2] = {gal, ran};
+  long long off = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (cats[k]->dtype == FRSD_F64) launch_count<double>(cats[k], k, off, g, ws, pl, s);
+    else launch_count<float>(cats[k], k, off, g, ws, pl, s);
+    off += cats[k]->n;
+  }
+  FRSD_LAUNCH_CHECK();
+  const long long n = ncell + 1;
+  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk));
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, ws_ptr<int>(ws, L.scan_blk), nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk));
+  off = 0;
+  for (int k = 0; k < 2; ++k) {
+    if (cats[k]->dtype == FRSD_F64) launch_scatter<double, T>(cats[k], k, off, alpha, g, ws, pl, s);
+    else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s);
+    off += cats[k]->n;
+  }
+  hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(64), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
+                     ws_ptr<double>(ws, L.scal));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+template int ingest_and_sort<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
+                                    hipStream_t);
+template int ingest_and_sort<double>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
+                                     hipStream_t);
+
+}  // namespace frsd

@@ -1,0 +1,263 @@
+// Host side of the library: parameter validation, bins, triangle list, FFT
+// radix schedules, workspace layout and the thread-local error string.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "frsd_internal.h"
+
+namespace frsd {
+
+static thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+const char *last_error() { return g_err.c_str(); }
+
+// Moment components (Sec. II.B eqs. delta2b and delta4b); the multiplicity
+// of a component is the number of distinct orderings of its index tuple.
+const MomentTable &moment_table() {
+  static MomentTable t = [] {
+    MomentTable m{};
+    const int comp[kMaxMom][4] = {
+        {-1, -1, -1, -1},
+        {0, 0, -1, -1}, {1, 1, -1, -1}, {2, 2, -1, -1}, {0, 1, -1, -1}, {1, 2, -1, -1}, {2, 0, -1, -1},
+        {0, 0, 0, 0}, {1, 1, 1, 1}, {2, 2, 2, 2},
+        {0, 0, 0, 1}, {0, 0, 0, 2}, {1, 1, 1, 0}, {1, 1, 1, 2}, {2, 2, 2, 0}, {2, 2, 2, 1},
+        {0, 0, 1, 1}, {1, 1, 2, 2}, {2, 2, 0, 0},
+        {0, 0, 1, 2}, {1, 1, 0, 2}, {2, 2, 0, 1},
+        {-1, -1, -1, -1}};
+    for (int i = 0; i < kMaxMom; ++i) {
+      int rank = 0, cnt[3] = {0, 0, 0};
+      for (int k = 0; k < 4; ++k) {
+        m.idx[i][k] = (int8_t)comp[i][k];
+        if (comp[i][k] >= 0) { ++rank; ++cnt[comp[i][k]]; }
+      }
+      m.rank[i] = (int8_t)rank;
+      double f = 1;
+      for (int k = 2; k <= rank; ++k) f *= k;
+      for (int a = 0; a < 3; ++a)
+        for (int k = 2; k <= cnt[a]; ++k) f /= k;
+      m.mult[i] = (float)f;
+    }
+    return m;
+  }();
+  return t;
+}
+
+bool make_fft_len(int n, FftLen *out) {
+  FftLen f{};
+  f.n = n;
+  int m = n;
+  int ns = 0;
+  while (m % 3 == 0) { f.radix[ns++] = 3; m /= 3; }
+  while (m % 8 == 0) { f.radix[ns++] = 8; m /= 8; }
+  if (m % 4 == 0) { f.radix[ns++] = 4; m /= 4; }
+  if (m % 2 == 0) { f.radix[ns++] = 2; m /= 2; }
+  if (m != 1 || ns > 12) return false;
+  f.nstage = ns;
+  *out = f;
+  return true;
+}
+
+static bool is_smooth(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+static int smallest_smooth_at_least(int n) {
+  for (int m = n;; ++m)
+    if (is_smooth(m)) return m;
+}
+
+// squared edges in k_f units, snapped to integers within 1e-9 relative
+static std::vector<double> squared_edges(double kmin, double dk, int nb, double kf) {
+  std::vector<double> e2(nb + 1);
+  for (int b = 0; b <= nb; ++b) {
+    const double e = (kmin + dk * b) / kf;
+    double v = e * e;
+    const double r = std::nearbyint(v);
+    if (std::fabs(v - r) <= 1e-9 * std::fmax(r, 1.0)) v = r;
+    e2[b] = v;
+  }
+  return e2;
+}
+
+// largest integer strictly below sqrt(e2top)
+static int max_component(double e2top) {
+  int c = (int)std::floor(std::sqrt(e2top));
+  while ((double)c * c >= e2top && c > 0) --c;
+  while ((double)(c + 1) * (c + 1) < e2top) ++c;
+  return c;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace frsd
+
+using namespace frsd;
+
+extern "C" const char *frsd_last_error(void) { return frsd::last_error(); }
+
+extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out) {
+  clear_error();
+  if (!params || !plan_out) return fail(FRSD_EINVAL, "null argument");
+  const frsd_params &p = *params;
+  if (p.n_grid < 32 || p.n_grid > 1024 || p.n_grid % 16 != 0 || !is_smooth(p.n_grid))
+    return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b, a multiple of 16, in [32, 1024]");
+  if (p.order < 1 || p.order > 3) return fail(FRSD_EINVAL, "order must be 1 (NGP), 2 (CIC) or 3 (TSC)");
+  if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(FRSD_EINVAL, "ell_max must be 0, 2 or 4");
+  if (p.precision != FRSD_F32 && p.precision != FRSD_F64) return fail(FRSD_EINVAL, "precision must be 32 or 64");
+  if (!(p.box > 0) || !std::isfinite(p.box)) return fail(FRSD_EINVAL, "box must be positive");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p.observer[d])) return fail(FRSD_EINVAL, "observer must be finite");
+  if (p.pk_nbins < 1 || !(p.pk_dk > 0) || p.pk_kmin < 0) return fail(FRSD_EINVAL, "invalid power-spectrum bins");
+  if (p.bk_nbins < 0 || (p.bk_nbins > 0 && (!(p.bk_dk > 0) || p.bk_kmin < 0)))
+    return fail(FRSD_EINVAL, "invalid bispectrum bins");
+  if (p.max_objects < 0) return fail(FRSD_EINVAL, "max_objects must be >= 0");
+
+  frsd_plan *pl = new frsd_plan();
+  pl->p = p;
+  pl->N = p.n_grid;
+  pl->h = p.box / p.n_grid;
+  pl->kf = 2.0 * M_PI / p.box;
+  const int N = pl->N;
+  const double ny2 = (double)(N / 2) * (N / 2);
+
+  pl->pk_e2 = squared_edges(p.pk_kmin, p.pk_dk, p.pk_nbins, pl->kf);
+  if (pl->pk_e2.back() > ny2 * (1 + 1e-12)) { delete pl; return fail(FRSD_EINVAL, "pk k_max beyond Nyquist"); }
+  if (pl->pk_e2.back() <= 1.0) { delete pl; return fail(FRSD_EINVAL, "pk bins contain no mode"); }
+  pl->nc_p = max_component(pl->pk_e2.back());
+  pl->nmax = pl->nc_p;
+  if (p.bk_nbins > 0) {
+    pl->bk_e2 = squared_edges(p.bk_kmin, p.bk_dk, p.bk_nbins, pl->kf);
+    if (pl->bk_e2.back() > ny2 * (1 + 1e-12)) { delete pl; return fail(FRSD_EINVAL, "bk k_max beyond Nyquist"); }
+    if (pl->bk_e2.back() <= 1.0) { delete pl; return fail(FRSD_EINVAL, "bk bins contain no mode"); }
+    pl->nc_b = max_component(pl->bk_e2.back());
+    if (pl->nc_b > pl->nmax) pl->nmax = pl->nc_b;
+    pl->D = 2 * pl->nc_b + 1;
+    const int need = 3 * pl->nc_b + 1;
+    if (p.bk_grid) {
+      if (p.bk_grid < need || !is_smooth(p.bk_grid) || p.bk_grid > 1024) {
+        delete pl;
+        return fail(FRSD_EINVAL, "bk_grid must be 2^a 3^b > 3 n_c and <= 1024");
+      }
+      pl->M = p.bk_grid;
+    } else {
+      pl->M = smallest_smooth_at_least(need);
+    }
+    if (pl->M > 1024) { delete pl; return fail(FRSD_EINVAL, "bispectrum grid would exceed 1024"); }
+    // triangle list: b1 >= b2 >= b3 with lo(b1) < hi(b2) + hi(b3)
+    std::vector<double> e(p.bk_nbins + 1);
+    for (int b = 0; b <= p.bk_nbins; ++b) e[b] = std::sqrt(pl->bk_e2[b]);
+    for (int b1 = 0; b1 < p.bk_nbins; ++b1)
+      for (int b2 = 0; b2 <= b1; ++b2)
+        for (int b3 = 0; b3 <= b2; ++b3)
+          if (e[b1] < e[b2 + 1] + e[b3 + 1]) {
+            pl->tri.push_back(b1); pl->tri.push_back(b2); pl->tri.push_back(b3);
+          }
+    pl->ntri = (int64_t)pl->tri.size() / 3;
+    pl->n_ell = p.ell_max == 0 ? 1 : (p.ell_max == 2 ? 2 : 3);
+    pl->n_out = (int)(pl->ntri * pl->n_ell);
+  }
+
+  // moments in slot order, and their packing into complex meshes
+  SlotDesc &sd = pl->slots;
+  int nm = 0;
+  const int nmom_ell = p.ell_max == 0 ? 1 : (p.ell_max == 2 ? 7 : 22);
+  for (int m = 0; m < nmom_ell; ++m) sd.mom_id[nm++] = m;
+  if (p.bk_nbins > 0) sd.mom_id[nm++] = kMomW;
+  sd.n_mom = nm;
+  int ns = 0;
+  if (p.interlace) {
+    for (int m = 0; m < nm; ++m) {
+      sd.re_mom[ns] = m; sd.im_mom[ns] = m; sd.im_shift[ns] = 1; ++ns;
+    }
+  } else {
+    for (int m = 0; m < nm; m += 2) {
+      sd.re_mom[ns] = m; sd.im_mom[ns] = (m + 1 < nm) ? m + 1 : -1; sd.im_shift[ns] = 0; ++ns;
+    }
+  }
+  sd.n_slot = ns;
+
+  if (!make_fft_len(N, &pl->fft_n)) { delete pl; return fail(FRSD_EINVAL, "no radix schedule for n_grid"); }
+  if (pl->M && !make_fft_len(pl->M, &pl->fft_m)) { delete pl; return fail(FRSD_EINVAL, "no radix schedule for M"); }
+
+  // workspace layout
+  const size_t T = (p.precision == FRSD_F64) ? 8 : 4;
+  const size_t NNN = (size_t)N * N * N;
+  const size_t nobj = (size_t)(p.max_objects > 0 ? p.max_objects : 1);
+  Layout &L = pl->L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  L.tw_fwd = take(2 * T * N);
+  L.tw_inv = take(2 * T * (pl->M ? pl->M : 1));
+  L.tw_inv64 = take(16 * (size_t)(pl->M ? pl->M : 1));
+  L.scal_part = take(8 * 6 * kIngestBlocks);
+  L.scal = take(8 * 16);
+  L.reject = take(8);
+  L.cnt = take(4 * (NNN + 1));
+  L.scan_blk = take(4 * ((NNN + 1 + 4095) / 4096 + 1));
+  L.slot = take(4 * nobj);
+  L.cellkey = take(4 * nobj);
+  L.sorted = take(sorted_bytes(nobj, T));
+  L.mesh = take(2 * T * NNN * sd.n_slot);
+  const int nbins_all = p.pk_nbins + p.bk_nbins;
+  L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kBinBlocks);
+  L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);
+  if (p.bk_nbins > 0) {
+    const size_t D = pl->D, M = pl->M;
+    const size_t npair_batch = kPairBatch;
+    L.lowk = take(2 * T * 3 * D * D * D);
+    // intermediates sized for FP64 (the N^T indicator fields are FP64 for every plan)
+    L.buf1 = take(16 * npair_batch * D * D * M);
+    L.buf2 = take(16 * npair_batch * D * M * M);
+    const size_t nfield = (size_t)pl->n_ell * p.bk_nbins;
+    const size_t shell_bytes = std::max(T * nfield, (size_t)8 * p.bk_nbins) * M * M * M;
+    L.shells = take(shell_bytes);
+    L.tri_tab = take(16 * (size_t)pl->n_out + 16 * (size_t)pl->ntri + 12 * (size_t)pl->ntri);
+    L.tri_part = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri) * kTriBlocks);
+    L.tri_sum = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri));
+    L.nt = take(8 * (size_t)pl->ntri);
+  }
+  // bin lookup tables |n|^2 -> bin (int16)
+  pl->pk_lut_len = (int)std::ceil(pl->pk_e2.back());
+  L.pk_lut = take(2 * (size_t)pl->pk_lut_len);
+  if (p.bk_nbins > 0) {
+    pl->bk_lut_len = (int)std::ceil(pl->bk_e2.back());
+    L.bk_lut = take(2 * (size_t)pl->bk_lut_len);
+  }
+  L.total = off;
+  *plan_out = pl;
+  return FRSD_OK;
+}
+
+extern "C" void frsd_plan_destroy(frsd_plan *plan) { delete plan; }
+
+extern "C" int frsd_plan_workspace_bytes(const frsd_plan *plan, size_t *bytes) {
+  clear_error();
+  if (!plan || !bytes) return fail(FRSD_EINVAL, "null argument");
+  *bytes = plan->L.total;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_bk_ntriangles(const frsd_plan *plan, int64_t *ntri) {
+  clear_error();
+  if (!plan || !ntri) return fail(FRSD_EINVAL, "null argument");
+  *ntri = plan->ntri;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_bk_triangles(const frsd_plan *plan, int32_t *b123) {
+  clear_error();
+  if (!plan || (!b123 && plan->ntri > 0)) return fail(FRSD_EINVAL, "null argument");
+  if (plan->ntri > 0) std::memcpy(b123, plan->tri.data(), sizeof(int32_t) * plan->tri.size());
+  return FRSD_OK;
+}

@@ -1,0 +1,296 @@
+"""Python binding of the fastrsd C ABI (include/fastrsd.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library ``libfastrsd.so`` built next to this file.  PyTorch provides device
+memory and streams.  Importing this module raises if the library is not
+built; there is no CPU fallback.
+
+Low-level functions carry the C names (``frsd_plan_create``,
+``frsd_mesh_assign``, ...).  ``Plan`` wraps them with torch-allocated
+workspace and output buffers.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastrsd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"fastrsd HIP library not built: {LIB_PATH} is missing "
+                      "(run python -m paper_1506_02729_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+FRSD_OK, FRSD_EINVAL, FRSD_EDOM, FRSD_ENOMEM, FRSD_EHIP, FRSD_ESTATE = 0, -1, -2, -3, -4, -5
+FRSD_F32, FRSD_F64 = 32, 64
+_ERRNAMES = {-1: "FRSD_EINVAL", -2: "FRSD_EDOM", -3: "FRSD_ENOMEM", -4: "FRSD_EHIP", -5: "FRSD_ESTATE"}
+
+
+class FrsdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class frsd_params(ctypes.Structure):
+    _fields_ = [
+        ("n_grid", ctypes.c_int32), ("order", ctypes.c_int32), ("interlace", ctypes.c_int32),
+        ("compensate", ctypes.c_int32), ("ell_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("box", ctypes.c_double), ("observer", ctypes.c_double * 3),
+        ("pk_kmin", ctypes.c_double), ("pk_dk", ctypes.c_double), ("pk_nbins", ctypes.c_int32),
+        ("bk_kmin", ctypes.c_double), ("bk_dk", ctypes.c_double), ("bk_nbins", ctypes.c_int32),
+        ("bk_grid", ctypes.c_int32), ("max_objects", ctypes.c_int64),
+    ]
+
+
+class frsd_catalog(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+class frsd_pk_out(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("n_modes", "k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "scalars")]
+
+
+class frsd_bk_out(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4")]
+
+
+_P = ctypes.c_void_p
+_proto = {
+    "frsd_plan_create": (ctypes.c_int, [ctypes.POINTER(frsd_params), ctypes.POINTER(_P)]),
+    "frsd_plan_destroy": (None, [_P]),
+    "frsd_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "frsd_plan_init": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "frsd_mesh_assign": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
+                                        ctypes.c_double, _P]),
+    "frsd_pk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_pk_out), _P]),
+    "frsd_bk_ntriangles": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "frsd_bk_triangles": (ctypes.c_int, [_P, _P]),
+    "frsd_bk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_bk_out), _P]),
+    "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
+    "frsd_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _proto.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_proto)
+
+
+def _check(rc):
+    if rc != FRSD_OK:
+        raise FrsdError(rc, _lib.frsd_last_error().decode())
+
+
+# --- thin wrappers with the C names -------------------------------------------
+
+def frsd_last_error() -> str:
+    return _lib.frsd_last_error().decode()
+
+
+def frsd_plan_create(params: frsd_params) -> int:
+    h = _P()
+    _check(_lib.frsd_plan_create(ctypes.byref(params), ctypes.byref(h)))
+    return h.value
+
+
+def frsd_plan_destroy(plan: int) -> None:
+    _lib.frsd_plan_destroy(plan)
+
+
+def frsd_plan_workspace_bytes(plan: int) -> int:
+    v = ctypes.c_size_t()
+    _check(_lib.frsd_plan_workspace_bytes(plan, ctypes.byref(v)))
+    return v.value
+
+
+def frsd_plan_init(plan: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _check(_lib.frsd_plan_init(plan, ws_ptr, ws_bytes, stream))
+
+
+def frsd_mesh_assign(plan, ws_ptr, gal: frsd_catalog, ran: frsd_catalog, alpha: float, stream) -> None:
+    _check(_lib.frsd_mesh_assign(plan, ws_ptr, ctypes.byref(gal), ctypes.byref(ran), float(alpha), stream))
+
+
+def frsd_pk_multipoles(plan, ws_ptr, out: frsd_pk_out, stream) -> None:
+    _check(_lib.frsd_pk_multipoles(plan, ws_ptr, ctypes.byref(out), stream))
+
+
+def frsd_bk_ntriangles(plan) -> int:
+    v = ctypes.c_int64()
+    _check(_lib.frsd_bk_ntriangles(plan, ctypes.byref(v)))
+    return v.value
+
+
+def frsd_bk_triangles(plan) -> np.ndarray:
+    n = frsd_bk_ntriangles(plan)
+    arr = np.zeros((max(n, 1), 3), dtype=np.int32)
+    _check(_lib.frsd_bk_triangles(plan, arr.ctypes.data))
+    return arr[:n]
+
+
+def frsd_bk_multipoles(plan, ws_ptr, out: frsd_bk_out, stream) -> None:
+    _check(_lib.frsd_bk_multipoles(plan, ws_ptr, ctypes.byref(out), stream))
+
+
+def frsd_status(plan, ws_ptr, stream) -> int:
+    v = ctypes.c_int64()
+    rc = _lib.frsd_status(plan, ws_ptr, ctypes.byref(v), stream)
+    if rc not in (FRSD_OK, FRSD_EDOM):
+        _check(rc)
+    return v.value
+
+
+# --- convenience plan object ---------------------------------------------------
+
+@dataclass
+class Config:
+    n_grid: int
+    box: float
+    observer: tuple
+    order: int = 3
+    interlace: bool = True
+    compensate: bool = True
+    ell_max: int = 4
+    precision: int = 32
+    pk_kmin: float = 0.0
+    pk_dk: float = 0.0
+    pk_nbins: int = 0
+    bk_kmin: float = 0.0
+    bk_dk: float = 0.0
+    bk_nbins: int = 0
+    bk_grid: int = 0
+    max_objects: int = 0
+
+    def to_c(self) -> frsd_params:
+        p = frsd_params()
+        p.n_grid, p.order, p.interlace = self.n_grid, self.order, int(self.interlace)
+        p.compensate, p.ell_max, p.precision = int(self.compensate), self.ell_max, self.precision
+        p.box = self.box
+        for d in range(3):
+            p.observer[d] = float(self.observer[d])
+        p.pk_kmin, p.pk_dk, p.pk_nbins = self.pk_kmin, self.pk_dk, self.pk_nbins
+        p.bk_kmin, p.bk_dk, p.bk_nbins = self.bk_kmin, self.bk_dk, self.bk_nbins
+        p.bk_grid, p.max_objects = self.bk_grid, int(self.max_objects)
+        return p
+
+
+def device_catalog(cat: dict | None, device, dtype=torch.float64) -> dict:
+    """Copy a host catalogue (NumPy arrays) to device tensors of `dtype`."""
+    if cat is None or len(cat["w"]) == 0:
+        z = torch.zeros(0, device=device, dtype=dtype)
+        return {"pos": z.reshape(0, 3), "w": z, "nbar": z}
+    out = {}
+    for key in ("pos", "w", "nbar"):
+        out[key] = torch.as_tensor(np.ascontiguousarray(cat[key]), dtype=dtype).to(device)
+    return out
+
+
+def _c_catalog(cat: dict) -> frsd_catalog:
+    c = frsd_catalog()
+    n = int(cat["w"].shape[0])
+    c.n = n
+    if n == 0:
+        c.pos = c.w = c.nbar = None
+        c.dtype = FRSD_F64
+        return c
+    for key in ("pos", "w", "nbar"):
+        t = cat[key]
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"catalogue array {key} must be a contiguous device tensor")
+    dt = cat["pos"].dtype
+    if dt not in (torch.float32, torch.float64) or cat["w"].dtype != dt or cat["nbar"].dtype != dt:
+        raise ValueError("catalogue arrays must share one dtype, float32 or float64")
+    c.dtype = FRSD_F64 if dt == torch.float64 else FRSD_F32
+    c.pos, c.w, c.nbar = cat["pos"].data_ptr(), cat["w"].data_ptr(), cat["nbar"].data_ptr()
+    return c
+
+
+class Plan:
+    """A plan plus its device workspace and output buffers on one GPU."""
+
+    def __init__(self, cfg: Config, device="cuda", stream: torch.cuda.Stream | None = None):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.handle = frsd_plan_create(cfg.to_c())
+        self.ws_bytes = frsd_plan_workspace_bytes(self.handle)
+        # 256-byte alignment: over-allocate and offset
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = cfg.pk_nbins
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.pk_buf = {"n_modes": torch.zeros(nb, dtype=torch.int64, device=self.device)}
+        for key in ("k_eff", "p0", "p2", "p4", "s00", "s20", "s40"):
+            self.pk_buf[key] = torch.zeros(nb, **f64)
+        self.pk_buf["scalars"] = torch.zeros(4, **f64)
+        self.ntri = frsd_bk_ntriangles(self.handle) if cfg.bk_nbins > 0 else 0
+        self.bk_buf = {}
+        if self.ntri:
+            for key in ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4"):
+                self.bk_buf[key] = torch.zeros(self.ntri, **f64)
+        frsd_plan_init(self.handle, self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            frsd_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def triangles(self) -> np.ndarray:
+        return frsd_bk_triangles(self.handle)
+
+    def mesh_assign(self, gal: dict, ran: dict | None, alpha: float) -> None:
+        empty = {"pos": torch.zeros(0, 3, device=self.device, dtype=torch.float64),
+                 "w": torch.zeros(0, device=self.device, dtype=torch.float64),
+                 "nbar": torch.zeros(0, device=self.device, dtype=torch.float64)}
+        self._gal, self._ran = gal, (ran if ran is not None else empty)  # keep alive while queued
+        frsd_mesh_assign(self.handle, self.ws_ptr, _c_catalog(self._gal), _c_catalog(self._ran), alpha,
+                         self.stream.cuda_stream)
+
+    def pk(self) -> dict:
+        o = frsd_pk_out()
+        for name, _ in frsd_pk_out._fields_:
+            setattr(o, name, self.pk_buf[name].data_ptr())
+        frsd_pk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
+        return self.pk_buf
+
+    def bk(self) -> dict:
+        o = frsd_bk_out()
+        for name, _ in frsd_bk_out._fields_:
+            setattr(o, name, self.bk_buf[name].data_ptr())
+        frsd_bk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
+        return self.bk_buf
+
+    def status(self) -> int:
+        return frsd_status(self.handle, self.ws_ptr, self.stream.cuda_stream)
+
+    def run(self, gal: dict, ran: dict | None, alpha: float, bispectrum: bool | None = None) -> dict:
+        """mesh_assign + pk (+ bk); synchronises and returns host NumPy arrays."""
+        self.mesh_assign(gal, ran, alpha)
+        pk = self.pk()
+        out = {k: v for k, v in pk.items()}
+        if (bispectrum is None and self.ntri) or bispectrum:
+            bk = self.bk()
+            out.update({"bk_" + k: v for k, v in bk.items()})
+        rej = self.status()
+        if rej:
+            raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
+        return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def kf(box: float) -> float:
+    return 2.0 * math.pi / box
