@@ -1,0 +1,289 @@
+"""Throughput of the FFT multipole estimators on one MI355X.
+
+One step = one synthetic BOSS-like mock through the whole hot path:
+ingest + sort, interlaced TSC assignment of the 22 moment meshes and the
+w^2 mesh, their forward FFTs, multipole combination and binning into
+P_0, P_2, P_4 (60 bins to k = 0.3 h/Mpc), shell-filtered inverse FFTs on the
+M = 384 grid and the triple-product sums of B_0, B_2, B_4 over all 5416
+triangles of 37 bins of width 3 k_f up to k = 0.2 h/Mpc.  Catalogues are
+resident in HBM before the timed region; nothing is cached between steps.
+
+Prints one JSON line (see the "metric" key).  --gpus N > 1 is refused: the
+build targets one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mocks/s for P_0,2,4+B_0,2,4 at 512^3 (served FP32 vs plain FP64), HBM %, p99 ms"
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def workload(quick: bool):
+    box = 3500.0
+    kf = 2 * math.pi / box
+    if quick:
+        return dict(name="Q256: lognormal mock 2.0e5 galaxies + 1.0e7 randoms, N=256 TSC interlaced, "
+                         "P_ell 45 bins to k=0.225, B_ell 37 bins of 3k_f (5416 triangles), M=384",
+                    n_mesh=256, n_gal=2.0e5, n_ran=10_000_000, pk_dk=0.005, pk_nbins=45,
+                    bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
+    return dict(name="H512: lognormal mock 8.0e5 galaxies + 4.0e7 randoms in a 3500 Mpc/h box, N=512 TSC "
+                     "interlaced, 23 moment meshes, P_ell l=0,2,4 in 60 bins of 0.005 to k=0.3, B_ell l=0,2,4 "
+                     "over 5416 triangles of 37 bins of 3k_f to k=0.202, M=384",
+                n_mesh=512, n_gal=8.0e5, n_ran=40_000_000, pk_dk=0.005, pk_nbins=60,
+                bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
+
+
+def make_config(F, wl, precision, observer, max_objects):
+    return F.Config(n_grid=wl["n_mesh"], box=wl["box"], observer=observer, order=3, interlace=True,
+                    compensate=True, ell_max=4, precision=precision, pk_kmin=0.0, pk_dk=wl["pk_dk"],
+                    pk_nbins=wl["pk_nbins"], bk_kmin=wl["bk_kmin"], bk_dk=wl["bk_dk"],
+                    bk_nbins=wl["bk_nbins"], max_objects=max_objects)
+
+
+def algorithmic_cost(name, plan_cfg, n_obj, n_slot, M, n_out, tbytes):
+    """Algorithmic bytes (HBM-bound kernels) or flops of one launch."""
+    N = plan_cfg.n_grid
+    cplx = 2 * tbytes
+    mesh = n_slot * N**3 * cplx
+    if name == "grid":          # write every moment mesh once, read every object record once
+        return "hbm", mesh + n_obj * (4 + 8 * tbytes)
+    if name.startswith("fft_"):  # read + write every mesh once per pass
+        return "hbm", 2 * mesh
+    if name == "shell_x":       # write two real M^3 fields per pair, read the y-pass rows
+        return "hbm", None
+    if name == "triple":        # 3 flops per output per cell (2 multiplies, 1 add)
+        return "alu", 3.0 * n_out * M**3
+    return None, None
+
+
+def run_steps(F, torch, plan, mocks, steps, timed: bool):
+    lat = []
+    for i in range(steps):
+        g, r, a = mocks[i % len(mocks)]
+        if timed:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(plan.stream)
+        plan.mesh_assign(g, r, a)
+        plan.pk()
+        plan.bk()
+        if timed:
+            e1.record(plan.stream)
+            lat.append((e0, e1))
+    return lat
+
+
+def cpu_baseline(wl, gal, ran, alpha, observer):
+    """FP64 oracle timed on a bounded sample of the same workload, scaled to one mock."""
+    from oracle import estimator as est
+    N, M = wl["n_mesh"], 384
+    n_obj = len(gal["w"]) + len(ran["w"])
+    t = {}
+    sample = 1_000_000
+    pos = ran["pos"][:sample]
+    u = pos / (wl["box"] / N)
+    w = -alpha * ran["w"][:sample]
+    t0 = time.perf_counter()
+    est.assign_mesh(u, w, N, 3)
+    t["grid_1moment_1e6obj"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    mesh = np.random.default_rng(0).standard_normal((N, N, N))
+    t1 = time.perf_counter()
+    np.fft.rfftn(mesh)
+    t["rfftn"] = time.perf_counter() - t1
+    del mesh
+    prm = est.Params(n_grid=N, box=wl["box"], observer=observer, pk_kmin=0.0, pk_dk=wl["pk_dk"],
+                     pk_nbins=wl["pk_nbins"])
+    fields = {0: np.ones((N, N, N // 2 + 1), complex), 2: np.ones((N, N, N // 2 + 1), complex),
+              4: np.ones((N, N, N // 2 + 1), complex)}
+    t0 = time.perf_counter()
+    est.shell_sums(fields, prm, 0.0, wl["pk_dk"], wl["pk_nbins"])
+    t["bin"] = time.perf_counter() - t0
+    del fields
+    bprm = est.Params(n_grid=N, box=wl["box"], observer=observer, bk_kmin=wl["bk_kmin"], bk_dk=wl["bk_dk"],
+                      bk_nbins=wl["bk_nbins"])
+    nx, ny, nz, b = est.lowk_modes(bprm)
+    sel = b == wl["bk_nbins"] // 2
+    t0 = time.perf_counter()
+    f = est.shell_field(np.ones(int(sel.sum()), complex), nx[sel], ny[sel], nz[sel], M)
+    t["shell_ifft"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(3):
+        float(np.sum(f * f * f))
+    t["triangle_sum"] = (time.perf_counter() - t0) / 3
+    del f
+    n_tri, n_ell, n_mom, n_fields = 5416, 3, 23, 111
+    per_mock = (t["grid_1moment_1e6obj"] * (n_obj / sample) * n_mom * 2 + t["rfftn"] * n_mom * 2 + t["bin"]
+                + t["shell_ifft"] * n_fields + t["triangle_sum"] * n_tri * n_ell)
+    return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": 1, "kind": "oracle",
+            "seconds_per_mock": per_mock,
+            "sample": ("FP64 NumPy oracle stages timed once each on this host and scaled to one mock: TSC "
+                       "assignment of 1e6 randoms for one moment plane (x %.0f objects x 46 planes), one "
+                       "512^3 rfftn (x 46), the 60-bin shell sums of 3 multipoles, one 384^3 shell inverse "
+                       "FFT (x 111), one 384^3 triple-product sum (x 5416 triangles x 3 multipoles)"
+                       % (n_obj / sample)),
+            "stage_seconds": {k: round(v, 4) for k, v in t.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--mocks", type=int, default=2)
+    ap.add_argument("--quick", action="store_true", help="256^3 workload for development runs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1506_02729_amd import fastrsd as F
+    from paper_1506_02729_amd import synth
+
+    dev = torch.device("cuda:0")
+    wl = workload(args.quick)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+
+    host_mocks = []
+    for i in range(args.mocks):
+        t0 = time.perf_counter()
+        gal, ran, alpha, obs, meta = synth.lognormal_mock(n_mesh=wl["n_mesh"], box=wl["box"], n_gal=wl["n_gal"],
+                                                          n_ran=wl["n_ran"], seed=2000 + 10 * i)
+        host_mocks.append((gal, ran, alpha, obs))
+        log(f"mock {i}: {len(gal['w'])} galaxies, {len(ran['w'])} randoms, {time.perf_counter() - t0:.1f} s")
+    observer = host_mocks[0][3]
+    max_obj = max(len(g["w"]) + len(r["w"]) for g, r, _, _ in host_mocks)
+    dev_mocks = [(F.device_catalog(g, dev), F.device_catalog(r, dev), a) for g, r, a, _ in host_mocks]
+
+    # ---- served FP32 -------------------------------------------------------
+    cfg = make_config(F, wl, 32, observer, max_obj)
+    t0 = time.perf_counter()
+    plan = F.Plan(cfg, device=dev)
+    torch.cuda.synchronize()
+    log(f"fp32 plan init (tables + N^T) {time.perf_counter() - t0:.2f} s, workspace {plan.ws_bytes / 1e9:.1f} GB")
+    run_steps(F, torch, plan, dev_mocks, args.warmup, False)
+    torch.cuda.synchronize()
+    log("warmup done")
+    F.frsd_profile(True)
+    F.frsd_profile_report()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = run_steps(F, torch, plan, dev_mocks, args.steps, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = F.frsd_profile_report()
+    F.frsd_profile(False)
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+    rej = plan.status()
+    assert rej == 0, f"{rej} objects rejected"
+    p32 = {k: v.cpu().numpy().copy() for k, v in plan.pk_buf.items()}
+    b32 = {k: v.cpu().numpy().copy() for k, v in plan.bk_buf.items()}
+    log(f"fp32: {args.steps} steps in {elapsed:.3f} s")
+
+    n_slot = 23
+    tbytes = 4
+    M = 384
+    n_out = plan.ntri * 3
+    n_obj_last = len(host_mocks[(args.steps - 1) % len(host_mocks)][0]["w"]) + \
+        len(host_mocks[(args.steps - 1) % len(host_mocks)][1]["w"])
+    kernels = {k: {"launches": n, "total_ms": round(ms, 3), "avg_ms": round(ms / n, 4)} for k, (n, ms) in kern.items()}
+    dom = max(kern, key=lambda k: kern[k][1])
+    n_launch, tot_ms = kern[dom]
+    avg_s = tot_ms / n_launch / 1e3
+    bound, cost = algorithmic_cost(dom, cfg, n_obj_last, n_slot, M, n_out, tbytes)
+    if bound == "hbm":
+        roof = {"kernel": dom, "bound": "hbm", "achieved": cost / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif bound == "alu":
+        roof = {"kernel": dom, "bound": "alu", "achieved": cost / avg_s / 1e12, "peak": FP32_VEC_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None}
+    if roof["achieved"] is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["avg_launch_ms"] = avg_s * 1e3
+    roof["traffic"] = None
+    del plan
+    torch.cuda.empty_cache()
+
+    # ---- plain FP64 ------------------------------------------------------------
+    fp64 = None
+    if not args.no_fp64 and args.fp64_steps > 0:
+        cfg64 = make_config(F, wl, 64, observer, max_obj)
+        plan64 = F.Plan(cfg64, device=dev)
+        run_steps(F, torch, plan64, dev_mocks[-1:], 1, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(F, torch, plan64, dev_mocks, args.fp64_steps, False)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t0
+        p64 = {k: v.cpu().numpy().copy() for k, v in plan64.pk_buf.items()}
+        b64 = {k: v.cpu().numpy().copy() for k, v in plan64.bk_buf.items()}
+        # same last mock in both runs when steps and fp64_steps have the same parity
+        same = (args.steps - 1) % len(dev_mocks) == (args.fp64_steps - 1) % len(dev_mocks)
+        cmp = {}
+        if same:
+            nb = p64["n_modes"]
+            for ell in (0, 2, 4):
+                ref = p64[f"p{ell}"]
+                floor = (2 * ell + 1) * np.abs(p64[f"s{ell}0"]) / (nb * p64["scalars"][0])
+                if ell == 0:
+                    floor = p64["s00"] / (nb * p64["scalars"][0])
+                cmp[f"P{ell}_max_rel"] = float(np.max(np.abs(p32[f"p{ell}"] - ref) / np.maximum(np.abs(ref), floor)))
+            ok = b64["nt"] > 0
+            for ell in (0, 2, 4):
+                ref = b64[f"t{ell}"][ok]
+                cmp[f"T{ell}_max_rel_vs_max"] = float(np.max(np.abs(b32[f"t{ell}"][ok] - ref)) / np.max(np.abs(ref)))
+        fp64 = {"value": args.fp64_steps / e64, "unit": "mocks/s", "steps": args.fp64_steps,
+                "ms_per_step": 1e3 * e64 / args.fp64_steps, "fp32_vs_fp64": cmp}
+        del plan64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        g, r, a, o = host_mocks[0]
+        cpu = cpu_baseline(wl, g, r, a, o)
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "mocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "mocks_cycled": args.mocks, "precision": "fp32 served, fp64 plain"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": roof,
+        "kernels": kernels,
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,14 @@ int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *
  * FRSD_EDOM when that number is non-zero. */
 int frsd_status(frsd_plan *plan, void *ws, int64_t *n_rejected, void *stream);
 
+/* Per-kernel timing with HIP events recorded on each call's stream.  Off
+ * by default.  frsd_profile(1) makes every later kernel launch of every plan
+ * record a start and a stop event; frsd_profile_report waits for the
+ * recorded events, writes one line "name launches total_ms" per kernel name
+ * into buf (NUL-terminated, truncated to len), and clears the records. */
+int frsd_profile(int enable);
+int frsd_profile_report(char *buf, size_t len);
+
 /* Thread-local description of the last failure ("" if none). */
 const char *frsd_last_error(void);
 

@@ -183,13 +183,13 @@ static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, T
     a.npair = std::min(kPairBatch, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * M,
                     nx = (long long)a.npair * M * M;
-    hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(kShThreads), shmem, s,
+    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(kShThreads), shmem, s,
                        ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, P, st, (const C *)tw,
-                       ws_ptr<C>(ws, L.buf1));
-    hipLaunchKernelGGL((k_shell_y<T>), dim3((unsigned)((ny + P - 1) / P)), dim3(kShThreads), shmem, s,
-                       ws_ptr<const C>(ws, L.buf1), a, P, st, (const C *)tw, ws_ptr<C>(ws, L.buf2));
-    hipLaunchKernelGGL((k_shell_x<T, TO>), dim3((unsigned)((nx + P - 1) / P)), dim3(kShThreads), shmem, s,
-                       ws_ptr<const C>(ws, L.buf2), a, P, st, (const C *)tw, shells);
+                       ws_ptr<C>(ws, L.buf1)));
+    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y<T>), dim3((unsigned)((ny + P - 1) / P)), dim3(kShThreads), shmem, s,
+                       ws_ptr<const C>(ws, L.buf1), a, P, st, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
+    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x<T, TO>), dim3((unsigned)((nx + P - 1) / P)), dim3(kShThreads), shmem, s,
+                       ws_ptr<const C>(ws, L.buf2), a, P, st, (const C *)tw, shells));
     FRSD_LAUNCH_CHECK();
   }
   return FRSD_OK;
@@ -297,10 +297,10 @@ static int contract(frsd_plan *pl, void *ws, const T *fields, int nfield, const 
   const size_t shmem = sizeof(T) * (size_t)nfield * kTriChunk;
   FRSD_HIP(hipFuncSetAttribute((const void *)k_triple<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const unsigned ny = (unsigned)((nout + kTriThreads * kTriKO - 1) / (kTriThreads * kTriKO));
-  hipLaunchKernelGGL(k_triple<T>, dim3(kTriBlocks, ny), dim3(kTriThreads), shmem, s, fields, M3, nfield, otab, nout,
-                     ws_ptr<double>(ws, L.tri_part));
-  hipLaunchKernelGGL(k_sum_part, dim3((nout + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.tri_part),
-                     kTriBlocks, nout, ws_ptr<double>(ws, L.tri_sum));
+  FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple<T>, dim3(kTriBlocks, ny), dim3(kTriThreads), shmem, s, fields, M3, nfield, otab, nout,
+                     ws_ptr<double>(ws, L.tri_part)));
+  FRSD_TIMED("tri_reduce", s, hipLaunchKernelGGL(k_sum_part, dim3((nout + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.tri_part),
+                     kTriBlocks, nout, ws_ptr<double>(ws, L.tri_sum)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -315,8 +315,8 @@ int run_nt(frsd_plan *pl, void *ws, hipStream_t s) {
   rc = contract<double>(pl, ws, shells, pl->p.bk_nbins, otab, (int)pl->ntri, s);
   if (rc) return rc;
   const double inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
-  hipLaunchKernelGGL(k_nt_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s,
-                     ws_ptr<const double>(ws, L.tri_sum), (int)pl->ntri, inv_m3, ws_ptr<double>(ws, L.nt));
+  FRSD_TIMED("nt_final", s, hipLaunchKernelGGL(k_nt_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s,
+                     ws_ptr<const double>(ws, L.tri_sum), (int)pl->ntri, inv_m3, ws_ptr<double>(ws, L.nt)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -335,9 +335,9 @@ int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s) {
   a.inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
   // the triangle list is kept in the tail of the table region as int32 triples
   const int *tri = reinterpret_cast<const int *>(ws_ptr<const int4>(ws, L.tri_tab) + pl->n_out + pl->ntri);
-  hipLaunchKernelGGL(k_bk_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s, tri,
+  FRSD_TIMED("bk_final", s, hipLaunchKernelGGL(k_bk_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s, tri,
                      ws_ptr<const double>(ws, L.tri_sum), ws_ptr<const double>(ws, L.nt),
-                     ws_ptr<const double>(ws, L.bin_sum), ws_ptr<const double>(ws, L.scal), a, *out);
+                     ws_ptr<const double>(ws, L.bin_sum), ws_ptr<const double>(ws, L.scal), a, *out));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

@@ -91,12 +91,12 @@ int fft3d_forward(const FftLen &f, const void *tw, void *mesh, int n_batch, hipS
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  hipLaunchKernelGGL((k_fft_axis<T, 2>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
-                     (const C *)tw, bs);
-  hipLaunchKernelGGL((k_fft_axis<T, 1>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
-                     (const C *)tw, bs);
-  hipLaunchKernelGGL((k_fft_axis<T, 0>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
-                     (const C *)tw, bs);
+  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
+                     (const C *)tw, bs));
+  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
+                     (const C *)tw, bs));
+  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0>), grid, dim3(kFftThreads), shmem, s, (C *)mesh, N, P, st,
+                     (const C *)tw, bs));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

@@ -134,6 +134,25 @@ void clear_error();
                                          hipGetErrorString(e_));             \
   } while (0)
 
+// Optional per-kernel timing (frsd_profile): events recorded on the launch
+// stream around each wrapped launch.
+bool prof_on();
+class ProfScope {
+ public:
+  ProfScope(const char *name, hipStream_t s);
+  ~ProfScope();
+
+ private:
+  const char *name_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+#define FRSD_TIMED(name, stream, ...)          \
+  do {                                         \
+    ::frsd::ProfScope prof_scope_(name, stream); \
+    __VA_ARGS__;                               \
+  } while (0)
+
 template <typename T>
 inline T *ws_ptr(void *ws, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + off);

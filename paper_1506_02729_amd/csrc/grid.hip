@@ -258,9 +258,9 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const unsigned ntiles = (unsigned)((N / kTX) * (N / kTY) * (N / kTZ));
   const unsigned ngroups = (unsigned)((pl->slots.n_slot + GMAX - 1) / GMAX);
-  hipLaunchKernelGGL(kern, dim3(ntiles, ngroups), dim3(kGridThreads), shmem, s, ws_ptr<const int>(ws, L.cnt),
+  FRSD_TIMED("grid", s, hipLaunchKernelGGL(kern, dim3(ntiles, ngroups), dim3(kGridThreads), shmem, s, ws_ptr<const int>(ws, L.cnt),
                      ws_ptr<const int>(ws, L.sorted), ws_ptr<const T>(ws, L.sorted + cstride), fstride, N,
-                     pl->slots, mt, ws_ptr<cplx_t<T>>(ws, L.mesh), (long long)N * N * N);
+                     pl->slots, mt, ws_ptr<cplx_t<T>>(ws, L.mesh), (long long)N * N * N));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

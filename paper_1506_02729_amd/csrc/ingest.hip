@@ -222,10 +222,10 @@ template <typename TIN>
 static void launch_count(const frsd_catalog *c, int is_ran, long long off, const GeomArgs &g, void *ws,
                          const frsd_plan *pl, hipStream_t s) {
   const Layout &L = pl->L;
-  hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
+  FRSD_TIMED("count", s, hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
                      (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<double>(ws, L.scal_part), ws_ptr<unsigned long long>(ws, L.reject));
+                     ws_ptr<double>(ws, L.scal_part), ws_ptr<unsigned long long>(ws, L.reject)));
 }
 
 template <typename TIN, typename T>
@@ -235,10 +235,10 @@ static void launch_scatter(const frsd_catalog *c, int is_ran, long long off, dou
   const size_t nobj = (size_t)(pl->p.max_objects > 0 ? pl->p.max_objects : 1);
   const size_t cstride = sorted_stride(nobj, 4);
   const size_t fstride = sorted_stride(nobj, sizeof(T)) / sizeof(T);
-  hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
+  FRSD_TIMED("scatter", s, hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
                      (const TIN *)c->pos, (const TIN *)c->w, (long long)c->n, is_ran, off, alpha, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<int>(ws, L.sorted), ws_ptr<T>(ws, L.sorted + cstride), fstride);
+                     ws_ptr<int>(ws, L.sorted), ws_ptr<T>(ws, L.sorted + cstride), fstride));
 }
 
 template <typename T>
@@ -249,8 +249,8 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   const long long ncell = (long long)N * N * N;
   GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N};
 
-  hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0);
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject));
+  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0));
+  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject)));
   const frsd_catalog *cats[2] = {gal, ran};
   long long off = 0;
   for (int k = 0; k < 2; ++k) {
@@ -261,17 +261,17 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   FRSD_LAUNCH_CHECK();
   const long long n = ncell + 1;
   const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk));
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, ws_ptr<int>(ws, L.scan_blk), nb);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk));
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk)));
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, ws_ptr<int>(ws, L.scan_blk), nb));
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk)));
   off = 0;
   for (int k = 0; k < 2; ++k) {
     if (cats[k]->dtype == FRSD_F64) launch_scatter<double, T>(cats[k], k, off, alpha, g, ws, pl, s);
     else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s);
     off += cats[k]->n;
   }
-  hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(64), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
-                     ws_ptr<double>(ws, L.scal));
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(64), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
+                     ws_ptr<double>(ws, L.scal)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

@@ -238,16 +238,16 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
   }
   using C = cplx_t<T>;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
-  hipLaunchKernelGGL(k_bin<T>, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh), NNN,
+  FRSD_TIMED("bin", s, hipLaunchKernelGGL(k_bin<T>, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh), NNN,
                      pl->slots, ca, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                      p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
-                     p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr, ws_ptr<double>(ws, L.bin_part));
+                     p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr, ws_ptr<double>(ws, L.bin_part)));
   const int nvals = nall * kBinSums;
-  hipLaunchKernelGGL(k_bin_reduce, dim3((nvals + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_part),
-                     kBinBlocks, nvals, ws_ptr<double>(ws, L.bin_sum));
-  hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nvals + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_part),
+                     kBinBlocks, nvals, ws_ptr<double>(ws, L.bin_sum)));
+  FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
                      ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
-                     out->p4, out->s00, out->s20, out->s40, out->scalars);
+                     out->p4, out->s00, out->s20, out->s40, out->scalars));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

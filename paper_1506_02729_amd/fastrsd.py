@@ -78,6 +78,8 @@ _proto = {
     "frsd_bk_triangles": (ctypes.c_int, [_P, _P]),
     "frsd_bk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_bk_out), _P]),
     "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
+    "frsd_profile": (ctypes.c_int, [ctypes.c_int]),
+    "frsd_profile_report": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
     "frsd_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _proto.items():
@@ -150,6 +152,21 @@ def frsd_status(plan, ws_ptr, stream) -> int:
     if rc not in (FRSD_OK, FRSD_EDOM):
         _check(rc)
     return v.value
+
+
+def frsd_profile(enable: bool) -> None:
+    _check(_lib.frsd_profile(1 if enable else 0))
+
+
+def frsd_profile_report() -> dict:
+    """{kernel name: (launches, total_ms)} recorded since the last report."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.frsd_profile_report(buf, len(buf)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
+    return out
 
 
 # --- convenience plan object ---------------------------------------------------

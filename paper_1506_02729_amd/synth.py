@@ -22,8 +22,12 @@ Generators (seed = 1000 * workload + stream, NumPy ``Generator(PCG64)``):
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 
 def rng_for(workload: int, stream: int = 0) -> np.random.Generator:
@@ -114,11 +118,11 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     sigma2 = float(np.sum(pk * mult[None, None, :]) / L**3)
 
     white = rng.standard_normal((N, N, N))
-    gk = np.fft.rfftn(white)
+    gk = sfft.rfftn(white, workers=_WORKERS)
     del white
     gk *= np.sqrt(pk / h**3)
     del pk
-    delta = np.fft.irfftn(gk, s=(N, N, N), axes=(0, 1, 2))
+    delta = sfft.irfftn(gk, s=(N, N, N), axes=(0, 1, 2), workers=_WORKERS)
     np.exp(delta - 0.5 * sigma2, out=delta)           # 1 + delta
     lam = (nbar * h**3) * delta.ravel()
     del delta
@@ -135,7 +139,7 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     ux = np.zeros(len(cells))
     k2[0, 0, 0] = 1.0
     for d, kd in enumerate((kx[:, None, None], kx[None, :, None], kz[None, None, :])):
-        comp = np.fft.irfftn(-1j * kd * gk / k2, s=(N, N, N), axes=(0, 1, 2)).ravel()
+        comp = sfft.irfftn(-1j * kd * gk / k2, s=(N, N, N), axes=(0, 1, 2), workers=_WORKERS).ravel()
         ux += comp[cells] * xhat[:, d]
         del comp
     del gk, k2
