@@ -21,8 +21,6 @@
 
 namespace frsd {
 
-constexpr int kShThreads = 256;
-constexpr int kShPN = 4096;
 constexpr int kTriThreads = 256;
 constexpr int kTriKO = 32;     // outputs per thread
 constexpr int kTriChunk = 64;  // cells staged per step
@@ -41,24 +39,24 @@ static StageList stage_list(const FftLen &f) {
 }
 
 // z pass: pencils (pair, ix, iy) of the low-k cube, output buf1[pair][ix][iy][z]
-template <typename T, bool IND>
-__global__ __launch_bounds__(kShThreads) void k_shell_z(const cplx_t<T> *__restrict__ lowk,
+template <typename T, bool IND, int LEN>
+__global__ __launch_bounds__(FftTune<T>::threads) void k_shell_z(const cplx_t<T> *__restrict__ lowk,
                                                         const int16_t *__restrict__ lut, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
   using C = cplx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
-  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long DD = (long long)D * D;
   const long long npen_all = (long long)a.npair * DD;
   const long long q0 = (long long)blockIdx.x * P;
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  for (int i = threadIdx.x; i < npen * ld; i += FftTune<T>::threads) lds[i] = cmake<C>(T(0), T(0));
   __syncthreads();
   const long long DDD = DD * D;
-  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+  for (int f = threadIdx.x; f < npen * D; f += FftTune<T>::threads) {
     const int p = f / D, kz = f - p * D;
     const long long q = q0 + p;
     const int pair = (int)(q / DD);
@@ -83,30 +81,30 @@ __global__ __launch_bounds__(kShThreads) void k_shell_z(const cplx_t<T> *__restr
     lds[p * ld + (nz + M) % M] = cmake<C>(ar - bi, ai + br);
   }
   __syncthreads();
-  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
+  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
   C *dst = buf1 + q0 * M;
-  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+  for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int p = f / M, e = f - p * M;
     dst[f] = lds[p * ld + e];
   }
 }
 
 // y pass: pencils (pair, ix, z); input buf1[pair][ix][iy][z], output buf2[pair][ix][y][z]
-template <typename T>
-__global__ __launch_bounds__(kShThreads) void k_shell_y(const cplx_t<T> *__restrict__ buf1, ShellArgs a, int P,
+template <typename T, int LEN>
+__global__ __launch_bounds__(FftTune<T>::threads) void k_shell_y(const cplx_t<T> *__restrict__ buf1, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
   using C = cplx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
-  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long npen_all = (long long)a.npair * D * M;
   const long long q0 = (long long)blockIdx.x * P;
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  for (int i = threadIdx.x; i < npen * ld; i += FftTune<T>::threads) lds[i] = cmake<C>(T(0), T(0));
   __syncthreads();
-  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+  for (int f = threadIdx.x; f < npen * D; f += FftTune<T>::threads) {
     const int iy = f / npen, p = f - iy * npen;
     const long long q = q0 + p;               // q = (pair * D + ix) * M + z
     const long long pix = q / M;
@@ -114,8 +112,8 @@ __global__ __launch_bounds__(kShThreads) void k_shell_y(const cplx_t<T> *__restr
     lds[p * ld + (iy - nc + M) % M] = buf1[(pix * D + iy) * M + z];
   }
   __syncthreads();
-  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
-  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
+  for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int y = f / npen, p = f - y * npen;
     const long long q = q0 + p;
     const long long pix = q / M;
@@ -126,22 +124,22 @@ __global__ __launch_bounds__(kShThreads) void k_shell_y(const cplx_t<T> *__restr
 
 // x pass: pencils (pair, y, z); input buf2[pair][ix][y][z]; output the two
 // real shell fields of the pair, shells[f][x][y][z]
-template <typename T, typename TO>
-__global__ __launch_bounds__(kShThreads) void k_shell_x(const cplx_t<T> *__restrict__ buf2, ShellArgs a, int P,
+template <typename T, typename TO, int LEN>
+__global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T> *__restrict__ buf2, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, TO *shells) {
   using C = cplx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int ld = a.M + 1, M = a.M, D = a.D, nc = a.nc;
-  for (int i = threadIdx.x; i < M; i += kShThreads) tw[i] = tw_g[i];
+  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long MM = (long long)M * M;
   const long long npen_all = (long long)a.npair * MM;
   const long long q0 = (long long)blockIdx.x * P;
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  for (int i = threadIdx.x; i < npen * ld; i += kShThreads) lds[i] = cmake<C>(T(0), T(0));
+  for (int i = threadIdx.x; i < npen * ld; i += FftTune<T>::threads) lds[i] = cmake<C>(T(0), T(0));
   __syncthreads();
-  for (int f = threadIdx.x; f < npen * D; f += kShThreads) {
+  for (int f = threadIdx.x; f < npen * D; f += FftTune<T>::threads) {
     const int ix = f / npen, p = f - ix * npen;
     const long long q = q0 + p;               // q = pair * M^2 + (y * M + z)
     const long long pair = q / MM;
@@ -149,9 +147,9 @@ __global__ __launch_bounds__(kShThreads) void k_shell_x(const cplx_t<T> *__restr
     lds[p * ld + (ix - nc + M) % M] = buf2[(pair * D + ix) * MM + yz];
   }
   __syncthreads();
-  lds_fft<C, true, kShThreads, kShPN>(lds, ld, M, npen, st, tw);
+  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
   const long long MMM = MM * M;
-  for (int f = threadIdx.x; f < npen * M; f += kShThreads) {
+  for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int x = f / npen, p = f - x * npen;
     const long long q = q0 + p;
     const long long pair = q / MM;
@@ -163,36 +161,47 @@ __global__ __launch_bounds__(kShThreads) void k_shell_x(const cplx_t<T> *__restr
   }
 }
 
-template <typename T, typename TO, bool IND>
-static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
+template <typename T, typename TO, bool IND, int LEN>
+static int shell_pipeline_len(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
   using C = cplx_t<T>;
   const Layout &L = pl->L;
   ShellArgs a{};
   a.M = pl->M; a.D = pl->D; a.nc = pl->nc_b; a.nb = pl->p.bk_nbins; a.nfield = nfield;
   a.lut_len = pl->bk_lut_len;
   const int M = a.M, D = a.D;
-  const int P = kShPN / M;
+  const int P = FftTune<T>::pn / M;
   const StageList st = stage_list(pl->fft_m);
   const size_t shmem = sizeof(C) * ((size_t)M + (size_t)P * (M + 1));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z<T, IND>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z<T, IND, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const int npairs = (nfield + 1) / 2;
   for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
     a.pair0 = p0;
     a.npair = std::min(kPairBatch, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * M,
                     nx = (long long)a.npair * M * M;
-    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(kShThreads), shmem, s,
+    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND, LEN>), dim3((unsigned)((nz + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, P, st, (const C *)tw,
                        ws_ptr<C>(ws, L.buf1)));
-    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y<T>), dim3((unsigned)((ny + P - 1) / P)), dim3(kShThreads), shmem, s,
+    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.buf1), a, P, st, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
-    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x<T, TO>), dim3((unsigned)((nx + P - 1) / P)), dim3(kShThreads), shmem, s,
+    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x<T, TO, LEN>), dim3((unsigned)((nx + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.buf2), a, P, st, (const C *)tw, shells));
     FRSD_LAUNCH_CHECK();
   }
   return FRSD_OK;
+}
+
+template <typename T, typename TO, bool IND>
+static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
+  switch (pl->M) {
+#define FRSD_CASE(L) \
+  case L: return shell_pipeline_len<T, TO, IND, L>(pl, ws, nfield, tw, shells, s);
+    FRSD_FFT_LENGTHS(FRSD_CASE)
+#undef FRSD_CASE
+    default: return shell_pipeline_len<T, TO, IND, 0>(pl, ws, nfield, tw, shells, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -328,7 +337,12 @@ int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s) {
   T *shells = ws_ptr<T>(ws, L.shells);
   int rc = shell_pipeline<T, T, false>(pl, ws, nfield, ws_ptr<void>(ws, L.tw_inv), shells, s);
   if (rc) return rc;
-  rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+  if constexpr (sizeof(T) == 4) {
+    if (triple_mfma_supported(pl)) rc = triple_mfma(pl, ws, reinterpret_cast<const float *>(shells), s);
+    else rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+  } else {
+    rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+  }
   if (rc) return rc;
   BkFinalArgs a{};
   a.ntri = (int)pl->ntri; a.n_ell = pl->n_ell; a.pk_nb = pl->p.pk_nbins;
@@ -408,6 +422,15 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
     FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tri_tab), tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice));
     FRSD_HIP(hipMemcpy(ws_ptr<int4>(ws, L.tri_tab) + tab.size(), pl->tri.data(), pl->tri.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice));
+    // rows of the dense contraction: pair r = b2 (b2 + 1) / 2 + b3, b2 >= b3
+    std::vector<int2> pairs;
+    for (int b2 = 0; b2 < nb; ++b2)
+      for (int b3 = 0; b3 <= b2; ++b3) pairs.push_back(make_int2(b2, b3));
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.pair_tab), pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
+    if (!f64 && triple_mfma_supported(pl)) {
+      const int rc = triple_mfma_upload(pl, ws);
+      if (rc) return rc;
+    }
   }
   return FRSD_OK;
 }

@@ -152,6 +152,81 @@ struct StageList {
   int radix[12];
 };
 
+// Compile-time radix schedule of a length LEN = 2^a 3^b (same order as the
+// host schedule: all factors 3, then 8s, then one 4 and/or one 2).
+constexpr int ct_radix(int len, int s) {
+  int m = len, k = 0;
+  while (m % 3 == 0) { if (k == s) return 3; m /= 3; ++k; }
+  while (m % 8 == 0) { if (k == s) return 8; m /= 8; ++k; }
+  if (m % 4 == 0) { if (k == s) return 4; m /= 4; ++k; }
+  if (m % 2 == 0) { if (k == s) return 2; m /= 2; ++k; }
+  return 0;
+}
+constexpr int ct_nstage(int len) {
+  int s = 0;
+  while (ct_radix(len, s) != 0) ++s;
+  return s;
+}
+
+// One Stockham stage with everything known at compile time except the
+// number of pencils P.
+template <typename C, int R, bool INV, int THREADS, int PN, int LEN, int NS>
+__device__ __forceinline__ void stockham_stage_ct(C *lds, int ld, int P, const C *tw) {
+  constexpr int MAXB = (PN + R * THREADS - 1) / (R * THREADS);
+  constexpr int nbf = LEN / R;
+  constexpr int tstride = LEN / (NS * R);
+  const int total = P * nbf;
+  C v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const int k = j % NS;
+      const C *src = lds + p * ld + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * k * tstride];
+          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+        }
+      }
+      dftR<C, R, INV>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * THREADS;
+    if (b < total) {
+      const int p = b / nbf;
+      const int j = b - p * nbf;
+      const int k = j % NS;
+      C *dst = lds + p * ld + (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename C, bool INV, int THREADS, int PN, int LEN, int S = 0, int NS = 1>
+__device__ __forceinline__ void lds_fft_ct(C *lds, int ld, int P, const C *tw) {
+  if constexpr (S < ct_nstage(LEN)) {
+    constexpr int R = ct_radix(LEN, S);
+    stockham_stage_ct<C, R, INV, THREADS, PN, LEN, NS>(lds, ld, P, tw);
+    lds_fft_ct<C, INV, THREADS, PN, LEN, S + 1, NS * R>(lds, ld, P, tw);
+  }
+}
+
+// Transform of P pencils of length n (LEN = n at compile time, or 0 for a
+// run-time length with the stage list st).
+template <typename C, bool INV, int THREADS, int PN, int LEN>
+__device__ __forceinline__ void lds_fft_any(C *lds, int ld, int n, int P, const StageList &st, const C *tw);
+
 // Full transform of P pencils in LDS.  Caller synchronises before the call
 // (data loaded) and may read results right after it returns.
 template <typename C, bool INV, int THREADS, int PN>
@@ -166,5 +241,22 @@ __device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const
     Ns *= R;
   }
 }
+
+template <typename C, bool INV, int THREADS, int PN, int LEN>
+__device__ __forceinline__ void lds_fft_any(C *lds, int ld, int n, int P, const StageList &st, const C *tw) {
+  if constexpr (LEN > 0) lds_fft_ct<C, INV, THREADS, PN, LEN>(lds, ld, P, tw);
+  else lds_fft<C, INV, THREADS, PN>(lds, ld, n, P, st, tw);
+}
+
+// Pencil batching of the LDS transforms: P = pn / n pencils per workgroup.
+// FP32 stages 8192 complex values with 512 threads so that the strided
+// passes move rows of >= 16 consecutive complex values (>= 128 bytes).
+template <typename T> struct FftTune {
+  static constexpr int threads = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int pn = sizeof(T) == 4 ? 8192 : 4096;
+};
+
+// Lengths with a compile-time kernel; other 2^a 3^b lengths use the run-time one.
+#define FRSD_FFT_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 }  // namespace frsd

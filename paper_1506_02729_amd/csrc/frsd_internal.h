@@ -63,18 +63,21 @@ struct Layout {
   size_t slot = 0, cellkey = 0;                  // per-object rank within its cell, cell id
   size_t sorted = 0;                             // sorted object records
   size_t mesh = 0;                               // n_slot complex N^3 meshes
+  size_t planar = 0;                             // 2 n_slot real N^3 assignment planes
+  size_t tile_cnt = 0;                           // objects per 8 x 4 x 16 gridding tile
   size_t bin_part = 0, bin_sum = 0;              // shell-sum partials and totals
   size_t lowk = 0;                               // A_0, A_2, A_4 on |n| < top bk edge
   size_t buf1 = 0, buf2 = 0;                     // inverse-FFT intermediates
   size_t shells = 0;                             // shell fields on M^3
   size_t tri_tab = 0, tri_part = 0, tri_sum = 0; // contraction tables and partials
+  size_t pair_tab = 0, tri_dense = 0;             // (b2, b3) of each row; dense sums of the MFMA path
   size_t nt = 0;                                 // N^T per triangle
   size_t pk_lut = 0, bk_lut = 0;                 // |n|^2 -> bin index (int16, -1 outside)
   size_t total = 0;
 };
 
 // Sorted object records, structure of arrays inside the `sorted` region:
-// cell id (int32), then 8 arrays of T: fx, fy, fz (fraction of the grid
+// packed cell coordinates (int32: cx << 20 | cy << 10 | cz), then 8 arrays of T: fx, fy, fz (fraction of the grid
 // coordinate inside its cell), t0 (signed weight s w), tw (w^2 weight of
 // F_0^w), xhat_x, xhat_y, xhat_z.
 inline size_t sorted_stride(size_t nobj, size_t tbytes) { return ((nobj * tbytes) + 255) & ~(size_t)255; }
@@ -87,6 +90,7 @@ constexpr int kScalars = 4;     // I22, N0, I33, W3
 constexpr int kIngestBlocks = 1024;
 constexpr int kBinBlocks = 2048;
 constexpr int kTriBlocks = 1024;
+constexpr int kTriMfmaBlocks = 1024;
 constexpr int kPairBatch = 8;   // shell-field pairs per inverse-FFT batch
 
 }  // namespace frsd
@@ -170,9 +174,17 @@ int run_nt(frsd_plan *pl, void *ws, hipStream_t s);
 int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
 
 // FFT passes (fft.hip) --------------------------------------------------------
-// Forward c2c FFT in place over n_batch contiguous N^3 complex meshes.
+// Forward c2c FFT of n_batch N^3 complex meshes given as planar real arrays
+// (re of mesh s = array 2s, im = array 2s+1); output interleaved complex.
 template <typename T>
-int fft3d_forward(const FftLen &f, const void *tw, void *mesh, int n_batch, hipStream_t s);
+int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, hipStream_t s);
+
+// Triple-product contraction on the matrix cores (triple_mfma.hip).
+bool triple_mfma_supported(const frsd_plan *pl);
+size_t triple_mfma_part_bytes(int nwg);
+size_t triple_mfma_dense_bytes();
+int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
+int triple_mfma_upload(frsd_plan *pl, void *ws);
 
 // Shell-filtered inverse FFTs on the M^3 grid (bk.hip).
 template <typename T>

@@ -67,7 +67,7 @@ template <typename TIN>
 __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const TIN *w, const TIN *nbar,
                                                            long long n, int is_ran, long long obj_off,
                                                            GeomArgs g, int *cnt, int *slot, int *cellkey,
-                                                           double *part, unsigned long long *reject) {
+                                                           int *tile_cnt, double *part, unsigned long long *reject) {
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -79,6 +79,8 @@ __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const 
       const int cell = (cx * g.N + cy) * g.N + cz;
       slot[obj_off + i] = atomicAdd(&cnt[cell], 1);
       cellkey[obj_off + i] = cell;
+      // gridding tiles are 8 x 4 x 16 cells
+      atomicAdd(&tile_cnt[((cx >> 3) * (g.N >> 2) + (cy >> 2)) * (g.N >> 4) + (cz >> 4)], 1);
       const double wi = (double)w[i];
       const double w2 = wi * wi, w3 = w2 * wi;
       if (is_ran) {
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, cons
     const double rx = x - g.ox, ry = y - g.oy, rz = z - g.oz;
     const double ir = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
     const double wi = (double)w[i];
-    r_cell[dst] = cell;
+    r_cell[dst] = (cx << 20) | (cy << 10) | cz;  // packed cell coordinates (N <= 1024)
     fx[dst] = (T)f0; fy[dst] = (T)f1; fz[dst] = (T)f2;
     t0[dst] = (T)(is_ran ? -alpha * wi : wi);
     tw[dst] = (T)(is_ran ? alpha * alpha * wi * wi : wi * wi);
@@ -225,7 +227,8 @@ static void launch_count(const frsd_catalog *c, int is_ran, long long off, const
   FRSD_TIMED("count", s, hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
                      (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<double>(ws, L.scal_part), ws_ptr<unsigned long long>(ws, L.reject)));
+                     ws_ptr<int>(ws, L.tile_cnt), ws_ptr<double>(ws, L.scal_part),
+                     ws_ptr<unsigned long long>(ws, L.reject)));
 }
 
 template <typename TIN, typename T>
@@ -250,6 +253,8 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N};
 
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0));
+  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(256), 0, s, ws_ptr<int>(ws, L.tile_cnt),
+                                           ncell / 512, 0));
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject)));
   const frsd_catalog *cats[2] = {gal, ran};
   long long off = 0;

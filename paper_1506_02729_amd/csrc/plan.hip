@@ -209,6 +209,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));
   L.mesh = take(2 * T * NNN * sd.n_slot);
+  L.planar = take(2 * T * NNN * sd.n_slot);
+  L.tile_cnt = take(4 * (NNN / 512));
   const int nbins_all = p.pk_nbins + p.bk_nbins;
   L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kBinBlocks);
   L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);
@@ -223,7 +225,10 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     const size_t shell_bytes = std::max(T * nfield, (size_t)8 * p.bk_nbins) * M * M * M;
     L.shells = take(shell_bytes);
     L.tri_tab = take(16 * (size_t)pl->n_out + 16 * (size_t)pl->ntri + 12 * (size_t)pl->ntri);
-    L.tri_part = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri) * kTriBlocks);
+    L.tri_part = take(std::max(8 * (size_t)std::max(pl->n_out, (int)pl->ntri) * kTriBlocks,
+                               triple_mfma_part_bytes(kTriMfmaBlocks)));
+    L.pair_tab = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
+    L.tri_dense = take(triple_mfma_dense_bytes());
     L.tri_sum = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri));
     L.nt = take(8 * (size_t)pl->ntri);
   }
