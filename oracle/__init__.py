@@ -15,10 +15,10 @@ float64, of what the estimator computes:
 * ``brute``      -- brute-force twins used to pin the estimator: per-mode
   direct sums over objects, direct triangle enumeration, lattice-point
   counts.
-* ``assign_c``   -- an optional plain-C (OpenMP) mass-assignment helper with
-  the same definition as ``estimator.assign_mesh``, used only to keep the
-  oracle tractable on catalogs of 10^7-10^8 objects; it is pinned against
-  the NumPy path in the CPU tests.
+
+Parity unpinned: the l > 0 thin-shell shot-noise q1 term (SN2, SN4) has no
+pin beyond its formula, and I33 (not defined in the paper; read as
+alpha sum_r nbar^2 w^3) is pinned only through its definition.
 
 It shares no code with the GPU path.  Every function cites the passage of
 the paper it follows.
