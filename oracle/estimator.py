@@ -27,7 +27,12 @@ import math
 from dataclasses import dataclass, field
 from itertools import product
 
+import os
+
 import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 # ---------------------------------------------------------------------------
 # Moment tensors (Sec. II.B eqs. delta2b and delta4b)
@@ -254,7 +259,7 @@ def combined_catalog(gal, ran, alpha):
     return np.asarray(pos, np.float64), np.asarray(w, np.float64), np.asarray(w2, np.float64)
 
 
-def fourier_of_weights(u, weight, prm: Params, nx, ny, nz):
+def fourier_of_weights(u, weight, prm: Params, nx, ny, nz, u_twin=None):
     """Compensated, interlaced Fourier transform of one weighted point set.
 
     Returns sum_j weight_j exp(-i k.x_j) as estimated on the grid: the
@@ -264,9 +269,10 @@ def fourier_of_weights(u, weight, prm: Params, nx, ny, nz):
     """
     N, p = prm.n_grid, prm.order
     assign = prm.assign or assign_mesh
-    X = np.fft.rfftn(assign(u, weight, N, p))
+    X = sfft.rfftn(assign(u, weight, N, p), workers=_WORKERS)
     if prm.interlace:
-        Y = np.fft.rfftn(assign(u - 0.5, weight, N, p))
+        ut = u - 0.5 if u_twin is None else u_twin
+        Y = sfft.rfftn(assign(ut, weight, N, p), workers=_WORKERS)
         X = 0.5 * (X + np.exp(-1j * np.pi * (nx + ny + nz) / N) * Y)
     if prm.compensate:
         win = np.ones(X.shape)
@@ -290,6 +296,7 @@ def multipole_fields(gal, ran, alpha, prm: Params, with_w: bool = False,
     N = prm.n_grid
     pos, w, w2 = combined_catalog(gal, ran, alpha)
     u = pos / (prm.box / N)
+    ut = u - 0.5                      # coordinates on the interlaced twin grid
     xhat = los_unit(pos, prm.observer)
     nx, ny, nz = half_grid(N)
     kk = np.sqrt((nx * nx + ny * ny + nz * nz).astype(np.float64))
@@ -303,23 +310,23 @@ def multipole_fields(gal, ran, alpha, prm: Params, with_w: bool = False,
         return out
 
     fields = {}
-    A0 = fourier_of_weights(u, w, prm, nx, ny, nz)
+    A0 = fourier_of_weights(u, w, prm, nx, ny, nz, ut)
     fields[0] = A0
     if prm.ell_max >= 2:
         s = np.zeros_like(A0)
         for idx in MOMENTS_2:
             s += multiplicity(idx) * khat_mono(idx) * fourier_of_weights(
-                u, w * monomial(xhat, idx), prm, nx, ny, nz)
+                u, w * monomial(xhat, idx), prm, nx, ny, nz, ut)
         A2 = 1.5 * s - 0.5 * A0
         fields[2] = A2
     if prm.ell_max >= 4:
         s = np.zeros_like(A0)
         for idx in MOMENTS_4:
             s += multiplicity(idx) * khat_mono(idx) * fourier_of_weights(
-                u, w * monomial(xhat, idx), prm, nx, ny, nz)
+                u, w * monomial(xhat, idx), prm, nx, ny, nz, ut)
         fields[4] = 35.0 / 8.0 * s - 2.5 * fields[2] - 7.0 / 8.0 * A0
     if with_w:
-        fields["w"] = fourier_of_weights(u, w2, prm, nx, ny, nz)
+        fields["w"] = fourier_of_weights(u, w2, prm, nx, ny, nz, ut)
     if sign > 0:
         fields = {k: np.conj(v) for k, v in fields.items()}
     return fields
@@ -465,7 +472,7 @@ def shell_field(values, nx, ny, nz, M: int) -> np.ndarray:
     """
     spec = np.zeros((M, M, M), dtype=np.complex128)
     spec[nx % M, ny % M, nz % M] = values
-    f = np.fft.ifftn(spec) * (M**3)
+    f = sfft.ifftn(spec, workers=_WORKERS) * (M**3)
     scale = np.sum(np.abs(values)) + 1e-300
     assert np.max(np.abs(f.imag)) <= 1e-10 * scale, "shell field not real"
     return f.real

@@ -416,3 +416,21 @@ def test_bk_shot_noise_thin_shell_monopole_on_poisson_points():
     assert np.all(np.abs(z) < 4.0), z
     assert abs(z.mean()) < 1.0
     assert z_raw.mean() > 10.0
+
+
+# --------------------------------------------------------------------------
+# The plain-C assignment loop equals the NumPy definition
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,order", [(32, 1), (32, 2), (48, 3), (64, 4), (16, 3)])
+def test_c_assignment_matches_numpy_definition(N, order):
+    from oracle import assign_c
+    rng = np.random.default_rng(N + order)
+    n = 7000
+    u = rng.random((n, 3)) * N
+    u[:50] -= 0.5            # twin-grid style coordinates below zero
+    u[50:100, 0] = N - 1e-9  # right at the periodic seam
+    w = rng.standard_normal(n)
+    a = assign_c.assign_mesh(u, w, N, order)
+    b = est.assign_mesh(u, w, N, order)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
