@@ -10,68 +10,98 @@
 // passes the P pencils are P consecutive z columns, so every global row
 // access is a contiguous run of P complex values.  Common lengths get a
 // kernel with the length and radix schedule fixed at compile time.
+//
+// Pruning: the binning step reads only modes whose signed frequencies all
+// satisfy |n_d| <= n_max (the largest component of any mode in a bin), so
+// each pass keeps only those frequencies of the axis it transforms: the z
+// pass writes kept z, the y pass transforms only kept-z columns and writes
+// kept y, the x pass transforms only columns with kept y and z and writes
+// kept x.  Kept indices form two runs, [0, ka) and [N - kb, N).  Entries
+// outside the kept set are never written and never read.
+#include <algorithm>
+
 #include "device.h"
 #include "frsd_internal.h"
 
 namespace frsd {
 
+struct Keep {
+  int ka, kb;    // kept runs [0, ka) and [N - kb, N) (kb = 0: one run [0, ka))
+  int nba, nbb;  // workgroups of P columns over each run
+};
+
+__device__ __forceinline__ bool kept(int e, int N, const Keep &k) { return e < k.ka || e >= N - k.kb; }
+
+// Column block b of the kept runs: first column and number of columns.
+__device__ __forceinline__ void column_block(int b, int P, int N, const Keep &k, int &z0, int &nz) {
+  if (b < k.nba) {
+    z0 = b * P;
+    nz = min(P, k.ka - z0);
+  } else {
+    z0 = N - k.kb + (b - k.nba) * P;
+    nz = min(P, N - z0);
+  }
+}
 
 // AXIS 2 reads the planar real arrays `planar` (re, im of mesh b at arrays
 // 2b, 2b+1) and writes `data`; AXIS 1 and 0 work in place on `data`.
+// Grid: AXIS 2 (N^2 / P rows, batch); AXIS 1 (x * (nba + nbb) + column
+// block, batch); AXIS 0 (kept y * (nba + nbb) + column block, batch).
 template <typename T, int AXIS, int LEN>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *data, const T *planar, int n_rt, int P_rt,
                                                            StageList st, const cplx_t<T> *tw_g,
-                                                           long long batch_stride) {
+                                                           long long batch_stride, Keep keep) {
   using C = cplx_t<T>;
+  constexpr int NT = FftTune<T>::threads;
   const int N = LEN ? LEN : n_rt;
   const int P = LEN ? FftTune<T>::pn / LEN : P_rt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + N;
   const int ld = N + 1;
-  for (int i = threadIdx.x; i < N; i += FftTune<T>::threads) tw[i] = tw_g[i];
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
 
   C *mesh = data + (long long)blockIdx.y * batch_stride;
   const long long NN = (long long)N * N;
-  const long long q0 = (long long)blockIdx.x * P;  // first pencil of this workgroup
-  const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
-  const int tot = npen * N;
 
   if (AXIS == 2) {
     // pencil q: row q of length N, contiguous in both planar arrays
+    const long long q0 = (long long)blockIdx.x * P;
+    const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
+    const int tot = npen * N;
     const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * N;
     const T *im = re + batch_stride;
-    for (int f = threadIdx.x; f < tot; f += FftTune<T>::threads) {
+    for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
       lds[p * ld + e] = cmake<C>(re[f], im[f]);
     }
-  } else {
-    // pencil q = (outer, z) with z fastest; element stride N (AXIS 1) or N^2 (AXIS 0)
-    const long long es = (AXIS == 1) ? N : NN;
-    for (int f = threadIdx.x; f < tot; f += FftTune<T>::threads) {
-      const int e = f / npen, p = f - e * npen;
-      const long long q = q0 + p;
-      const long long base = (AXIS == 1) ? ((q / N) * NN + (q % N)) : q;
-      lds[p * ld + e] = mesh[base + e * es];
+    __syncthreads();
+    lds_fft_any<C, false, NT, FftTune<T>::pn, LEN>(lds, ld, N, npen, st, tw);
+    C *dst = mesh + q0 * N;
+    for (int f = threadIdx.x; f < tot; f += NT) {
+      const int p = f / N, e = f - p * N;
+      if (kept(e, N, keep)) dst[f] = lds[p * ld + e];
     }
+    return;
+  }
+
+  // AXIS 1: pencil (x, z), element stride N; AXIS 0: pencil (y, z), stride N^2
+  const int nzb = keep.nba + keep.nbb;
+  const int outer_i = blockIdx.x / nzb;
+  int z0, npen;
+  column_block(blockIdx.x - outer_i * nzb, P, N, keep, z0, npen);
+  const int outer = (AXIS == 1) ? outer_i : (outer_i < keep.ka ? outer_i : N - keep.kb + (outer_i - keep.ka));
+  const long long es = (AXIS == 1) ? N : NN;
+  C *col = mesh + ((AXIS == 1) ? (long long)outer * NN : (long long)outer * N) + z0;
+  for (int f = threadIdx.x; f < P * N; f += NT) {
+    const int e = f / P, p = f - e * P;
+    if (p < npen) lds[p * ld + e] = col[e * es + p];
   }
   __syncthreads();
-  lds_fft_any<C, false, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, N, npen, st, tw);
-
-  if (AXIS == 2) {
-    C *dst = mesh + q0 * N;
-    for (int f = threadIdx.x; f < tot; f += FftTune<T>::threads) {
-      const int p = f / N, e = f - p * N;
-      dst[f] = lds[p * ld + e];
-    }
-  } else {
-    const long long es = (AXIS == 1) ? N : NN;
-    for (int f = threadIdx.x; f < tot; f += FftTune<T>::threads) {
-      const int e = f / npen, p = f - e * npen;
-      const long long q = q0 + p;
-      const long long base = (AXIS == 1) ? ((q / N) * NN + (q % N)) : q;
-      mesh[base + e * es] = lds[p * ld + e];
-    }
+  lds_fft_any<C, false, NT, FftTune<T>::pn, LEN>(lds, ld, N, npen, st, tw);
+  for (int f = threadIdx.x; f < P * N; f += NT) {
+    const int e = f / P, p = f - e * P;
+    if (p < npen && kept(e, N, keep)) col[e * es + p] = lds[p * ld + e];
   }
 }
 
@@ -84,41 +114,51 @@ static StageList stages_of(const FftLen &f) {
 
 template <typename T, int LEN>
 static int fft3d_forward_len(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch,
-                             hipStream_t s) {
+                             int nmax, hipStream_t s) {
   using C = cplx_t<T>;
   const int N = f.n;
   const int P = FftTune<T>::pn / N;
   const long long NN = (long long)N * N;
-  const unsigned nblk = (unsigned)((NN + P - 1) / P);
+  // kept runs [0, nmax] and [N - nmax, N), widened to whole blocks of P columns
+  Keep k{};
+  k.ka = std::min(N, (nmax + 1 + P - 1) / P * P);
+  const int b0 = std::max(k.ka, (N - nmax) / P * P);
+  k.kb = N - b0;
+  if (k.ka + k.kb >= N || 2 * nmax + 1 >= N) { k.ka = N; k.kb = 0; }
+  k.nba = (k.ka + P - 1) / P;
+  k.nbb = (k.kb + P - 1) / P;
+  const unsigned nzb = (unsigned)(k.nba + k.nbb);
   const size_t shmem = sizeof(C) * ((size_t)N + (size_t)P * (N + 1));
   const StageList st = stages_of(f);
   const long long bs = NN * N;
-  dim3 grid(nblk, n_batch);
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 2, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2, LEN>), grid, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs));
-  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1, LEN>), grid, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs));
-  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0, LEN>), grid, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs));
+  const dim3 gz((unsigned)((NN + P - 1) / P), n_batch), gy((unsigned)N * nzb, n_batch),
+      gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
+  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2, LEN>), gz, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
+  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1, LEN>), gy, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
+  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0, LEN>), gx, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
-int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, hipStream_t s) {
+int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+                  hipStream_t s) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_len<T, L>(f, tw, planar, mesh, n_batch, s);
+  case L: return fft3d_forward_len<T, L>(f, tw, planar, mesh, n_batch, nmax, s);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
-    default: return fft3d_forward_len<T, 0>(f, tw, planar, mesh, n_batch, s);
+    default: return fft3d_forward_len<T, 0>(f, tw, planar, mesh, n_batch, nmax, s);
   }
 }
 
-template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, hipStream_t);
-template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, hipStream_t);
+template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, hipStream_t);
+template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, hipStream_t);
 
 }  // namespace frsd

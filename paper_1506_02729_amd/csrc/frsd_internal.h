@@ -177,7 +177,8 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
 // Forward c2c FFT of n_batch N^3 complex meshes given as planar real arrays
 // (re of mesh s = array 2s, im = array 2s+1); output interleaved complex.
 template <typename T>
-int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, hipStream_t s);
+int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+                  hipStream_t s);
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);

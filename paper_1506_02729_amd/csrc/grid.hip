@@ -338,7 +338,7 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   }
   if (rc) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
-                          ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, s);
+                          ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax, s);
 }
 
 template int run_mesh_assign<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,

@@ -16,9 +16,10 @@
 // term is below 2^-16 relative).  Accumulation is FP32 inside a
 // workgroup's range of cells; workgroup partials are summed in FP64.
 //
-// Work split: 8 wavefronts per workgroup; wavefront w owns up to 16 output
-// tiles ("jobs", sorted by row tile) in 64 accumulator registers.  Every
-// workgroup covers all jobs for its own contiguous range of cells.
+// Work split: 16 wavefronts per workgroup (one workgroup per CU); wavefront
+// w owns up to 8 output tiles ("jobs", sorted by row tile) in 32 accumulator
+// registers.  Every workgroup covers all jobs for its own contiguous range
+// of cells.
 #include <vector>
 
 #include "device.h"
@@ -29,15 +30,16 @@ namespace frsd {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kXThreads = 512;
+constexpr int kXThreads = 1024;
 constexpr int kXWaves = kXThreads / 64;
-constexpr int kXMaxJobs = 16;     // output tiles per wavefront
+constexpr int kXMaxJobs = 8;      // output tiles per wavefront
 constexpr int kXCols = 112;       // columns (7 tiles)
 constexpr int kXMaxRows = 768;    // pairs
 constexpr int kXKC = 64;          // cells per LDS stage (2 MFMA k-steps)
-constexpr int kXUPad = kXKC + 4;  // FP32 row stride of the staged F_0 shells
-constexpr int kXBPad = kXKC + 8;  // bf16 row stride of the staged B operand
+constexpr int kXUPad = kXKC + 4;  // FP32 row stride of the staged F_0 shells (16-byte aligned rows)
+constexpr int kXBPad = kXKC + 8;  // bf16 row stride of the staged B operand (16-byte aligned rows)
 constexpr int kXMaxB = 37;        // bins
+constexpr int kXPf = (kXCols * (kXKC / 2) + kXThreads - 1) / kXThreads;  // cell pairs per thread per stage
 
 struct XJobs {
   uint8_t rt[kXWaves][kXMaxJobs];
@@ -52,17 +54,26 @@ struct XArgs {
   int nb, n_ell, ncol, npair, njobs;
 };
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
   hi = (__bf16)v;
   lo = (__bf16)(v - (float)hi);
 }
 
-__global__ __launch_bounds__(kXThreads, 2) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
+// One workgroup: a contiguous range of cells, all jobs.  Per stage of kXKC
+// cells every field is read once from HBM (two adjacent cells per thread),
+// split into bf16 hi/lo for the B operand, and the F_0 fields are kept in
+// FP32 for the on-the-fly pair products.  The global loads of stage s + 1
+// are issued before the MFMAs of stage s, so HBM latency hides behind them.
+__global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                float *__restrict__ part) {
-  __shared__ float U[kXMaxB][kXUPad];
+  __shared__ __attribute__((aligned(16))) float U[kXMaxB][kXUPad];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[kXCols][kXBPad];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[kXCols][kXBPad];
+  __shared__ uint16_t prs[kXMaxRows];  // b2 | b3 << 8 of each row, 0xffff past the last pair
+  __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -74,6 +85,15 @@ __global__ __launch_bounds__(kXThreads, 2) void k_triple_mfma(const float *__res
 #pragma unroll
   for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
+  for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
+    uint16_t v = 0xffff;
+    if (i < a.npair) { const int2 p = pairs[i]; v = (uint16_t)(p.x | (p.y << 8)); }
+    prs[i] = v;
+  }
+  for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
+    const int l = i / a.nb, b1 = i - l * a.nb;
+    cmap[i] = (uint8_t)(b1 * a.n_ell + l);
+  }
   // padding columns stay zero
   for (int i = threadIdx.x; i < (kXCols - a.ncol) * kXBPad; i += kXThreads) {
     const int c = a.ncol + i / kXBPad, k = i % kXBPad;
@@ -83,21 +103,52 @@ __global__ __launch_bounds__(kXThreads, 2) void k_triple_mfma(const float *__res
 
   const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
   const long long c_end = min(a.ncell, c_begin + a.cells_per_wg);
-  for (long long c0 = c_begin; c0 < c_end; c0 += kXKC) {
+  const int npe = a.ncol * (kXKC / 2);  // cell pairs per stage
+  const bool even = (a.ncell & 1) == 0;
+  float2 pf[kXPf];
+
+  auto load = [&](long long c0) {
     const int len = (int)min((long long)kXKC, c_end - c0);
-    __syncthreads();  // previous stage fully consumed
-    for (int i = threadIdx.x; i < a.ncol * kXKC; i += kXThreads) {
-      const int fl = i / kXKC, k = i - fl * kXKC;  // field fl = l * nb + b1
-      const float v = (k < len) ? f[(long long)fl * a.ncell + c0 + k] : 0.f;
-      const int l = fl / a.nb, b1 = fl - l * a.nb;
-      const int col = b1 * a.n_ell + l;
-      __bf16 h, lo;
-      split_bf16(v, h, lo);
-      Bh[col][k] = h;
-      Bl[col][k] = lo;
-      if (fl < a.nb) U[fl][k] = v;
+#pragma unroll
+    for (int q = 0; q < kXPf; ++q) {
+      const int e = threadIdx.x + q * kXThreads;
+      const int fl = e >> 5, k = 2 * (e & 31);
+      float2 v = make_float2(0.f, 0.f);
+      if (e < npe) {
+        const float *src = f + (long long)fl * a.ncell + c0 + k;
+        if (k + 1 < len) {
+          if (even) v = *reinterpret_cast<const float2 *>(src);
+          else v = make_float2(src[0], src[1]);
+        } else if (k < len) {
+          v.x = src[0];
+        }
+      }
+      pf[q] = v;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < kXPf; ++q) {
+      const int e = threadIdx.x + q * kXThreads;
+      if (e < npe) {
+        const int fl = e >> 5, k = 2 * (e & 31);
+        const int col = cmap[fl];
+        __bf16 h0, l0, h1, l1;
+        split_bf16(pf[q].x, h0, l0);
+        split_bf16(pf[q].y, h1, l1);
+        *reinterpret_cast<bf16x2_t *>(&Bh[col][k]) = bf16x2_t{h0, h1};
+        *reinterpret_cast<bf16x2_t *>(&Bl[col][k]) = bf16x2_t{l0, l1};
+        if (fl < a.nb) *reinterpret_cast<float2 *>(&U[fl][k]) = pf[q];
+      }
+    }
+  };
+
+  if (c_begin < c_end) load(c_begin);
+  for (long long c0 = c_begin; c0 < c_end; c0 += kXKC) {
+    __syncthreads();  // previous stage fully consumed (and the tables above written)
+    store();
     __syncthreads();
+    if (c0 + kXKC < c_end) load(c0 + kXKC);
 #pragma unroll
     for (int ks = 0; ks < kXKC / 32; ++ks) {
       const int k0 = ks * 32 + lk * 8;
@@ -109,16 +160,19 @@ __global__ __launch_bounds__(kXThreads, 2) void k_triple_mfma(const float *__res
           const int rt = jobs.rt[wave][j], ct = jobs.ct[wave][j];
           if (rt != cur_rt) {
             cur_rt = rt;
-            const int r = rt * 16 + li;
-            const bool ok = r < a.npair;
-            const int2 p = pairs[ok ? r : 0];
-            const float *u2 = &U[p.x][k0];
-            const float *u3 = &U[p.y][k0];
+            const unsigned pr = prs[rt * 16 + li];
+            const bool ok = pr != 0xffffu;
+            const int b2 = ok ? (int)(pr & 0xff) : 0, b3 = ok ? (int)(pr >> 8) : 0;
+            const float4 x0 = *reinterpret_cast<const float4 *>(&U[b2][k0]);
+            const float4 x1 = *reinterpret_cast<const float4 *>(&U[b2][k0 + 4]);
+            const float4 y0 = *reinterpret_cast<const float4 *>(&U[b3][k0]);
+            const float4 y1 = *reinterpret_cast<const float4 *>(&U[b3][k0 + 4]);
+            const float v[8] = {x0.x * y0.x, x0.y * y0.y, x0.z * y0.z, x0.w * y0.w,
+                                x1.x * y1.x, x1.y * y1.y, x1.z * y1.z, x1.w * y1.w};
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-              const float v = ok ? u2[e] * u3[e] : 0.f;
               __bf16 h, lo;
-              split_bf16(v, h, lo);
+              split_bf16(ok ? v[e] : 0.f, h, lo);
               ah[e] = h;
               al[e] = lo;
             }
@@ -186,9 +240,10 @@ static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *ti
   if (n > kXWaves * kXMaxJobs) return false;
   *jobs = XJobs{};
   tile_job->assign((size_t)kXMaxRows / 16 * 7, (int16_t)-1);
-  const int per = (n + kXWaves - 1) / kXWaves;
+  // n / kXWaves jobs per wave, one more for the first n % kXWaves waves
+  const int base = n / kXWaves, extra = n % kXWaves;
   for (int w = 0; w < kXWaves; ++w) {
-    const int a = std::min(n, w * per), b = std::min(n, (w + 1) * per);
+    const int a = w * base + std::min(w, extra), b = a + base + (w < extra ? 1 : 0);
     jobs->first[w] = a;
     jobs->nj[w] = b - a;
     for (int j = a; j < b; ++j) {

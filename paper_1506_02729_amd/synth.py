@@ -204,3 +204,15 @@ def kaiser_nodes(N: int, box: float, f: float, rng: np.random.Generator, pk=None
     pos = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1) * (box / N)
     cat = {"pos": pos, "w": field.ravel().copy(), "nbar": np.ones(N**3)}
     return cat, amp2
+
+
+def catalog_digest(gal: dict, ran: dict, alpha: float, observer) -> str:
+    """SHA-256 of a catalogue pair (float64 bytes of every array, alpha and the
+    observer), to tell whether two hosts drew bit-identical mocks."""
+    import hashlib
+    h = hashlib.sha256()
+    for cat in (gal, ran):
+        for key in ("pos", "w", "nbar"):
+            h.update(np.ascontiguousarray(cat[key], dtype=np.float64).tobytes())
+    h.update(np.asarray([alpha, *observer], dtype=np.float64).tobytes())
+    return h.hexdigest()

@@ -20,6 +20,7 @@ from paper_1506_02729_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = {64: 1e-10, 32: 2e-4}
+_ORACLE_CACHE = {}   # oracle results shared by the precisions of one case
 
 
 def _log(msg):
@@ -136,6 +137,26 @@ def test_pk_bk_interlaced(gpu_lib, precision, order, interlace):
     fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
     refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
     refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_pruned_fft_passes_192(gpu_lib, precision):
+    """N = 192 with k_max = 40.5 k_f: the forward FFT passes keep only
+    frequencies |n_d| <= 40 in column blocks that do not divide N."""
+    _log(f"case: pk+bk 192^3 pruned FFT precision={precision}")
+    if "pruned192" not in _ORACLE_CACHE:
+        gal, ran, alpha, prm = _bk_case(23, N=192, n_gal=30000, n_ran=150000)
+        kf = prm.kf
+        prm.pk_kmin, prm.pk_dk, prm.pk_nbins = 0.5 * kf, 2.0 * kf, 20
+        prm.bk_nbins = 6
+        fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+        refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+        refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
+        _ORACLE_CACHE["pruned192"] = (gal, ran, alpha, prm, refp, refb)
+    gal, ran, alpha, prm, refp, refb = _ORACLE_CACHE["pruned192"]
     out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
     _check_pk(out, refp, prm, precision)
     _check_bk(out, refb, prm, precision, plan)
