@@ -64,7 +64,6 @@ struct Layout {
   size_t sorted = 0;                             // sorted object records
   size_t mesh = 0;                               // n_slot complex N^3 meshes
   size_t planar = 0;                             // 2 n_slot real N^3 assignment planes
-  size_t tile_cnt = 0;                           // objects per 8 x 4 x 16 gridding tile
   size_t bin_part = 0, bin_sum = 0;              // shell-sum partials and totals
   size_t lowk = 0;                               // A_0, A_2, A_4 on |n| < top bk edge
   size_t buf1 = 0, buf2 = 0;                     // inverse-FFT intermediates
@@ -76,14 +75,12 @@ struct Layout {
   size_t total = 0;
 };
 
-// Sorted object records, structure of arrays inside the `sorted` region:
-// packed cell coordinates (int32: cx << 20 | cy << 10 | cz), then 8 arrays of T: fx, fy, fz (fraction of the grid
-// coordinate inside its cell), t0 (signed weight s w), tw (w^2 weight of
-// F_0^w), xhat_x, xhat_y, xhat_z.
-inline size_t sorted_stride(size_t nobj, size_t tbytes) { return ((nobj * tbytes) + 255) & ~(size_t)255; }
-inline size_t sorted_bytes(size_t nobj, size_t tbytes) {
-  return sorted_stride(nobj, 4) + 8 * sorted_stride(nobj, tbytes);
-}
+// Sorted object records: one record of four T per object, ordered by cell
+// (x-major, z fastest): fx, fy, fz (fraction of the grid coordinate inside
+// its cell, in [0, 1)) and t0 (the signed weight s w).  The w^2 weight of
+// F_0^w is t0^2 and the line of sight is rebuilt from the position.
+template <typename T> struct alignas(4 * sizeof(T)) Rec4 { T x, y, z, w; };
+inline size_t sorted_bytes(size_t nobj, size_t tbytes) { return ((nobj * 4 * tbytes) + 255) & ~(size_t)255; }
 
 constexpr int kBinSums = 8;     // per bin: count, sum|k|, S00, S20, S40, S0w, S2w, S4w
 constexpr int kScalars = 4;     // I22, N0, I33, W3

@@ -67,7 +67,7 @@ template <typename TIN>
 __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const TIN *w, const TIN *nbar,
                                                            long long n, int is_ran, long long obj_off,
                                                            GeomArgs g, int *cnt, int *slot, int *cellkey,
-                                                           int *tile_cnt, double *part, unsigned long long *reject) {
+                                                           double *part, unsigned long long *reject) {
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -79,8 +79,6 @@ __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const 
       const int cell = (cx * g.N + cy) * g.N + cz;
       slot[obj_off + i] = atomicAdd(&cnt[cell], 1);
       cellkey[obj_off + i] = cell;
-      // gridding tiles are 8 x 4 x 16 cells
-      atomicAdd(&tile_cnt[((cx >> 3) * (g.N >> 2) + (cy >> 2)) * (g.N >> 4) + (cz >> 4)], 1);
       const double wi = (double)w[i];
       const double w2 = wi * wi, w3 = w2 * wi;
       if (is_ran) {
@@ -103,30 +101,25 @@ template <typename TIN, typename T>
 __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, const TIN *w, long long n, int is_ran,
                                                              long long obj_off, double alpha, GeomArgs g,
                                                              const int *offs, const int *slot, const int *cellkey,
-                                                             int *r_cell, T *r_f, size_t fstride) {
-  T *fx = r_f, *fy = r_f + fstride, *fz = r_f + 2 * fstride, *t0 = r_f + 3 * fstride, *tw = r_f + 4 * fstride,
-    *hx = r_f + 5 * fstride, *hy = r_f + 6 * fstride, *hz = r_f + 7 * fstride;
+                                                             Rec4<T> *rec) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const int cell = cellkey[obj_off + i];
     if (cell < 0) continue;
     const long long dst = (long long)offs[cell] + slot[obj_off + i];
-    const double x = (double)pos[3 * i], y = (double)pos[3 * i + 1], z = (double)pos[3 * i + 2];
-    const double ux = x * g.inv_h, uy = y * g.inv_h, uz = z * g.inv_h;
+    const double ux = (double)pos[3 * i] * g.inv_h, uy = (double)pos[3 * i + 1] * g.inv_h,
+                 uz = (double)pos[3 * i + 2] * g.inv_h;
     const int cx = cell_coord(ux, g.N), cy = cell_coord(uy, g.N), cz = cell_coord(uz, g.N);
     const double one_minus = 1.0 - 1e-15;
     double f0 = ux - cx, f1 = uy - cy, f2 = uz - cz;
     f0 = f0 < 0 ? 0 : (f0 > one_minus ? one_minus : f0);
     f1 = f1 < 0 ? 0 : (f1 > one_minus ? one_minus : f1);
     f2 = f2 < 0 ? 0 : (f2 > one_minus ? one_minus : f2);
-    const double rx = x - g.ox, ry = y - g.oy, rz = z - g.oz;
-    const double ir = 1.0 / sqrt(rx * rx + ry * ry + rz * rz);
     const double wi = (double)w[i];
-    r_cell[dst] = (cx << 20) | (cy << 10) | cz;  // packed cell coordinates (N <= 1024)
-    fx[dst] = (T)f0; fy[dst] = (T)f1; fz[dst] = (T)f2;
-    t0[dst] = (T)(is_ran ? -alpha * wi : wi);
-    tw[dst] = (T)(is_ran ? alpha * alpha * wi * wi : wi * wi);
-    hx[dst] = (T)(rx * ir); hy[dst] = (T)(ry * ir); hz[dst] = (T)(rz * ir);
+    Rec4<T> r;
+    r.x = (T)f0; r.y = (T)f1; r.z = (T)f2;
+    r.w = (T)(is_ran ? -alpha * wi : wi);
+    rec[dst] = r;
   }
 }
 
@@ -227,7 +220,7 @@ static void launch_count(const frsd_catalog *c, int is_ran, long long off, const
   FRSD_TIMED("count", s, hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
                      (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<int>(ws, L.tile_cnt), ws_ptr<double>(ws, L.scal_part),
+                     ws_ptr<double>(ws, L.scal_part),
                      ws_ptr<unsigned long long>(ws, L.reject)));
 }
 
@@ -235,13 +228,10 @@ template <typename TIN, typename T>
 static void launch_scatter(const frsd_catalog *c, int is_ran, long long off, double alpha, const GeomArgs &g,
                            void *ws, const frsd_plan *pl, hipStream_t s) {
   const Layout &L = pl->L;
-  const size_t nobj = (size_t)(pl->p.max_objects > 0 ? pl->p.max_objects : 1);
-  const size_t cstride = sorted_stride(nobj, 4);
-  const size_t fstride = sorted_stride(nobj, sizeof(T)) / sizeof(T);
   FRSD_TIMED("scatter", s, hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
                      (const TIN *)c->pos, (const TIN *)c->w, (long long)c->n, is_ran, off, alpha, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<int>(ws, L.sorted), ws_ptr<T>(ws, L.sorted + cstride), fstride));
+                     ws_ptr<Rec4<T>>(ws, L.sorted)));
 }
 
 template <typename T>
@@ -253,8 +243,6 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N};
 
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0));
-  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(256), 0, s, ws_ptr<int>(ws, L.tile_cnt),
-                                           ncell / 512, 0));
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject)));
   const frsd_catalog *cats[2] = {gal, ran};
   long long off = 0;

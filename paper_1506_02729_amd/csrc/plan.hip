@@ -210,7 +210,6 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.sorted = take(sorted_bytes(nobj, T));
   L.mesh = take(2 * T * NNN * sd.n_slot);
   L.planar = take(2 * T * NNN * sd.n_slot);
-  L.tile_cnt = take(4 * (NNN / 512));
   const int nbins_all = p.pk_nbins + p.bk_nbins;
   L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kBinBlocks);
   L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);
