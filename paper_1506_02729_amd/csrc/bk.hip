@@ -39,7 +39,7 @@ static StageList stage_list(const FftLen &f) {
 }
 
 // z pass: pencils (pair, ix, iy) of the low-k cube, output buf1[pair][ix][iy][z]
-template <typename T, bool IND, int LEN>
+template <typename T, bool IND>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_z(const cplx_t<T> *__restrict__ lowk,
                                                         const int16_t *__restrict__ lut, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_z(const cplx_t<T>
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  const int M = a.M, ld = M + 1, D = a.D, nc = a.nc;
   for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long DD = (long long)D * D;
   const long long npen_all = (long long)a.npair * DD;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_z(const cplx_t<T>
     lds[p * ld + (nz + M) % M] = cmake<C>(ar - bi, ai + br);
   }
   __syncthreads();
-  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
+  lds_fft<C, true, FftTune<T>::threads, FftTune<T>::pn>(lds, ld, M, npen, st, tw);
   C *dst = buf1 + q0 * M;
   for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int p = f / M, e = f - p * M;
@@ -90,14 +90,14 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_z(const cplx_t<T>
 }
 
 // y pass: pencils (pair, ix, z); input buf1[pair][ix][iy][z], output buf2[pair][ix][y][z]
-template <typename T, int LEN>
+template <typename T>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_y(const cplx_t<T> *__restrict__ buf1, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
   using C = cplx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  const int M = a.M, ld = M + 1, D = a.D, nc = a.nc;
   for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long npen_all = (long long)a.npair * D * M;
   const long long q0 = (long long)blockIdx.x * P;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_y(const cplx_t<T>
     lds[p * ld + (iy - nc + M) % M] = buf1[(pix * D + iy) * M + z];
   }
   __syncthreads();
-  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
+  lds_fft<C, true, FftTune<T>::threads, FftTune<T>::pn>(lds, ld, M, npen, st, tw);
   for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int y = f / npen, p = f - y * npen;
     const long long q = q0 + p;
@@ -124,14 +124,14 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_y(const cplx_t<T>
 
 // x pass: pencils (pair, y, z); input buf2[pair][ix][y][z]; output the two
 // real shell fields of the pair, shells[f][x][y][z]
-template <typename T, typename TO, int LEN>
+template <typename T, typename TO>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T> *__restrict__ buf2, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, TO *shells) {
   using C = cplx_t<T>;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + a.M;
-  const int M = LEN ? LEN : a.M, ld = M + 1, D = a.D, nc = a.nc;
+  const int M = a.M, ld = M + 1, D = a.D, nc = a.nc;
   for (int i = threadIdx.x; i < M; i += FftTune<T>::threads) tw[i] = tw_g[i];
   const long long MM = (long long)M * M;
   const long long npen_all = (long long)a.npair * MM;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T>
     lds[p * ld + (ix - nc + M) % M] = buf2[(pair * D + ix) * MM + yz];
   }
   __syncthreads();
-  lds_fft_any<C, true, FftTune<T>::threads, FftTune<T>::pn, LEN>(lds, ld, M, npen, st, tw);
+  lds_fft<C, true, FftTune<T>::threads, FftTune<T>::pn>(lds, ld, M, npen, st, tw);
   const long long MMM = MM * M;
   for (int f = threadIdx.x; f < npen * M; f += FftTune<T>::threads) {
     const int x = f / npen, p = f - x * npen;
@@ -161,8 +161,155 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T>
   }
 }
 
+// Compiled-length shell passes on the register-resident core (fft_pencils);
+// same pencils and buffers as the run-time kernels above.  A pencil element
+// e holds frequency e (e <= nc) or e - M (e >= M - nc) and is zero between.
+template <typename T> struct ShellTune {
+  static constexpr int nt = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int p = sizeof(T) == 4 ? 16 : 8;
+};
+
+__device__ __forceinline__ int band_index(int e, int M, int nc) {
+  return e <= nc ? e + nc : (e >= M - nc ? e - M + nc : -1);
+}
+
+template <typename T, bool IND, int LEN>
+__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T> *__restrict__ lowk,
+                                                                 const int16_t *__restrict__ lut, ShellArgs a,
+                                                                 const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
+  using C = cplx_t<T>;
+  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
+  const int D = a.D, nc = a.nc;
+  const long long DD = (long long)D * D, DDD = DD * D;
+  const long long npen_all = (long long)a.npair * DD;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  fft_pencils<C, LEN, P, NT, true, false>(
+      lds, tw, npen,
+      [&](int p, int e) {
+        const int kz = band_index(e, LEN, nc);
+        if (kz < 0) return cmake<C>(T(0), T(0));
+        const long long q = q0 + p;
+        const int pair = (int)(q / DD);
+        const int colq = (int)(q - (long long)pair * DD);
+        const int ix = colq / D, iy = colq - ix * D;
+        const int nx = ix - nc, ny = iy - nc, nz = kz - nc;
+        const long long m2 = (long long)nx * nx + (long long)ny * ny + (long long)nz * nz;
+        const int b = (m2 > 0 && m2 < a.lut_len) ? lut[m2] : -1;
+        const int fa = 2 * (a.pair0 + pair), fb = fa + 1;
+        T ar = 0, ai = 0, br = 0, bi = 0;
+        if (b >= 0) {
+          if (fa % a.nb == b) {
+            if (IND) ar = T(1);
+            else { const C v = lowk[(fa / a.nb) * DDD + (long long)colq * D + kz]; ar = v.x; ai = v.y; }
+          }
+          if (fb < a.nfield && fb % a.nb == b) {
+            if (IND) br = T(1);
+            else { const C v = lowk[(fb / a.nb) * DDD + (long long)colq * D + kz]; br = v.x; bi = v.y; }
+          }
+        }
+        return cmake<C>(ar - bi, ai + br);  // Z = A + i B
+      },
+      [&](int p, int e, C v) { buf1[(q0 + p) * LEN + e] = v; });
+}
+
+template <typename T, int LEN>
+__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T> *__restrict__ buf1, ShellArgs a,
+                                                                 const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
+  using C = cplx_t<T>;
+  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
+  const int D = a.D, nc = a.nc;
+  const long long npen_all = (long long)a.npair * D * LEN;
+  const long long q0 = (long long)blockIdx.x * P;  // q = (pair * D + ix) * M + z
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  fft_pencils<C, LEN, P, NT, true, true>(
+      lds, tw, npen,
+      [&](int p, int e) {
+        const int iy = band_index(e, LEN, nc);
+        if (iy < 0) return cmake<C>(T(0), T(0));
+        const long long q = q0 + p, pix = q / LEN;
+        return buf1[(pix * D + iy) * LEN + (q - pix * LEN)];
+      },
+      [&](int p, int e, C v) {
+        const long long q = q0 + p, pix = q / LEN;
+        buf2[(pix * LEN + e) * LEN + (q - pix * LEN)] = v;
+      });
+}
+
+template <typename T, typename TO, int LEN>
+__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T> *__restrict__ buf2, ShellArgs a,
+                                                                 const cplx_t<T> *tw_g, TO *shells) {
+  using C = cplx_t<T>;
+  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
+  const int D = a.D, nc = a.nc;
+  constexpr long long MM = (long long)LEN * LEN, MMM = MM * LEN;
+  const long long npen_all = (long long)a.npair * MM;
+  const long long q0 = (long long)blockIdx.x * P;  // q = pair * M^2 + (y * M + z)
+  const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  fft_pencils<C, LEN, P, NT, true, true>(
+      lds, tw, npen,
+      [&](int p, int e) {
+        const int ix = band_index(e, LEN, nc);
+        if (ix < 0) return cmake<C>(T(0), T(0));
+        const long long q = q0 + p, pair = q / MM;
+        return buf2[(pair * D + ix) * MM + (q - pair * MM)];
+      },
+      [&](int p, int e, C v) {
+        const long long q = q0 + p, pair = q / MM, yz = q - pair * MM;
+        const int fa = 2 * (a.pair0 + (int)pair), fb = fa + 1;
+        shells[(long long)fa * MMM + e * MM + yz] = (TO)v.x;
+        if (fb < a.nfield) shells[(long long)fb * MMM + e * MM + yz] = (TO)v.y;
+      });
+}
+
 template <typename T, typename TO, bool IND, int LEN>
-static int shell_pipeline_len(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
+static int shell_pipeline_ct(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
+  using C = cplx_t<T>;
+  const Layout &L = pl->L;
+  ShellArgs a{};
+  a.M = LEN; a.D = pl->D; a.nc = pl->nc_b; a.nb = pl->p.bk_nbins; a.nfield = nfield;
+  a.lut_len = pl->bk_lut_len;
+  const int D = a.D;
+  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  constexpr size_t shmem = fft_pencils_lds<C, LEN, P>();
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z_ct<T, IND, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y_ct<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x_ct<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  const int npairs = (nfield + 1) / 2;
+  for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
+    a.pair0 = p0;
+    a.npair = std::min(kPairBatch, npairs - p0);
+    const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * LEN,
+                    nx = (long long)a.npair * LEN * LEN;
+    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z_ct<T, IND, LEN>), dim3((unsigned)((nz + P - 1) / P)), dim3(NT), shmem, s,
+                       ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, (const C *)tw,
+                       ws_ptr<C>(ws, L.buf1)));
+    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y_ct<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(NT), shmem, s,
+                       ws_ptr<const C>(ws, L.buf1), a, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
+    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x_ct<T, TO, LEN>), dim3((unsigned)((nx + P - 1) / P)), dim3(NT), shmem, s,
+                       ws_ptr<const C>(ws, L.buf2), a, (const C *)tw, shells));
+    FRSD_LAUNCH_CHECK();
+  }
+  return FRSD_OK;
+}
+
+template <typename T, typename TO, bool IND>
+static int shell_pipeline_rt(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
   using C = cplx_t<T>;
   const Layout &L = pl->L;
   ShellArgs a{};
@@ -172,21 +319,21 @@ static int shell_pipeline_len(frsd_plan *pl, void *ws, int nfield, const void *t
   const int P = FftTune<T>::pn / M;
   const StageList st = stage_list(pl->fft_m);
   const size_t shmem = sizeof(C) * ((size_t)M + (size_t)P * (M + 1));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z<T, IND, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z<T, IND>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const int npairs = (nfield + 1) / 2;
   for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
     a.pair0 = p0;
     a.npair = std::min(kPairBatch, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * M,
                     nx = (long long)a.npair * M * M;
-    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND, LEN>), dim3((unsigned)((nz + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
+    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, P, st, (const C *)tw,
                        ws_ptr<C>(ws, L.buf1)));
-    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
+    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y<T>), dim3((unsigned)((ny + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.buf1), a, P, st, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
-    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x<T, TO, LEN>), dim3((unsigned)((nx + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
+    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x<T, TO>), dim3((unsigned)((nx + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,
                        ws_ptr<const C>(ws, L.buf2), a, P, st, (const C *)tw, shells));
     FRSD_LAUNCH_CHECK();
   }
@@ -197,10 +344,10 @@ template <typename T, typename TO, bool IND>
 static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, TO *shells, hipStream_t s) {
   switch (pl->M) {
 #define FRSD_CASE(L) \
-  case L: return shell_pipeline_len<T, TO, IND, L>(pl, ws, nfield, tw, shells, s);
+  case L: return shell_pipeline_ct<T, TO, IND, L>(pl, ws, nfield, tw, shells, s);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
-    default: return shell_pipeline_len<T, TO, IND, 0>(pl, ws, nfield, tw, shells, s);
+    default: return shell_pipeline_rt<T, TO, IND>(pl, ws, nfield, tw, shells, s);
   }
 }
 
@@ -362,15 +509,29 @@ template int run_bk<double>(frsd_plan *, void *, const frsd_bk_out *, hipStream_
 // ---------------------------------------------------------------------------
 // Tables uploaded by frsd_plan_init.
 // ---------------------------------------------------------------------------
+// Stage twiddle table of a length-n transform (radix schedule of
+// make_fft_len): for every stage s > 0 with Ns = product of the earlier
+// radices, W_{Ns R}^{r k} = exp(-2 pi i r k / (Ns R)) at (Ns - 1) + k (R - 1)
+// + (r - 1), k < Ns, 1 <= r < R; the entries fill [R_0 - 1, n - 1).
 template <typename T>
 static std::vector<T> twiddles(int n) {
-  // W_n^e = exp(-2 pi i e / n), interleaved (re, im)
-  std::vector<T> t(2 * (size_t)n);
+  std::vector<T> t(2 * (size_t)n, T(0));
+  FftLen f;
+  if (!make_fft_len(n, &f)) return t;
   const long double two_pi = 6.283185307179586476925286766559005768L;
-  for (int e = 0; e < n; ++e) {
-    const long double a = two_pi * (long double)e / (long double)n;
-    t[2 * e] = (T)cosl(a);
-    t[2 * e + 1] = (T)(-sinl(a));
+  int ns = 1;
+  for (int s = 0; s < f.nstage; ++s) {
+    const int R = f.radix[s];
+    if (s > 0) {
+      for (int k = 0; k < ns; ++k)
+        for (int r = 1; r < R; ++r) {
+          const size_t idx = (size_t)(ns - 1) + (size_t)k * (R - 1) + (r - 1);
+          const long double a = two_pi * (long double)(r * k) / (long double)(ns * R);
+          t[2 * idx] = (T)cosl(a);
+          t[2 * idx + 1] = (T)(-sinl(a));
+        }
+    }
+    ns *= R;
   }
   return t;
 }

@@ -102,14 +102,15 @@ template <typename C, int R, bool INV> __device__ __forceinline__ void dftR(C *v
 // W_{Ns R}^{r (j mod Ns)}, does an R-point DFT and writes the results to
 // (j / Ns) Ns R + (j mod Ns) + r Ns.  All reads of the stage complete
 // (barrier) before any write, so the stage runs in place.
-// tw holds W_n^e = exp(-2 pi i e / n), e in [0, n), in LDS.
+// tw is the stage twiddle table (fill order of the host's stage_twiddles):
+// W_{Ns R}^{r k} at (Ns - 1) + k (R - 1) + (r - 1), for every stage but the
+// first, in LDS.
 // ---------------------------------------------------------------------------
 template <typename C, int R, bool INV, int THREADS, int PN>
 __device__ __forceinline__ void stockham_stage(C *lds, int ld, int n, int P, int Ns, const C *tw) {
   constexpr int MAXB = (PN + R * THREADS - 1) / (R * THREADS);
   const int nbf = n / R;
   const int total = P * nbf;
-  const int tstride = n / (Ns * R);
   C v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
@@ -122,11 +123,9 @@ __device__ __forceinline__ void stockham_stage(C *lds, int ld, int n, int P, int
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
       if (Ns > 1) {
+        const C *w = tw + (Ns - 1) + k * (R - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * tstride];
-          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
-        }
+        for (int r = 1; r < R; ++r) v[q][r] = INV ? cmulc(v[q][r], w[r - 1]) : cmul(v[q][r], w[r - 1]);
       }
       dftR<C, R, INV>(v[q]);
     }
@@ -168,65 +167,6 @@ constexpr int ct_nstage(int len) {
   return s;
 }
 
-// One Stockham stage with everything known at compile time except the
-// number of pencils P.
-template <typename C, int R, bool INV, int THREADS, int PN, int LEN, int NS>
-__device__ __forceinline__ void stockham_stage_ct(C *lds, int ld, int P, const C *tw) {
-  constexpr int MAXB = (PN + R * THREADS - 1) / (R * THREADS);
-  constexpr int nbf = LEN / R;
-  constexpr int tstride = LEN / (NS * R);
-  const int total = P * nbf;
-  C v[MAXB][R];
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + q * THREADS;
-    if (b < total) {
-      const int p = b / nbf;
-      const int j = b - p * nbf;
-      const int k = j % NS;
-      const C *src = lds + p * ld + j;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = src[r * nbf];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * tstride];
-          v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
-        }
-      }
-      dftR<C, R, INV>(v[q]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int b = threadIdx.x + q * THREADS;
-    if (b < total) {
-      const int p = b / nbf;
-      const int j = b - p * nbf;
-      const int k = j % NS;
-      C *dst = lds + p * ld + (j / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename C, bool INV, int THREADS, int PN, int LEN, int S = 0, int NS = 1>
-__device__ __forceinline__ void lds_fft_ct(C *lds, int ld, int P, const C *tw) {
-  if constexpr (S < ct_nstage(LEN)) {
-    constexpr int R = ct_radix(LEN, S);
-    stockham_stage_ct<C, R, INV, THREADS, PN, LEN, NS>(lds, ld, P, tw);
-    lds_fft_ct<C, INV, THREADS, PN, LEN, S + 1, NS * R>(lds, ld, P, tw);
-  }
-}
-
-// Transform of P pencils of length n (LEN = n at compile time, or 0 for a
-// run-time length with the stage list st).
-template <typename C, bool INV, int THREADS, int PN, int LEN>
-__device__ __forceinline__ void lds_fft_any(C *lds, int ld, int n, int P, const StageList &st, const C *tw);
-
 // Full transform of P pencils in LDS.  Caller synchronises before the call
 // (data loaded) and may read results right after it returns.
 template <typename C, bool INV, int THREADS, int PN>
@@ -242,10 +182,90 @@ __device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const
   }
 }
 
-template <typename C, bool INV, int THREADS, int PN, int LEN>
-__device__ __forceinline__ void lds_fft_any(C *lds, int ld, int n, int P, const StageList &st, const C *tw) {
-  if constexpr (LEN > 0) lds_fft_ct<C, INV, THREADS, PN, LEN>(lds, ld, P, tw);
-  else lds_fft<C, INV, THREADS, PN>(lds, ld, n, P, st, tw);
+// ---------------------------------------------------------------------------
+// Register-resident Stockham transform of P pencils of length LEN (radix
+// schedule ct_radix).  Each stage keeps its butterflies' operands in
+// registers; LDS is used only to exchange data between stages, with one pad
+// slot per 8 elements and an odd pencil stride so that the strided stage
+// writes and the pencil-strided accesses spread over the banks.  The first
+// stage reads its operands straight from global memory through load(p, e)
+// and the last stage writes its results through store(p, e, v), so a pass
+// touches LDS 4 times per element for three stages.  With PFAST, the first
+// and last stages give consecutive threads consecutive pencils (global rows
+// strided by pencil, e.g. y and x passes over z columns); otherwise
+// consecutive elements (contiguous rows).  load / store are called only for
+// pencils p < npen.  twst is the stage twiddle table of fill_stage_twiddles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ constexpr int fpad(int i) { return i + (i >> 3); }
+template <int LEN> constexpr int fft_ld() { return LEN + LEN / 8 + 1; }
+
+template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, int STAGE, int NS, class Load, class Store>
+__device__ __forceinline__ void fft_stage(C *lds, const C *twst, int npen, Load &load, Store &store) {
+  constexpr int S = ct_nstage(LEN);
+  constexpr int R = ct_radix(LEN, STAGE);
+  constexpr bool FIRST = STAGE == 0, LAST = STAGE == S - 1;
+  constexpr int NBF = LEN / R;
+  constexpr int TOT = P * NBF;
+  constexpr int MAXB = (TOT + NT - 1) / NT;
+  constexpr int LD = fft_ld<LEN>();
+  constexpr bool PMAP = (FIRST || LAST) && PFAST;
+  C v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if (b < TOT) {
+      const int p = PMAP ? b % P : b / NBF;
+      const int j = PMAP ? b / P : b % NBF;
+      if constexpr (FIRST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = p < npen ? load(p, j + r * NBF) : cmake<C>(0, 0);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = lds[p * LD + fpad(j + r * NBF)];
+      }
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+        const C *w = twst + (NS - 1) + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = INV ? cmulc(v[q][r], w[r - 1]) : cmul(v[q][r], w[r - 1]);
+      }
+      dftR<C, R, INV>(v[q]);
+    }
+  }
+  if constexpr (!FIRST) __syncthreads();  // every read of the stage precedes the in-place writes
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if (b < TOT) {
+      const int p = PMAP ? b % P : b / NBF;
+      const int j = PMAP ? b / P : b % NBF;
+      if constexpr (LAST) {
+        if (p < npen) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) store(p, j + r * NS, v[q][r]);
+        }
+      } else {
+        const int base = (j / NS) * NS * R + j % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[p * LD + fpad(base + r * NS)] = v[q][r];
+      }
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+    fft_stage<C, LEN, P, NT, INV, PFAST, STAGE + 1, NS * R>(lds, twst, npen, load, store);
+  }
+}
+
+template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, class Load, class Store>
+__device__ __forceinline__ void fft_pencils(C *lds, const C *twst, int npen, Load &&load, Store &&store) {
+  static_assert(ct_nstage(LEN) >= 2, "length too short");
+  fft_stage<C, LEN, P, NT, INV, PFAST, 0, 1>(lds, twst, npen, load, store);
+}
+
+// LDS bytes of fft_pencils: stage twiddles (LEN) + P padded pencils.
+template <typename C, int LEN, int P> constexpr size_t fft_pencils_lds() {
+  return sizeof(C) * ((size_t)LEN + (size_t)P * fft_ld<LEN>());
 }
 
 // Pencil batching of the LDS transforms: P = pn / n pencils per workgroup.

@@ -43,18 +43,17 @@ __device__ __forceinline__ void column_block(int b, int P, int N, const Keep &k,
   }
 }
 
-// AXIS 2 reads the planar real arrays `planar` (re, im of mesh b at arrays
-// 2b, 2b+1) and writes `data`; AXIS 1 and 0 work in place on `data`.
+// Run-time length kernel (lengths without a compiled kernel).  AXIS 2
+// reads the planar real arrays `planar` (re, im of mesh b at arrays 2b,
+// 2b+1) and writes `data`; AXIS 1 and 0 work in place on `data`.
 // Grid: AXIS 2 (N^2 / P rows, batch); AXIS 1 (x * (nba + nbb) + column
 // block, batch); AXIS 0 (kept y * (nba + nbb) + column block, batch).
-template <typename T, int AXIS, int LEN>
-__global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *data, const T *planar, int n_rt, int P_rt,
+template <typename T, int AXIS>
+__global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *data, const T *planar, int N, int P,
                                                            StageList st, const cplx_t<T> *tw_g,
                                                            long long batch_stride, Keep keep) {
   using C = cplx_t<T>;
   constexpr int NT = FftTune<T>::threads;
-  const int N = LEN ? LEN : n_rt;
-  const int P = LEN ? FftTune<T>::pn / LEN : P_rt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + N;
@@ -65,7 +64,6 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
   const long long NN = (long long)N * N;
 
   if (AXIS == 2) {
-    // pencil q: row q of length N, contiguous in both planar arrays
     const long long q0 = (long long)blockIdx.x * P;
     const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
     const int tot = npen * N;
@@ -76,7 +74,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
       lds[p * ld + e] = cmake<C>(re[f], im[f]);
     }
     __syncthreads();
-    lds_fft_any<C, false, NT, FftTune<T>::pn, LEN>(lds, ld, N, npen, st, tw);
+    lds_fft<C, false, NT, FftTune<T>::pn>(lds, ld, N, npen, st, tw);
     C *dst = mesh + q0 * N;
     for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
@@ -85,7 +83,6 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
     return;
   }
 
-  // AXIS 1: pencil (x, z), element stride N; AXIS 0: pencil (y, z), stride N^2
   const int nzb = keep.nba + keep.nbb;
   const int outer_i = blockIdx.x / nzb;
   int z0, npen;
@@ -98,11 +95,75 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
     if (p < npen) lds[p * ld + e] = col[e * es + p];
   }
   __syncthreads();
-  lds_fft_any<C, false, NT, FftTune<T>::pn, LEN>(lds, ld, N, npen, st, tw);
+  lds_fft<C, false, NT, FftTune<T>::pn>(lds, ld, N, npen, st, tw);
   for (int f = threadIdx.x; f < P * N; f += NT) {
     const int e = f / P, p = f - e * P;
     if (p < npen && kept(e, N, keep)) col[e * es + p] = lds[p * ld + e];
   }
+}
+
+// Compiled-length kernels on the register-resident core (fft_pencils).
+// Row pass (z): P_ROW contiguous rows per workgroup.  Column passes (y, x):
+// P_COL consecutive z columns per workgroup, so every global access is a run
+// of P_COL complex values.
+template <typename T> struct FwdTune {
+  static constexpr int nt_row = 256, nt_col = sizeof(T) == 4 ? 512 : 256;
+  static constexpr int row_elems = sizeof(T) == 4 ? 4096 : 2048;  // rows per workgroup x length
+  static constexpr int p_col = sizeof(T) == 4 ? 16 : 8;
+};
+template <typename T, int LEN> constexpr int p_row() {
+  return FwdTune<T>::row_elems / LEN > 0 ? FwdTune<T>::row_elems / LEN : 1;
+}
+
+template <typename T, int LEN>
+__global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data, const T *planar,
+                                                                const cplx_t<T> *tw_g, long long batch_stride,
+                                                                Keep keep) {
+  using C = cplx_t<T>;
+  constexpr int P = p_row<T, LEN>(), NT = FwdTune<T>::nt_row;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
+  constexpr long long NN = (long long)LEN * LEN;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
+  const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * LEN;
+  const T *im = re + batch_stride;
+  C *dst = data + (long long)blockIdx.y * batch_stride + q0 * LEN;
+  fft_pencils<C, LEN, P, NT, false, false>(
+      lds, tw, npen, [&](int p, int e) { return cmake<C>(re[p * LEN + e], im[p * LEN + e]); },
+      [&](int p, int e, C v) {
+        if (kept(e, LEN, keep)) dst[p * LEN + e] = v;
+      });
+}
+
+template <typename T, int AXIS, int LEN>
+__global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data, const cplx_t<T> *tw_g,
+                                                                long long batch_stride, Keep keep) {
+  using C = cplx_t<T>;
+  constexpr int P = FwdTune<T>::p_col, NT = FwdTune<T>::nt_col;
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
+  constexpr long long NN = (long long)LEN * LEN;
+  const int nzb = keep.nba + keep.nbb;
+  const int outer_i = blockIdx.x / nzb;
+  int z0, npen;
+  column_block(blockIdx.x - outer_i * nzb, P, LEN, keep, z0, npen);
+  const int outer = (AXIS == 1) ? outer_i : (outer_i < keep.ka ? outer_i : LEN - keep.kb + (outer_i - keep.ka));
+  constexpr long long es = (AXIS == 1) ? LEN : NN;
+  C *col = data + (long long)blockIdx.y * batch_stride +
+           ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
+  // in place: every load happens in the first stage, every store in the last
+  fft_pencils<C, LEN, P, NT, false, true>(
+      lds, tw, npen, [&](int p, int e) { return col[e * es + p]; },
+      [&](int p, int e, C v) {
+        if (kept(e, LEN, keep)) col[e * es + p] = v;
+      });
 }
 
 static StageList stages_of(const FftLen &f) {
@@ -112,13 +173,7 @@ static StageList stages_of(const FftLen &f) {
   return s;
 }
 
-template <typename T, int LEN>
-static int fft3d_forward_len(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch,
-                             int nmax, hipStream_t s) {
-  using C = cplx_t<T>;
-  const int N = f.n;
-  const int P = FftTune<T>::pn / N;
-  const long long NN = (long long)N * N;
+static Keep make_keep(int N, int P, int nmax) {
   // kept runs [0, nmax] and [N - nmax, N), widened to whole blocks of P columns
   Keep k{};
   k.ka = std::min(N, (nmax + 1 + P - 1) / P * P);
@@ -127,20 +182,55 @@ static int fft3d_forward_len(const FftLen &f, const void *tw, const void *planar
   if (k.ka + k.kb >= N || 2 * nmax + 1 >= N) { k.ka = N; k.kb = 0; }
   k.nba = (k.ka + P - 1) / P;
   k.nbb = (k.kb + P - 1) / P;
+  return k;
+}
+
+template <typename T, int LEN>
+static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, hipStream_t s) {
+  using C = cplx_t<T>;
+  constexpr int PR = p_row<T, LEN>(), PC = FwdTune<T>::p_col;
+  constexpr long long NN = (long long)LEN * LEN;
+  const Keep k = make_keep(LEN, PC, nmax);
+  const unsigned nzb = (unsigned)(k.nba + k.nbb);
+  constexpr size_t sh_row = fft_pencils_lds<C, LEN, PR>(), sh_col = fft_pencils_lds<C, LEN, PC>();
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_row<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_row));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
+  const long long bs = NN * LEN;
+  const dim3 gz((unsigned)((NN + PR - 1) / PR), n_batch), gy((unsigned)LEN * nzb, n_batch),
+      gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
+  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_row<T, LEN>), gz, dim3(FwdTune<T>::nt_row), sh_row, s, (C *)mesh,
+                                            (const T *)planar, (const C *)tw, bs, k));
+  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_col<T, 1, LEN>), gy, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
+                                            (const C *)tw, bs, k));
+  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_col<T, 0, LEN>), gx, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
+                                            (const C *)tw, bs, k));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+template <typename T>
+static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+                            hipStream_t s) {
+  using C = cplx_t<T>;
+  const int N = f.n;
+  const int P = FftTune<T>::pn / N;
+  const long long NN = (long long)N * N;
+  const Keep k = make_keep(N, P, nmax);
   const unsigned nzb = (unsigned)(k.nba + k.nbb);
   const size_t shmem = sizeof(C) * ((size_t)N + (size_t)P * (N + 1));
   const StageList st = stages_of(f);
   const long long bs = NN * N;
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 2, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const dim3 gz((unsigned)((NN + P - 1) / P), n_batch), gy((unsigned)N * nzb, n_batch),
       gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
-  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2, LEN>), gz, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+  FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2>), gz, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
                                             (const T *)planar, N, P, st, (const C *)tw, bs, k));
-  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1, LEN>), gy, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+  FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1>), gy, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
                                             (const T *)planar, N, P, st, (const C *)tw, bs, k));
-  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0, LEN>), gx, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
+  FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0>), gx, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
                                             (const T *)planar, N, P, st, (const C *)tw, bs, k));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
@@ -151,10 +241,10 @@ int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mes
                   hipStream_t s) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_len<T, L>(f, tw, planar, mesh, n_batch, nmax, s);
+  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, s);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
-    default: return fft3d_forward_len<T, 0>(f, tw, planar, mesh, n_batch, nmax, s);
+    default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, s);
   }
 }
 
