@@ -33,7 +33,7 @@ namespace frsd {
 constexpr int kBX = 4, kBY = 8, kBZ = 16;
 constexpr int kGThreads = kBX * kBY * kBZ;  // one (main, twin) node pair per thread
 constexpr int kGCellsMax = 1536;            // cells of the grown block (77 columns x 19 for TSC)
-constexpr int kGStageBytes = 114688;        // staged object records
+constexpr int kGStageBytes = 65536;         // staged object records (two workgroups per CU)
 
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
@@ -205,8 +205,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) trips = max(trips, __shfl_xor(trips, o, 64));
     int wi = 0, j = 0, je = 0;
-#pragma unroll 1
-    for (int t = 0; t < trips; ++t) {
+    auto advance = [&]() {
 #pragma unroll 1
       while (j >= je && wi < RW * RW) {
         const int e = ((lx + wi / RW) * CY + (ly + wi % RW)) * CZ + lz;
@@ -214,10 +213,19 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
         je = min(cst[e + RW], s1) - s0;
         ++wi;
       }
-      const bool valid = j < je;
-      Rec4<T> r = st[valid ? j : 0];
-      if (!valid) r.w = T(0);
-      j += valid ? 1 : 0;
+    };
+    advance();
+    bool nvalid = j < je;
+    Rec4<T> nr = st[nvalid ? j : 0];
+#pragma unroll 1
+    for (int t = 0; t < trips; ++t) {
+      // the next record is read while this one is processed
+      Rec4<T> r = nr;
+      if (!nvalid) r.w = T(0);
+      j += nvalid ? 1 : 0;
+      advance();
+      nvalid = j < je;
+      nr = st[nvalid ? j : 0];
       const T dx = r.x - fx, dy = r.y - fy, dz = r.z - fz;
       const T sm = r.w * (kernel_w<T, P>(dx) * kernel_w<T, P>(dy) * kernel_w<T, P>(dz));
       T stw = T(0);
