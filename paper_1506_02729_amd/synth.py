@@ -85,7 +85,7 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
                    n_ran: int = 40_000_000, f: float = 0.7, seed: int = 2000,
                    r_min: float = 1150.0, r_max: float = 1750.0, cap_deg: float = 60.0,
                    observer=(-400.0, 1750.0, 1750.0), p_fkp: float = 1.0e4,
-                   ran_seed: int | None = None):
+                   ran_seed: int | None = None, make_randoms: bool = True):
     """Lognormal redshift-space mock in a shell x cap survey.
 
     G is Gaussian on an n_mesh^3 grid with power P(k) (``power_law_bump``);
@@ -96,6 +96,8 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     uniformly inside the cell, displaced, and kept if s lies in the survey.
     Randoms are uniform in r^3 and in solid angle over the cap.
     Constant nbar = n_gal / V_survey and w = 1 / (1 + nbar P_FKP).
+    With make_randoms=False the random catalogue is returned empty (alpha is
+    still N_g / n_ran, for a random catalogue drawn separately).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N, L = n_mesh, box
@@ -150,9 +152,12 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     ng = len(gpos)
     gal = {"pos": gpos, "w": np.full(ng, w), "nbar": np.full(ng, nbar)}
 
-    rr = np.random.Generator(np.random.PCG64(seed + 500 if ran_seed is None else ran_seed))
-    ran = {"pos": _cap_randoms(rr, int(n_ran), obs, r_min, r_max, cos_max),
-           "w": np.full(int(n_ran), w), "nbar": np.full(int(n_ran), nbar)}
+    if make_randoms:
+        rr = np.random.Generator(np.random.PCG64(seed + 500 if ran_seed is None else ran_seed))
+        ran = {"pos": _cap_randoms(rr, int(n_ran), obs, r_min, r_max, cos_max),
+               "w": np.full(int(n_ran), w), "nbar": np.full(int(n_ran), nbar)}
+    else:
+        ran = {"pos": np.zeros((0, 3)), "w": np.zeros(0), "nbar": np.zeros(0)}
     alpha = ng / float(n_ran)
     meta = {"nbar": nbar, "w": w, "sigma2": sigma2, "volume": vol, "n_gal": ng}
     return gal, ran, alpha, tuple(obs.tolist()), meta
@@ -216,3 +221,15 @@ def catalog_digest(gal: dict, ran: dict, alpha: float, observer) -> str:
             h.update(np.ascontiguousarray(cat[key], dtype=np.float64).tobytes())
     h.update(np.asarray([alpha, *observer], dtype=np.float64).tobytes())
     return h.hexdigest()
+
+
+def lognormal_pool(n_mocks: int, seed0: int = 2000, **kw):
+    """Pool of mocks sharing one random catalogue (that of mock 0, seed0 +
+    500), as a covariance run does: galaxy catalogues from seeds seed0 + 10 i.
+    Returns a list of (gal, alpha) and the shared (ran, observer)."""
+    gal0, ran, alpha0, obs, _ = lognormal_mock(seed=seed0, **kw)
+    out = [(gal0, alpha0)]
+    for i in range(1, n_mocks):
+        g, _, a, _, _ = lognormal_mock(seed=seed0 + 10 * i, ran_seed=seed0 + 500, make_randoms=False, **kw)
+        out.append((g, a))
+    return out, ran, obs
