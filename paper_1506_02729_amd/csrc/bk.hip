@@ -123,7 +123,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_y(const cplx_t<T>
 }
 
 // x pass: pencils (pair, y, z); input buf2[pair][ix][y][z]; output the two
-// real shell fields of the pair, shells[f][x][y][z]
+// real shell fields of the pair, shells[f][y][z][x] (the contraction only needs one cell order for all fields)
 template <typename T, typename TO>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T> *__restrict__ buf2, ShellArgs a, int P,
                                                         StageList st, const cplx_t<T> *tw_g, TO *shells) {
@@ -156,8 +156,8 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T>
     const long long yz = q - pair * MM;
     const int fa = 2 * (a.pair0 + (int)pair), fb = fa + 1;
     const C v = lds[p * ld + x];
-    shells[(long long)fa * MMM + x * MM + yz] = (TO)v.x;
-    if (fb < a.nfield) shells[(long long)fb * MMM + x * MM + yz] = (TO)v.y;
+    shells[(long long)fa * MMM + yz * M + x] = (TO)v.x;
+    if (fb < a.nfield) shells[(long long)fb * MMM + yz * M + x] = (TO)v.y;
   }
 }
 
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T>
   const long long npen_all = (long long)a.npair * MM;
   const long long q0 = (long long)blockIdx.x * P;  // q = pair * M^2 + (y * M + z)
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  fft_pencils<C, LEN, P, NT, true, true>(
+  // output cell order [y][z][x] (x fastest): contiguous rows of M values
+  fft_pencils<C, LEN, P, NT, true, true, false>(
       lds, tw, npen,
       [&](int p, int e) {
         const int ix = band_index(e, LEN, nc);
@@ -272,8 +273,8 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T>
       [&](int p, int e, C v) {
         const long long q = q0 + p, pair = q / MM, yz = q - pair * MM;
         const int fa = 2 * (a.pair0 + (int)pair), fb = fa + 1;
-        shells[(long long)fa * MMM + e * MM + yz] = (TO)v.x;
-        if (fb < a.nfield) shells[(long long)fb * MMM + e * MM + yz] = (TO)v.y;
+        shells[(long long)fa * MMM + yz * LEN + e] = (TO)v.x;
+        if (fb < a.nfield) shells[(long long)fb * MMM + yz * LEN + e] = (TO)v.y;
       });
 }
 

@@ -190,16 +190,17 @@ __device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const
 // writes and the pencil-strided accesses spread over the banks.  The first
 // stage reads its operands straight from global memory through load(p, e)
 // and the last stage writes its results through store(p, e, v), so a pass
-// touches LDS 4 times per element for three stages.  With PFAST, the first
-// and last stages give consecutive threads consecutive pencils (global rows
-// strided by pencil, e.g. y and x passes over z columns); otherwise
-// consecutive elements (contiguous rows).  load / store are called only for
+// touches LDS 4 times per element for three stages.  With PFAST (first
+// stage) / PFAST_OUT (last stage), consecutive threads take consecutive
+// pencils (global rows strided by pencil, e.g. y and x passes over z
+// columns); otherwise consecutive elements (contiguous rows).  load / store are called only for
 // pencils p < npen.  twst is the stage twiddle table of fill_stage_twiddles.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ constexpr int fpad(int i) { return i + (i >> 3); }
 template <int LEN> constexpr int fft_ld() { return LEN + LEN / 8 + 1; }
 
-template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, int STAGE, int NS, class Load, class Store>
+template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, bool PFAST_OUT, int STAGE, int NS, class Load,
+          class Store>
 __device__ __forceinline__ void fft_stage(C *lds, const C *twst, int npen, Load &load, Store &store) {
   constexpr int S = ct_nstage(LEN);
   constexpr int R = ct_radix(LEN, STAGE);
@@ -208,7 +209,7 @@ __device__ __forceinline__ void fft_stage(C *lds, const C *twst, int npen, Load 
   constexpr int TOT = P * NBF;
   constexpr int MAXB = (TOT + NT - 1) / NT;
   constexpr int LD = fft_ld<LEN>();
-  constexpr bool PMAP = (FIRST || LAST) && PFAST;
+  constexpr bool PMAP = FIRST ? PFAST : (LAST ? PFAST_OUT : false);
   C v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
@@ -253,14 +254,14 @@ __device__ __forceinline__ void fft_stage(C *lds, const C *twst, int npen, Load 
   }
   if constexpr (!LAST) {
     __syncthreads();
-    fft_stage<C, LEN, P, NT, INV, PFAST, STAGE + 1, NS * R>(lds, twst, npen, load, store);
+    fft_stage<C, LEN, P, NT, INV, PFAST, PFAST_OUT, STAGE + 1, NS * R>(lds, twst, npen, load, store);
   }
 }
 
-template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, class Load, class Store>
+template <typename C, int LEN, int P, int NT, bool INV, bool PFAST, bool PFAST_OUT = PFAST, class Load, class Store>
 __device__ __forceinline__ void fft_pencils(C *lds, const C *twst, int npen, Load &&load, Store &&store) {
   static_assert(ct_nstage(LEN) >= 2, "length too short");
-  fft_stage<C, LEN, P, NT, INV, PFAST, 0, 1>(lds, twst, npen, load, store);
+  fft_stage<C, LEN, P, NT, INV, PFAST, PFAST_OUT, 0, 1>(lds, twst, npen, load, store);
 }
 
 // LDS bytes of fft_pencils: stage twiddles (LEN) + P padded pencils.

@@ -69,14 +69,16 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                float *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) float U[kXMaxB][kXUPad];
+  __shared__ __attribute__((aligned(16))) float U[kXMaxB + 1][kXUPad];  // row kXMaxB stays zero
   __shared__ __attribute__((aligned(16))) __bf16 Bh[kXCols][kXBPad];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[kXCols][kXBPad];
-  __shared__ uint16_t prs[kXMaxRows];  // b2 | b3 << 8 of each row, 0xffff past the last pair
+  __shared__ uint16_t prs[kXMaxRows];  // b2 | b3 << 8 of each row
   __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform (scalar) so the job table is read with scalar loads and the
+  // row-tile test below is a scalar branch
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15;     // row (A) / column (B) inside a 16-tile
   const int lk = lane >> 4;     // 8-wide k group of the 32-wide k-step
   const int nj = jobs.nj[wave];
@@ -85,11 +87,13 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 #pragma unroll
   for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
+  // rows past the last pair read the zero row of U
   for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
-    uint16_t v = 0xffff;
+    uint16_t v = (uint16_t)(kXMaxB | (kXMaxB << 8));
     if (i < a.npair) { const int2 p = pairs[i]; v = (uint16_t)(p.x | (p.y << 8)); }
     prs[i] = v;
   }
+  for (int i = threadIdx.x; i < kXUPad; i += kXThreads) U[kXMaxB][i] = 0.f;
   for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
     const int l = i / a.nb, b1 = i - l * a.nb;
     cmap[i] = (uint8_t)(b1 * a.n_ell + l);
@@ -161,8 +165,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
           if (rt != cur_rt) {
             cur_rt = rt;
             const unsigned pr = prs[rt * 16 + li];
-            const bool ok = pr != 0xffffu;
-            const int b2 = ok ? (int)(pr & 0xff) : 0, b3 = ok ? (int)(pr >> 8) : 0;
+            const int b2 = (int)(pr & 0xff), b3 = (int)(pr >> 8);
             const float4 x0 = *reinterpret_cast<const float4 *>(&U[b2][k0]);
             const float4 x1 = *reinterpret_cast<const float4 *>(&U[b2][k0 + 4]);
             const float4 y0 = *reinterpret_cast<const float4 *>(&U[b3][k0]);
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
               __bf16 h, lo;
-              split_bf16(ok ? v[e] : 0.f, h, lo);
+              split_bf16(v[e], h, lo);
               ah[e] = h;
               al[e] = lo;
             }
