@@ -20,6 +20,7 @@
 // w owns up to 8 output tiles ("jobs", sorted by row tile) in 32 accumulator
 // registers.  Every workgroup covers all jobs for its own contiguous range
 // of cells.
+#include <algorithm>
 #include <vector>
 
 #include "device.h"
@@ -83,9 +84,14 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   const int lk = lane >> 4;     // 8-wide k group of the 32-wide k-step
   const int nj = jobs.nj[wave];
 
-  f32x4_t acc[kXMaxJobs];
+  // hi*hi products in acc, the two cross terms in acc2: two independent
+  // accumulation chains per tile keep consecutive MFMAs independent
+  f32x4_t acc[kXMaxJobs], acc2[kXMaxJobs];
 #pragma unroll
-  for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < kXMaxJobs; ++j) {
+    acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    acc2[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  }
 
   // rows past the last pair read the zero row of U
   for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
@@ -183,8 +189,8 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
           const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(&Bh[ct * 16 + li][k0]);
           const bf16x8_t bl = *reinterpret_cast<const bf16x8_t *>(&Bl[ct * 16 + li][k0]);
           acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc2[j], 0, 0, 0);
+          acc2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc2[j], 0, 0, 0);
         }
       }
     }
@@ -197,7 +203,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
     if (j < nj) {
       float *t = out + (long long)(jobs.first[wave] + j) * 256;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) t[(4 * lk + v) * 16 + li] = acc[j][v];
+      for (int v = 0; v < 4; ++v) t[(4 * lk + v) * 16 + li] = acc[j][v] + acc2[j][v];
     }
   }
 }
@@ -243,17 +249,65 @@ static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *ti
   if (n > kXWaves * kXMaxJobs) return false;
   *jobs = XJobs{};
   tile_job->assign((size_t)kXMaxRows / 16 * 7, (int16_t)-1);
-  // n / kXWaves jobs per wave, one more for the first n % kXWaves waves
-  const int base = n / kXWaves, extra = n % kXWaves;
-  for (int w = 0; w < kXWaves; ++w) {
-    const int a = w * base + std::min(w, extra), b = a + base + (w < extra ? 1 : 0);
-    jobs->first[w] = a;
-    jobs->nj[w] = b - a;
-    for (int j = a; j < b; ++j) {
-      jobs->rt[w][j - a] = (uint8_t)list[j].first;
-      jobs->ct[w][j - a] = (uint8_t)list[j].second;
-      (*tile_job)[list[j].first * 7 + list[j].second] = (int16_t)j;
+
+  // Preferred: whole row tiles per wavefront (each row tile's pair products
+  // formed by one wavefront only), balanced over the four SIMDs (wavefront w
+  // runs on SIMD w % 4) by longest-first placement; the cost of a row tile
+  // is 3 MFMAs per column tile plus about 3 MFMA-times of VALU for its pair
+  // products.
+  std::vector<std::vector<std::pair<int, int>>> wl(kXWaves);
+  {
+    std::vector<std::vector<std::pair<int, int>>> groups;
+    for (const auto &e : list) {
+      if (groups.empty() || groups.back()[0].first != e.first) groups.emplace_back();
+      groups.back().push_back(e);
     }
+    std::vector<int> order(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) order[g] = (int)g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return groups[a].size() > groups[b].size(); });
+    double simd_cost[4] = {0, 0, 0, 0};
+    bool ok = true;
+    for (int g : order) {
+      const int len = (int)groups[g].size();
+      int best_w = -1;
+      double best_c = 1e300;
+      for (int sidx = 0; sidx < 4; ++sidx) {
+        int w_fit = -1;
+        for (int k = 0; k < kXWaves / 4; ++k) {
+          const int w = 4 * k + sidx;
+          if ((int)wl[w].size() + len <= kXMaxJobs && (w_fit < 0 || wl[w].size() < wl[w_fit].size())) w_fit = w;
+        }
+        if (w_fit >= 0 && simd_cost[sidx] < best_c) { best_c = simd_cost[sidx]; best_w = w_fit; }
+      }
+      if (best_w < 0) { ok = false; break; }
+      for (const auto &e : groups[g]) wl[best_w].push_back(e);
+      simd_cost[best_w % 4] += 3.0 * len + 3.0;
+    }
+    if (ok)
+      for (auto &w : wl) std::sort(w.begin(), w.end());
+    else {
+      // fallback: contiguous runs of the sorted list
+      for (auto &w : wl) w.clear();
+      const int base = n / kXWaves, extra = n % kXWaves;
+      int a = 0;
+      for (int w = 0; w < kXWaves; ++w) {
+        const int b = a + base + (w < extra ? 1 : 0);
+        for (int j = a; j < b; ++j) wl[w].push_back(list[j]);
+        a = b;
+      }
+    }
+  }
+  int first = 0;
+  for (int w = 0; w < kXWaves; ++w) {
+    jobs->first[w] = first;
+    jobs->nj[w] = (int)wl[w].size();
+    for (int j = 0; j < (int)wl[w].size(); ++j) {
+      jobs->rt[w][j] = (uint8_t)wl[w][j].first;
+      jobs->ct[w][j] = (uint8_t)wl[w][j].second;
+      (*tile_job)[wl[w][j].first * 7 + wl[w][j].second] = (int16_t)(first + j);
+    }
+    first += (int)wl[w].size();
   }
   *njobs = n;
   return true;
