@@ -65,14 +65,16 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 // One workgroup: a contiguous range of cells, all jobs.  Per stage of kXKC
 // cells every field is read once from HBM (two adjacent cells per thread),
 // split into bf16 hi/lo for the B operand, and the F_0 fields are kept in
-// FP32 for the on-the-fly pair products.  The global loads of stage s + 1
-// are issued before the MFMAs of stage s, so HBM latency hides behind them.
+// FP32 for the on-the-fly pair products.  Stages alternate between two LDS
+// buffers: the global loads of stage s + 1 are issued before the MFMAs of
+// stage s and stored into the other buffer after them.
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                float *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) float U[kXMaxB + 1][kXUPad];  // row kXMaxB stays zero
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[kXCols][kXBPad];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[kXCols][kXBPad];
+  // two stage buffers; row kXMaxB of U stays zero
+  __shared__ __attribute__((aligned(16))) float U2[2][kXMaxB + 1][kXUPad];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh2[2][kXCols][kXBPad];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl2[2][kXCols][kXBPad];
   __shared__ uint16_t prs[kXMaxRows];  // b2 | b3 << 8 of each row
   __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
 
@@ -99,16 +101,17 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
     if (i < a.npair) { const int2 p = pairs[i]; v = (uint16_t)(p.x | (p.y << 8)); }
     prs[i] = v;
   }
-  for (int i = threadIdx.x; i < kXUPad; i += kXThreads) U[kXMaxB][i] = 0.f;
+  for (int i = threadIdx.x; i < 2 * kXUPad; i += kXThreads) U2[i / kXUPad][kXMaxB][i % kXUPad] = 0.f;
   for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
     const int l = i / a.nb, b1 = i - l * a.nb;
     cmap[i] = (uint8_t)(b1 * a.n_ell + l);
   }
   // padding columns stay zero
-  for (int i = threadIdx.x; i < (kXCols - a.ncol) * kXBPad; i += kXThreads) {
-    const int c = a.ncol + i / kXBPad, k = i % kXBPad;
-    Bh[c][k] = (__bf16)0.f;
-    Bl[c][k] = (__bf16)0.f;
+  for (int i = threadIdx.x; i < 2 * (kXCols - a.ncol) * kXBPad; i += kXThreads) {
+    const int bsel = i & 1, ii = i >> 1;
+    const int c = a.ncol + ii / kXBPad, k = ii % kXBPad;
+    Bh2[bsel][c][k] = (__bf16)0.f;
+    Bl2[bsel][c][k] = (__bf16)0.f;
   }
 
   const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
@@ -136,7 +139,10 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
       pf[q] = v;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int bsel) {
+    float(*U)[kXUPad] = U2[bsel];
+    __bf16(*Bh)[kXBPad] = Bh2[bsel];
+    __bf16(*Bl)[kXBPad] = Bl2[bsel];
 #pragma unroll
     for (int q = 0; q < kXPf; ++q) {
       const int e = threadIdx.x + q * kXThreads;
@@ -153,12 +159,22 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
     }
   };
 
-  if (c_begin < c_end) load(c_begin);
-  for (long long c0 = c_begin; c0 < c_end; c0 += kXKC) {
-    __syncthreads();  // previous stage fully consumed (and the tables above written)
-    store();
-    __syncthreads();
-    if (c0 + kXKC < c_end) load(c0 + kXKC);
+  // stages alternate between the two buffers: the loads of stage s + 1 are
+  // in flight during the MFMAs of stage s and are stored into the other
+  // buffer after them; one barrier per stage
+  if (c_begin < c_end) {
+    load(c_begin);
+    __syncthreads();  // tables above written
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (long long c0 = c_begin; c0 < c_end; c0 += kXKC, cur ^= 1) {
+    const bool more = c0 + kXKC < c_end;
+    if (more) load(c0 + kXKC);
+    const float(*U)[kXUPad] = U2[cur];
+    const __bf16(*Bh)[kXBPad] = Bh2[cur];
+    const __bf16(*Bl)[kXBPad] = Bl2[cur];
 #pragma unroll
     for (int ks = 0; ks < kXKC / 32; ++ks) {
       const int k0 = ks * 32 + lk * 8;
@@ -194,6 +210,8 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
         }
       }
     }
+    if (more) store(cur ^ 1);
+    __syncthreads();
   }
 
   // C[i][j] of a 16x16 tile: lane holds rows 4 (lane / 16) + v, column lane % 16
