@@ -31,6 +31,8 @@ extern "C" int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = upload_tables(plan, ws, s);
   if (rc) return rc;
+  rc = run_bin_geometry(plan, ws, s);
+  if (rc) return rc;
   if (plan->p.bk_nbins > 0) {
     rc = run_nt(plan, ws, s);
     if (rc) return rc;

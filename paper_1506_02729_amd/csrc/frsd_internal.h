@@ -165,6 +165,7 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
                     const frsd_catalog *ran, double alpha, hipStream_t s);
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s);
 template <typename T>
 int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s);
 int run_nt(frsd_plan *pl, void *ws, hipStream_t s);

@@ -12,7 +12,9 @@
 // Y = [Z(n) - Z(-n)^*] / 2i), the interlacing 1/2 [X + exp(-i pi sum n / N) Y]
 // and the window compensation prod sinc(pi n_d / N)^p are applied once per
 // multipole to the combined sums.  Shell sums are reduced per wavefront by
-// bin key and accumulated in FP64.
+// bin key and accumulated in FP64: three data sums per bin, since the mode
+// counts and sum |k| of every bin do not depend on the data and are summed
+// once per plan by the same kernel in its geometry mode.
 #include <cmath>
 
 #include "device.h"
@@ -37,8 +39,9 @@ struct CoefArgs {  // per moment position: rank, components, multiplicity
   float mult[kMaxMom];
 };
 
-// Reduce `v[kBinSums]` over the lanes of the wavefront that share `key`,
-// lane by lane of distinct keys, and add the sums to lds_bins[key][*].
+// Reduce v[NV] over the lanes of the wavefront that share `key`, one
+// distinct key at a time, and add the sums to lds_bins[key * NV + *].
+template <int NV>
 __device__ __forceinline__ void wave_bin_add(int key, const double *v, double *lds_bins) {
   const int lane = threadIdx.x & 63;
   bool pending = key >= 0;
@@ -49,24 +52,30 @@ __device__ __forceinline__ void wave_bin_add(int key, const double *v, double *l
     const int k = __shfl(key, leader, 64);
     const bool mine = pending && key == k;
 #pragma unroll
-    for (int s = 0; s < kBinSums; ++s) {
+    for (int s = 0; s < NV; ++s) {
       const double t = wave_sum(mine ? v[s] : 0.0);
-      if (lane == leader) atomicAdd(&lds_bins[k * kBinSums + s], t);
+      if (lane == leader) atomicAdd(&lds_bins[k * NV + s], t);
     }
     if (mine) pending = false;
   }
 }
 
-template <typename T>
+// Per-mode sums reduced by the binning kernel: GEOM (once per plan) the
+// mode count and sum |k| of every bin; otherwise the data sums, (S00, S20,
+// S40) for the P_ell bins and (S0w, S2w, S4w) for the bispectrum bins.
+template <bool GEOM> struct BinValues { static constexpr int n = GEOM ? 2 : 3; };
+
+template <typename T, bool GEOM>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict__ mesh, long long slot_stride,
                                                       SlotDesc sd, CoefArgs ca, BinArgs a,
                                                       const int16_t *__restrict__ pk_lut,
                                                       const int16_t *__restrict__ bk_lut, cplx_t<T> *lowk,
                                                       double *part) {
   using C = cplx_t<T>;
-  __shared__ double bins[kMaxBinsAll * kBinSums];
+  constexpr int NV = BinValues<GEOM>::n;
+  __shared__ double bins[kMaxBinsAll * 3];
   const int nall = a.pk_nb + a.bk_nb;
-  for (int i = threadIdx.x; i < nall * kBinSums; i += kBinThreads) bins[i] = 0.0;
+  for (int i = threadIdx.x; i < nall * NV; i += kBinThreads) bins[i] = 0.0;
   __syncthreads();
 
   const int N = a.N, nm = a.nmax;
@@ -79,9 +88,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
   for (long long itn = 0; itn < iters; ++itn) {
     const long long t = blockIdx.x * (long long)kBinThreads + threadIdx.x + itn * stride;
     int kp = -1, kb = -1;
-    double vp[kBinSums], vb[kBinSums];
+    double vp[NV], vb[NV];
 #pragma unroll
-    for (int s = 0; s < kBinSums; ++s) { vp[s] = 0; vb[s] = 0; }
+    for (int s = 0; s < NV; ++s) { vp[s] = 0; vb[s] = 0; }
     if (t < total) {
       const int iz = (int)(t % (nm + 1));
       const long long r = t / (nm + 1);
@@ -93,7 +102,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         kp = (m2 < a.pk_lut_len) ? pk_lut[m2] : -1;
         kb = (a.bk_nb > 0 && m2 < a.bk_lut_len) ? bk_lut[m2] : -1;
       }
-      if (kp >= 0 || kb >= 0) {
+      if (GEOM && (kp >= 0 || kb >= 0)) {
+        const double kmag = a.kf * sqrt((double)m2);
+        vp[0] = 2.0; vp[1] = 2.0 * kmag;
+        vb[0] = 2.0; vb[1] = 2.0 * kmag;
+      }
+      if (!GEOM && (kp >= 0 || kb >= 0)) {
         const T kk = (T)sqrt((double)m2);
         const T kh[3] = {(T)ix / kk, (T)iy / kk, (T)iz / kk};
         const long long gp = ((long long)((ix + N) % N) * N + (iy + N) % N) * N + iz;
@@ -168,10 +182,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         const double S0w = A[0][0] * A[3][0] + A[0][1] * A[3][1];
         const double S2w = A[1][0] * A[3][0] + A[1][1] * A[3][1];
         const double S4w = A[2][0] * A[3][0] + A[2][1] * A[3][1];
-        const double kmag = a.kf * sqrt((double)m2);
-        const double v[kBinSums] = {2.0, 2.0 * kmag, 2.0 * S00, 2.0 * S20, 2.0 * S40, 2.0 * S0w, 2.0 * S2w, 2.0 * S4w};
-#pragma unroll
-        for (int q = 0; q < kBinSums; ++q) { vp[q] = v[q]; vb[q] = v[q]; }
+        // each half-space mode stands for n and -n
+        vp[0] = 2.0 * S00; vp[NV > 1 ? 1 : 0] = 2.0 * S20; vp[NV - 1] = 2.0 * S40;
+        vb[0] = 2.0 * S0w; vb[NV > 1 ? 1 : 0] = 2.0 * S2w; vb[NV - 1] = 2.0 * S4w;
         if (kb >= 0 && lowk) {
           // A_0, A_2, A_4 at n and -n on the low-k cube [-nc, nc]^3
           const int D = a.D, nc = a.nc_b;
@@ -186,20 +199,24 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         }
       }
     }
-    wave_bin_add(kp, vp, bins);
-    wave_bin_add(kb >= 0 ? a.pk_nb + kb : -1, vb, bins);
+    wave_bin_add<NV>(kp, vp, bins);
+    wave_bin_add<NV>(kb >= 0 ? a.pk_nb + kb : -1, vb, bins);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nall * kBinSums; i += kBinThreads) part[(long long)i * gridDim.x + blockIdx.x] = bins[i];
+  for (int i = threadIdx.x; i < nall * NV; i += kBinThreads) part[(long long)i * gridDim.x + blockIdx.x] = bins[i];
 }
 
-// Sum of the per-block partials, one thread per (bin, quantity).
-__global__ void k_bin_reduce(const double *part, int nblk, int nvals, double *sum) {
+// Sum of the per-block partials, one thread per (bin, quantity), into the
+// kBinSums slots of the bin: geometry into slots 0-1, data sums into 2-4
+// (P_ell bins) or 5-7 (bispectrum bins).
+__global__ void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb, int geom, double *sum) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nvals) return;
+  if (i >= nall * nv) return;
   double s = 0;
   for (int b = 0; b < nblk; ++b) s += part[(long long)i * nblk + b];
-  sum[i] = s;
+  const int bin = i / nv, q = i - bin * nv;
+  const int slot = geom ? q : (bin < pk_nb ? 2 + q : 5 + q);
+  sum[bin * kBinSums + slot] = s;
 }
 
 __global__ void k_pk_final(const double *sum, const double *scal, int nb, int ell_max, int64_t *n_modes, double *k_eff,
@@ -220,16 +237,42 @@ __global__ void k_pk_final(const double *sum, const double *scal, int nb, int el
   p4[b] = ell_max >= 4 ? 9.0 * v[4] / (cnt * I22) : __builtin_nan("");
 }
 
+static BinArgs bin_args(const frsd_plan *pl) {
+  const frsd_params &p = pl->p;
+  BinArgs a{};
+  a.N = pl->N; a.nmax = pl->nmax; a.order = p.order; a.interlace = p.interlace; a.compensate = p.compensate;
+  a.pk_nb = p.pk_nbins; a.bk_nb = p.bk_nbins; a.pk_lut_len = pl->pk_lut_len; a.bk_lut_len = pl->bk_lut_len;
+  a.nc_b = pl->nc_b; a.D = pl->D; a.ell_max = p.ell_max; a.has_w = p.bk_nbins > 0; a.kf = pl->kf;
+  return a;
+}
+
+// Mode counts and sum |k| of every bin (data independent; once per plan).
+int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
+  const Layout &L = pl->L;
+  const frsd_params &p = pl->p;
+  const int nall = p.pk_nbins + p.bk_nbins;
+  if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
+  const BinArgs a = bin_args(pl);
+  constexpr int NV = BinValues<true>::n;
+  FRSD_TIMED("bin_geom", s, hipLaunchKernelGGL((k_bin<float, true>), dim3(kBinBlocks), dim3(kBinThreads), 0, s,
+                                               (const float2 *)nullptr, 0LL, pl->slots, CoefArgs{}, a,
+                                               ws_ptr<const int16_t>(ws, L.pk_lut),
+                                               p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
+                                               (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part)));
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 255) / 256), dim3(256), 0, s,
+                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
   const Layout &L = pl->L;
   const frsd_params &p = pl->p;
   const int nall = p.pk_nbins + p.bk_nbins;
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
-  BinArgs a{};
-  a.N = pl->N; a.nmax = pl->nmax; a.order = p.order; a.interlace = p.interlace; a.compensate = p.compensate;
-  a.pk_nb = p.pk_nbins; a.bk_nb = p.bk_nbins; a.pk_lut_len = pl->pk_lut_len; a.bk_lut_len = pl->bk_lut_len;
-  a.nc_b = pl->nc_b; a.D = pl->D; a.ell_max = p.ell_max; a.has_w = p.bk_nbins > 0; a.kf = pl->kf;
+  const BinArgs a = bin_args(pl);
   CoefArgs ca{};
   const MomentTable &tab = moment_table();
   for (int i = 0; i < kMaxMom; ++i) {
@@ -238,13 +281,14 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
   }
   using C = cplx_t<T>;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
-  FRSD_TIMED("bin", s, hipLaunchKernelGGL(k_bin<T>, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh), NNN,
+  constexpr int NV = BinValues<false>::n;
+  FRSD_TIMED("bin", s, hipLaunchKernelGGL((k_bin<T, false>), dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh), NNN,
                      pl->slots, ca, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                      p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                      p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr, ws_ptr<double>(ws, L.bin_part)));
-  const int nvals = nall * kBinSums;
-  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nvals + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_part),
-                     kBinBlocks, nvals, ws_ptr<double>(ws, L.bin_sum)));
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 255) / 256), dim3(256), 0, s,
+                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
                      ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
                      out->p4, out->s00, out->s20, out->s40, out->scalars));
