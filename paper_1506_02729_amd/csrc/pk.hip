@@ -16,6 +16,7 @@
 // counts and sum |k| of every bin do not depend on the data and are summed
 // once per plan by the same kernel in its geometry mode.
 #include <cmath>
+#include <utility>
 
 #include "device.h"
 #include "frsd_internal.h"
@@ -24,39 +25,43 @@ namespace frsd {
 
 constexpr int kBinThreads = 256;
 constexpr int kMaxBinsAll = 512;
+constexpr int kBinTab = 513;  // |n| <= N/2 for N <= 1024
 
 struct BinArgs {
   int N, nmax, order, interlace, compensate;
   int pk_nb, bk_nb, pk_lut_len, bk_lut_len;
   int nc_b, D;  // low-k cube
-  int ell_max, has_w;
+  int n_slot, n_ell, has_w;
   double kf;
 };
 
-struct CoefArgs {  // per moment position: rank, components, multiplicity
-  int8_t idx[kMaxMom][4];
-  int8_t rank[kMaxMom];
-  float mult[kMaxMom];
-};
-
-// Reduce v[NV] over the lanes of the wavefront that share `key`, one
-// distinct key at a time, and add the sums to lds_bins[key * NV + *].
+// Sum v[NV] over every run of equal keys among consecutive lanes (a
+// segmented inclusive scan), and let the last lane of each run whose key is
+// >= 0 add the run's sums to lds_bins[key * NV + *].  Lanes are assigned
+// consecutive modes along n_z, so keys come in a few long runs; a key that
+// forms several runs adds each run's sum separately.  Every lane of the
+// wavefront takes part.
 template <int NV>
-__device__ __forceinline__ void wave_bin_add(int key, const double *v, double *lds_bins) {
+__device__ __forceinline__ void wave_run_add(int key, double *v, double *lds_bins) {
+  if (__ballot(key >= 0) == 0ull) return;
   const int lane = threadIdx.x & 63;
-  bool pending = key >= 0;
-  while (true) {
-    const unsigned long long mask = __ballot(pending);
-    if (mask == 0ull) break;
-    const int leader = __ffsll((long long)mask) - 1;
-    const int k = __shfl(key, leader, 64);
-    const bool mine = pending && key == k;
+  const int prev = __shfl_up(key, 1, 64);
+  const int next = __shfl_down(key, 1, 64);
+  int start = (lane == 0 || prev != key) ? lane : 0;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) start = max(start, __shfl_up(start, o, 64));
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const bool take = lane - o >= start;
 #pragma unroll
     for (int s = 0; s < NV; ++s) {
-      const double t = wave_sum(mine ? v[s] : 0.0);
-      if (lane == leader) atomicAdd(&lds_bins[k * NV + s], t);
+      const double t = __shfl_up(v[s], o, 64);
+      v[s] += take ? t : 0.0;
     }
-    if (mine) pending = false;
+  }
+  if (key >= 0 && (lane == 63 || next != key)) {
+#pragma unroll
+    for (int s = 0; s < NV; ++s) atomicAdd(&lds_bins[key * NV + s], v[s]);
   }
 }
 
@@ -65,20 +70,86 @@ __device__ __forceinline__ void wave_bin_add(int key, const double *v, double *l
 // S40) for the P_ell bins and (S0w, S2w, S4w) for the bispectrum bins.
 template <bool GEOM> struct BinValues { static constexpr int n = GEOM ? 2 : 3; };
 
-template <typename T, bool GEOM>
+// Rank-2 and rank-4 monomials of k-hat times their multiplicities in the
+// full contraction, in moment-table order (xx yy zz xy yz zx; xxxx yyyy zzzz
+// xxxy xxxz yyyx yyyz zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy).
+template <typename T>
+__device__ __forceinline__ void khat_monomials(T hx, T hy, T hz, T *mono) {
+  const T q[6] = {hx * hx, hy * hy, hz * hz, hx * hy, hy * hz, hz * hx};
+  mono[0] = T(1);
+  mono[1] = q[0]; mono[2] = q[1]; mono[3] = q[2];
+  mono[4] = T(2) * q[3]; mono[5] = T(2) * q[4]; mono[6] = T(2) * q[5];
+  mono[7] = q[0] * q[0]; mono[8] = q[1] * q[1]; mono[9] = q[2] * q[2];
+  mono[10] = T(4) * q[0] * q[3]; mono[11] = T(4) * q[0] * q[5]; mono[12] = T(4) * q[1] * q[3];
+  mono[13] = T(4) * q[1] * q[4]; mono[14] = T(4) * q[2] * q[5]; mono[15] = T(4) * q[2] * q[4];
+  mono[16] = T(6) * q[0] * q[1]; mono[17] = T(6) * q[1] * q[2]; mono[18] = T(6) * q[2] * q[0];
+  mono[19] = T(12) * q[0] * q[4]; mono[20] = T(12) * q[1] * q[5]; mono[21] = T(12) * q[2] * q[3];
+}
+
+// Add the moment at position p of the moment list (moments 0..n_ell-1 in
+// table order, then the w^2 moment if has_w) with Fourier values z(n), z(-n)
+// to the class sums r[cls][+-]: class 0 the monopole moment, 1 the rank-2
+// sum, 2 the rank-4 sum (each weighted by its monomial), 3 the w^2 moment.
+template <typename C, typename T, int p>
+__device__ __forceinline__ void add_position(int n_ell, int has_w, const T *mono, C zp, C zm, C (&r)[4][2]) {
+  if (p < n_ell) {
+    constexpr int cls = p == 0 ? 0 : (p < 7 ? 1 : 2);
+    const T c = mono[p];
+    r[cls][0] = cadd(r[cls][0], cscale(zp, c));
+    r[cls][1] = cadd(r[cls][1], cscale(zm, c));
+  } else if (p == n_ell && has_w) {
+    r[3][0] = cadd(r[3][0], zp);
+    r[3][1] = cadd(r[3][1], zm);
+  }
+}
+
+// All slots of one mode, unrolled so that every position is a constant.
+template <typename C, typename T, bool IL, int... S>
+__device__ __forceinline__ void add_slots(std::integer_sequence<int, S...>, int n_slot, int n_ell, int has_w,
+                                          const T *mono, const C *zp, const C *zm, C (&rr)[4][2], C (&ri)[4][2]) {
+  if constexpr (IL) {
+    ((S < n_slot ? add_position<C, T, S>(n_ell, has_w, mono, zp[S], zm[S], rr) : void()), ...);
+  } else {
+    ((S < n_slot ? add_position<C, T, 2 * S>(n_ell, has_w, mono, zp[S], zm[S], rr) : void()), ...);
+    ((S < n_slot ? add_position<C, T, 2 * S + 1>(n_ell, has_w, mono, zp[S], zm[S], ri) : void()), ...);
+  }
+}
+
+// IL: slot s holds moment position s on the main grid (real part) and on
+// the twin grid (imaginary part); otherwise positions 2s and 2s+1.
+template <typename T, bool GEOM, bool IL>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict__ mesh, long long slot_stride,
-                                                      SlotDesc sd, CoefArgs ca, BinArgs a,
-                                                      const int16_t *__restrict__ pk_lut,
+                                                      BinArgs a, const int16_t *__restrict__ pk_lut,
                                                       const int16_t *__restrict__ bk_lut, cplx_t<T> *lowk,
                                                       double *part) {
   using C = cplx_t<T>;
   constexpr int NV = BinValues<GEOM>::n;
   __shared__ double bins[kMaxBinsAll * 3];
+  // per-axis factors for |n| <= nmax: interlacing phase exp(-i pi n / N)
+  // (cos, sin) and the inverse window 1 / sinc(pi n / N)^p
+  __shared__ double tcos[kBinTab], tsin[kBinTab], tiw[kBinTab];
   const int nall = a.pk_nb + a.bk_nb;
+  const int N = a.N, nm = a.nmax;
   for (int i = threadIdx.x; i < nall * NV; i += kBinThreads) bins[i] = 0.0;
+  if (!GEOM) {
+    for (int n = threadIdx.x; n <= nm; n += kBinThreads) {
+      const double x = (double)n / N;
+      double sn, cs;
+      sincospi(x, &sn, &cs);
+      tcos[n] = cs;
+      tsin[n] = -sn;
+      double iw = 1.0;
+      if (a.compensate && n != 0) {
+        const double sc = sn / (M_PI * x);
+        double wp = sc;
+        for (int q = 1; q < a.order; ++q) wp *= sc;
+        iw = 1.0 / wp;
+      }
+      tiw[n] = iw;
+    }
+  }
   __syncthreads();
 
-  const int N = a.N, nm = a.nmax;
   const int side = 2 * nm + 1;
   const long long total = (long long)side * side * (nm + 1);
   const long long stride = (long long)gridDim.x * kBinThreads;
@@ -91,116 +162,118 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
     double vp[NV], vb[NV];
 #pragma unroll
     for (int s = 0; s < NV; ++s) { vp[s] = 0; vb[s] = 0; }
+    int ix = 0, iy = 0, iz = 0;
+    long long m2 = 0;
     if (t < total) {
-      const int iz = (int)(t % (nm + 1));
+      iz = (int)(t % (nm + 1));
       const long long r = t / (nm + 1);
-      const int iy = (int)(r % side) - nm;
-      const int ix = (int)(r / side) - nm;
+      iy = (int)(r % side) - nm;
+      ix = (int)(r / side) - nm;
       const bool half = (iz > 0) || (iy > 0) || (iy == 0 && ix > 0);
-      const long long m2 = (long long)ix * ix + (long long)iy * iy + (long long)iz * iz;
+      m2 = (long long)ix * ix + (long long)iy * iy + (long long)iz * iz;
       if (half) {
         kp = (m2 < a.pk_lut_len) ? pk_lut[m2] : -1;
         kb = (a.bk_nb > 0 && m2 < a.bk_lut_len) ? bk_lut[m2] : -1;
       }
-      if (GEOM && (kp >= 0 || kb >= 0)) {
+    }
+    if (GEOM) {
+      if (kp >= 0 || kb >= 0) {
         const double kmag = a.kf * sqrt((double)m2);
         vp[0] = 2.0; vp[1] = 2.0 * kmag;
         vb[0] = 2.0; vb[1] = 2.0 * kmag;
       }
-      if (!GEOM && (kp >= 0 || kb >= 0)) {
-        const T kk = (T)sqrt((double)m2);
-        const T kh[3] = {(T)ix / kk, (T)iy / kk, (T)iz / kk};
-        const long long gp = ((long long)((ix + N) % N) * N + (iy + N) % N) * N + iz;
-        const long long gm = ((long long)((N - ix) % N) * N + (N - iy) % N) * N + (N - iz) % N;
-        // accumulators [ell: 0, 2, 4, w][re-plane / im-plane][n / -n]
-        C zr[4][2], zi[4][2];
+    } else if (kp >= 0 || kb >= 0) {
+      const long long gp = ((long long)((ix + N) % N) * N + (iy + N) % N) * N + iz;
+      const long long gm = ((long long)((N - ix) % N) * N + (N - iy) % N) * N + (N - iz) % N;
+      // every slot's Z(n) and Z(-n) are requested before any is used
+      C zp[kMaxSlots], zm[kMaxSlots];
 #pragma unroll
-        for (int l = 0; l < 4; ++l)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) { zr[l][q] = cmake<C>(T(0), T(0)); zi[l][q] = cmake<C>(T(0), T(0)); }
-        for (int sl = 0; sl < sd.n_slot; ++sl) {
-          const C zp = mesh[sl * slot_stride + gp];
-          const C zm = mesh[sl * slot_stride + gm];
-#pragma unroll
-          for (int part2 = 0; part2 < 2; ++part2) {
-            const int mp = part2 == 0 ? sd.re_mom[sl] : sd.im_mom[sl];
-            if (mp < 0) continue;
-            const int id = sd.mom_id[mp];
-            T c[4] = {T(0), T(0), T(0), T(0)};
-            if (id == kMomW) {
-              c[3] = T(1);
-            } else {
-              T mono = T(ca.mult[id]);
-              for (int k = 0; k < ca.rank[id]; ++k) mono *= kh[ca.idx[id][k]];
-              if (ca.rank[id] == 0) { c[0] = T(1); c[1] = T(-0.5); c[2] = T(0.375); }
-              else if (ca.rank[id] == 2) { c[1] = T(1.5) * mono; c[2] = T(-3.75) * mono; }
-              else { c[2] = T(4.375) * mono; }
-            }
-            C(*acc)[2] = part2 == 0 ? zr : zi;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-              acc[l][0] = cadd(acc[l][0], cscale(zp, c[l]));
-              acc[l][1] = cadd(acc[l][1], cscale(zm, c[l]));
-            }
-          }
+      for (int sl = 0; sl < kMaxSlots; ++sl) {
+        if (sl < a.n_slot) {
+          zp[sl] = mesh[sl * slot_stride + gp];
+          zm[sl] = mesh[sl * slot_stride + gm];
         }
-        // unpack, interlace, compensate
-        double ph_re = 1.0, ph_im = 0.0, s = 1.0;
-        if (a.interlace) {
-          sincospi(-(double)(ix + iy + iz) / N, &ph_im, &ph_re);
-          s = 0.5;
-        }
-        double win = 1.0;
-        if (a.compensate) {
-          const int nn[3] = {ix, iy, iz};
-          for (int d = 0; d < 3; ++d) {
-            if (nn[d] != 0) {
-              const double x = (double)nn[d] / N;
-              const double sc = sinpi(x) / (M_PI * x);
-              double wp = sc;
-              for (int q = 1; q < a.order; ++q) wp *= sc;
-              win *= wp;
-            }
-          }
-        }
-        const double scale = s / win;
-        double A[4][2];
+      }
+      const T ik = (T)(1.0 / sqrt((double)m2));
+      T mono[kMaxMom - 1];
+      khat_monomials<T>((T)ix * ik, (T)iy * ik, (T)iz * ik, mono);
+      // class sums [class][n / -n] of the real-part and imaginary-part planes
+      C rr[4][2], ri[4][2];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          // X = (zr(n) + conj zr(-n)) / 2 ;  Y = (zi(n) - conj zi(-n)) / 2i
-          const double xr = 0.5 * ((double)zr[l][0].x + (double)zr[l][1].x);
-          const double xi = 0.5 * ((double)zr[l][0].y - (double)zr[l][1].y);
-          const double yr = 0.5 * ((double)zi[l][0].y + (double)zi[l][1].y);
-          const double yi = -0.5 * ((double)zi[l][0].x - (double)zi[l][1].x);
-          const double pr = ph_re * yr - ph_im * yi, pi = ph_re * yi + ph_im * yr;
-          A[l][0] = scale * (xr + pr);
-          A[l][1] = scale * (xi + pi);
-        }
-        const double S00 = A[0][0] * A[0][0] + A[0][1] * A[0][1];
-        const double S20 = A[1][0] * A[0][0] + A[1][1] * A[0][1];
-        const double S40 = A[2][0] * A[0][0] + A[2][1] * A[0][1];
-        const double S0w = A[0][0] * A[3][0] + A[0][1] * A[3][1];
-        const double S2w = A[1][0] * A[3][0] + A[1][1] * A[3][1];
-        const double S4w = A[2][0] * A[3][0] + A[2][1] * A[3][1];
-        // each half-space mode stands for n and -n
-        vp[0] = 2.0 * S00; vp[NV > 1 ? 1 : 0] = 2.0 * S20; vp[NV - 1] = 2.0 * S40;
-        vb[0] = 2.0 * S0w; vb[NV > 1 ? 1 : 0] = 2.0 * S2w; vb[NV - 1] = 2.0 * S4w;
-        if (kb >= 0 && lowk) {
-          // A_0, A_2, A_4 at n and -n on the low-k cube [-nc, nc]^3
-          const int D = a.D, nc = a.nc_b;
-          const long long DDD = (long long)D * D * D;
-          const long long ip = ((long long)(ix + nc) * D + (iy + nc)) * D + (iz + nc);
-          const long long im = ((long long)(nc - ix) * D + (nc - iy)) * D + (nc - iz);
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-          for (int l = 0; l < 3; ++l) {
-            lowk[l * DDD + ip] = cmake<C>((T)A[l][0], (T)A[l][1]);
-            lowk[l * DDD + im] = cmake<C>((T)A[l][0], (T)(-A[l][1]));
-          }
+        for (int q = 0; q < 2; ++q) { rr[c][q] = cmake<C>(T(0), T(0)); ri[c][q] = cmake<C>(T(0), T(0)); }
+      add_slots<C, T, IL>(std::make_integer_sequence<int, kMaxSlots>{}, a.n_slot, a.n_ell, a.has_w, mono, zp, zm,
+                          rr, ri);
+      // multipole combinations (Sec. II.B): F_0 = R0, F_2 = 3/2 R2 - 1/2 R0,
+      // F_4 = 35/8 R4 - 15/4 R2 + 3/8 R0, and F_0^w
+      auto multipoles = [&](C (&r)[4][2], C (&z)[4][2]) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          z[0][q] = r[0][q];
+          z[1][q] = cadd(cscale(r[1][q], T(1.5)), cscale(r[0][q], T(-0.5)));
+          z[2][q] = cadd(cadd(cscale(r[2][q], T(4.375)), cscale(r[1][q], T(-3.75))), cscale(r[0][q], T(0.375)));
+          z[3][q] = r[3][q];
+        }
+      };
+      C zr[4][2], zi[4][2];
+      multipoles(rr, zr);
+      if constexpr (IL) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) { zi[l][0] = zr[l][0]; zi[l][1] = zr[l][1]; }
+      } else {
+        multipoles(ri, zi);
+      }
+      // unpack, interlace, compensate
+      const int ax = ix < 0 ? -ix : ix, ay = iy < 0 ? -iy : iy;
+      double ph_re = 1.0, ph_im = 0.0, s = 1.0;
+      if (a.interlace) {
+        // exp(-i pi (n_x + n_y + n_z) / N) as a product of per-axis factors
+        const double cx = tcos[ax], sx = ix < 0 ? -tsin[ax] : tsin[ax];
+        const double cy = tcos[ay], sy = iy < 0 ? -tsin[ay] : tsin[ay];
+        const double cz = tcos[iz], sz = tsin[iz];
+        const double cxy = cx * cy - sx * sy, sxy = cx * sy + sx * cy;
+        ph_re = cxy * cz - sxy * sz;
+        ph_im = cxy * sz + sxy * cz;
+        s = 0.5;
+      }
+      const double scale = s * (tiw[ax] * tiw[ay] * tiw[iz]);
+      double A[4][2];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        // X = (zr(n) + conj zr(-n)) / 2 ;  Y = (zi(n) - conj zi(-n)) / 2i
+        const double xr = 0.5 * ((double)zr[l][0].x + (double)zr[l][1].x);
+        const double xi = 0.5 * ((double)zr[l][0].y - (double)zr[l][1].y);
+        const double yr = 0.5 * ((double)zi[l][0].y + (double)zi[l][1].y);
+        const double yi = -0.5 * ((double)zi[l][0].x - (double)zi[l][1].x);
+        const double pr = ph_re * yr - ph_im * yi, pi = ph_re * yi + ph_im * yr;
+        A[l][0] = scale * (xr + pr);
+        A[l][1] = scale * (xi + pi);
+      }
+      const double S00 = A[0][0] * A[0][0] + A[0][1] * A[0][1];
+      const double S20 = A[1][0] * A[0][0] + A[1][1] * A[0][1];
+      const double S40 = A[2][0] * A[0][0] + A[2][1] * A[0][1];
+      const double S0w = A[0][0] * A[3][0] + A[0][1] * A[3][1];
+      const double S2w = A[1][0] * A[3][0] + A[1][1] * A[3][1];
+      const double S4w = A[2][0] * A[3][0] + A[2][1] * A[3][1];
+      // each half-space mode stands for n and -n
+      vp[0] = 2.0 * S00; vp[NV > 1 ? 1 : 0] = 2.0 * S20; vp[NV - 1] = 2.0 * S40;
+      vb[0] = 2.0 * S0w; vb[NV > 1 ? 1 : 0] = 2.0 * S2w; vb[NV - 1] = 2.0 * S4w;
+      if (kb >= 0 && lowk) {
+        // A_0, A_2, A_4 at n and -n on the low-k cube [-nc, nc]^3
+        const int D = a.D, nc = a.nc_b;
+        const long long DDD = (long long)D * D * D;
+        const long long ip = ((long long)(ix + nc) * D + (iy + nc)) * D + (iz + nc);
+        const long long im = ((long long)(nc - ix) * D + (nc - iy)) * D + (nc - iz);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          lowk[l * DDD + ip] = cmake<C>((T)A[l][0], (T)A[l][1]);
+          lowk[l * DDD + im] = cmake<C>((T)A[l][0], (T)(-A[l][1]));
         }
       }
     }
-    wave_bin_add<NV>(kp, vp, bins);
-    wave_bin_add<NV>(kb >= 0 ? a.pk_nb + kb : -1, vb, bins);
+    wave_run_add<NV>(kp, vp, bins);
+    wave_run_add<NV>(kb >= 0 ? a.pk_nb + kb : -1, vb, bins);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nall * NV; i += kBinThreads) part[(long long)i * gridDim.x + blockIdx.x] = bins[i];
@@ -239,11 +312,32 @@ __global__ void k_pk_final(const double *sum, const double *scal, int nb, int el
 
 static BinArgs bin_args(const frsd_plan *pl) {
   const frsd_params &p = pl->p;
+  const SlotDesc &sd = pl->slots;
   BinArgs a{};
   a.N = pl->N; a.nmax = pl->nmax; a.order = p.order; a.interlace = p.interlace; a.compensate = p.compensate;
   a.pk_nb = p.pk_nbins; a.bk_nb = p.bk_nbins; a.pk_lut_len = pl->pk_lut_len; a.bk_lut_len = pl->bk_lut_len;
-  a.nc_b = pl->nc_b; a.D = pl->D; a.ell_max = p.ell_max; a.has_w = p.bk_nbins > 0; a.kf = pl->kf;
+  a.nc_b = pl->nc_b; a.D = pl->D; a.kf = pl->kf;
+  a.n_slot = sd.n_slot;
+  for (int m = 0; m < sd.n_mom; ++m) {
+    if (sd.mom_id[m] == kMomW) a.has_w = 1;
+    else ++a.n_ell;
+  }
   return a;
+}
+
+// The binning kernel takes the slot layout the plan builds: moment
+// positions 0..n_ell-1 in table order, then w^2; with interlacing slot s
+// holds position s on both grids, without it positions 2s and 2s+1.
+static bool slot_layout_ok(const SlotDesc &sd, const BinArgs &a, bool interlace) {
+  if (sd.n_mom != a.n_ell + a.has_w) return false;
+  for (int m = 0; m < sd.n_mom; ++m)
+    if (sd.mom_id[m] != (m < a.n_ell ? m : kMomW)) return false;
+  for (int s = 0; s < sd.n_slot; ++s) {
+    const int re = interlace ? s : 2 * s;
+    const int im = interlace ? s : (2 * s + 1 < sd.n_mom ? 2 * s + 1 : -1);
+    if (sd.re_mom[s] != re || sd.im_mom[s] != im) return false;
+  }
+  return sd.n_slot == (interlace ? sd.n_mom : (sd.n_mom + 1) / 2);
 }
 
 // Mode counts and sum |k| of every bin (data independent; once per plan).
@@ -254,8 +348,8 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
   const BinArgs a = bin_args(pl);
   constexpr int NV = BinValues<true>::n;
-  FRSD_TIMED("bin_geom", s, hipLaunchKernelGGL((k_bin<float, true>), dim3(kBinBlocks), dim3(kBinThreads), 0, s,
-                                               (const float2 *)nullptr, 0LL, pl->slots, CoefArgs{}, a,
+  FRSD_TIMED("bin_geom", s, hipLaunchKernelGGL((k_bin<float, true, true>), dim3(kBinBlocks), dim3(kBinThreads), 0, s,
+                                               (const float2 *)nullptr, 0LL, a,
                                                ws_ptr<const int16_t>(ws, L.pk_lut),
                                                p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                                (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part)));
@@ -273,19 +367,17 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
   const int nall = p.pk_nbins + p.bk_nbins;
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
   const BinArgs a = bin_args(pl);
-  CoefArgs ca{};
-  const MomentTable &tab = moment_table();
-  for (int i = 0; i < kMaxMom; ++i) {
-    ca.rank[i] = tab.rank[i]; ca.mult[i] = tab.mult[i];
-    for (int k = 0; k < 4; ++k) ca.idx[i][k] = tab.idx[i][k];
-  }
+  if (a.nmax >= kBinTab) return fail(FRSD_EINVAL, "k range too large for the binning tables");
+  if (!slot_layout_ok(pl->slots, a, p.interlace != 0)) return fail(FRSD_EINVAL, "unexpected slot layout");
   using C = cplx_t<T>;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
   constexpr int NV = BinValues<false>::n;
-  FRSD_TIMED("bin", s, hipLaunchKernelGGL((k_bin<T, false>), dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh), NNN,
-                     pl->slots, ca, a, ws_ptr<const int16_t>(ws, L.pk_lut),
-                     p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
-                     p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr, ws_ptr<double>(ws, L.bin_part)));
+  auto kern = p.interlace ? k_bin<T, false, true> : k_bin<T, false, false>;
+  FRSD_TIMED("bin", s, hipLaunchKernelGGL(kern, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
+                                          NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
+                                          p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
+                                          p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr,
+                                          ws_ptr<double>(ws, L.bin_part)));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 255) / 256), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
