@@ -346,7 +346,7 @@ static int shell_pipeline(frsd_plan *pl, void *ws, int nfield, const void *tw, T
   switch (pl->M) {
 #define FRSD_CASE(L) \
   case L: return shell_pipeline_ct<T, TO, IND, L>(pl, ws, nfield, tw, shells, s);
-    FRSD_FFT_LENGTHS(FRSD_CASE)
+    FRSD_SHELL_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
     default: return shell_pipeline_rt<T, TO, IND>(pl, ws, nfield, tw, shells, s);
   }

@@ -68,6 +68,30 @@ template <typename C, bool INV> __device__ __forceinline__ void dft3(C &x0, C &x
   x0 = cadd(x0, t); x1 = cadd(m, s); x2 = csub(m, s);
 }
 
+// 5-point DFT from the real/imaginary split of the 2 conjugate pairs of
+// fifth roots of unity: with t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4,
+// t4 = x2 - x3, c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5),
+//   X1, X4 = x0 + c1 t1 + c2 t2 -/+ i (s1 t3 + s2 t4),
+//   X2, X3 = x0 + c2 t1 + c1 t2 -/+ i (s2 t3 - s1 t4)
+// (signs of i swapped for INV).
+template <typename C, bool INV> __device__ __forceinline__ void dft5(C *v) {
+  using S = decltype(C{}.x);
+  const S c1 = S(0.3090169943749474241022934171828190588602);   // cos(2 pi / 5)
+  const S c2 = S(-0.8090169943749474241022934171828190588602);  // cos(4 pi / 5)
+  const S s1 = S(0.9510565162951535721164393333793821434057);   // sin(2 pi / 5)
+  const S s2 = S(0.5877852522924731291687059546390727685977);   // sin(4 pi / 5)
+  const C x0 = v[0];
+  const C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  const C a1 = cadd(x0, cadd(cscale(t1, c1), cscale(t2, c2)));
+  const C a2 = cadd(x0, cadd(cscale(t1, c2), cscale(t2, c1)));
+  const C b1 = cmul_mi<C, INV>(cadd(cscale(t3, s1), cscale(t4, s2)));
+  const C b2 = cmul_mi<C, INV>(csub(cscale(t3, s2), cscale(t4, s1)));
+  v[0] = cadd(x0, cadd(t1, t2));
+  v[1] = cadd(a1, b1); v[4] = csub(a1, b1);
+  v[2] = cadd(a2, b2); v[3] = csub(a2, b2);
+}
+
 template <typename C, bool INV> __device__ __forceinline__ void dft8(C *v) {
   using S = decltype(C{}.x);
   const S r = S(0.7071067811865475244008443621048490392848);  // 1/sqrt(2)
@@ -92,6 +116,7 @@ template <typename C, int R, bool INV> __device__ __forceinline__ void dftR(C *v
   if constexpr (R == 2) dft2<C, INV>(v[0], v[1]);
   else if constexpr (R == 3) dft3<C, INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<C, INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 5) dft5<C, INV>(v);
   else dft8<C, INV>(v);
 }
 
@@ -151,11 +176,12 @@ struct StageList {
   int radix[12];
 };
 
-// Compile-time radix schedule of a length LEN = 2^a 3^b (same order as the
-// host schedule: all factors 3, then 8s, then one 4 and/or one 2).
+// Compile-time radix schedule of a length LEN = 2^a 3^b 5^c (same order as
+// the host schedule: all factors 3, then 5s, then 8s, then one 4 and/or one 2).
 constexpr int ct_radix(int len, int s) {
   int m = len, k = 0;
   while (m % 3 == 0) { if (k == s) return 3; m /= 3; ++k; }
+  while (m % 5 == 0) { if (k == s) return 5; m /= 5; ++k; }
   while (m % 8 == 0) { if (k == s) return 8; m /= 8; ++k; }
   if (m % 4 == 0) { if (k == s) return 4; m /= 4; ++k; }
   if (m % 2 == 0) { if (k == s) return 2; m /= 2; ++k; }
@@ -177,6 +203,7 @@ __device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const
     if (R == 8) stockham_stage<C, 8, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else if (R == 4) stockham_stage<C, 4, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else if (R == 2) stockham_stage<C, 2, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    else if (R == 5) stockham_stage<C, 5, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else stockham_stage<C, 3, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     Ns *= R;
   }
@@ -277,7 +304,10 @@ template <typename T> struct FftTune {
   static constexpr int pn = sizeof(T) == 4 ? 8192 : 4096;
 };
 
-// Lengths with a compile-time kernel; other 2^a 3^b lengths use the run-time one.
+// Lengths with a compile-time kernel; other 2^a 3^b 5^c lengths use the
+// run-time one.  Forward mesh sides (multiples of 16) and the real-space
+// grids of the triangle search.
 #define FRSD_FFT_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define FRSD_SHELL_LENGTHS(X) FRSD_FFT_LENGTHS(X) X(360)
 
 }  // namespace frsd

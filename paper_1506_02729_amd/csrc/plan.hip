@@ -56,6 +56,7 @@ bool make_fft_len(int n, FftLen *out) {
   int m = n;
   int ns = 0;
   while (m % 3 == 0) { f.radix[ns++] = 3; m /= 3; }
+  while (m % 5 == 0) { f.radix[ns++] = 5; m /= 5; }
   while (m % 8 == 0) { f.radix[ns++] = 8; m /= 8; }
   if (m % 4 == 0) { f.radix[ns++] = 4; m /= 4; }
   if (m % 2 == 0) { f.radix[ns++] = 2; m /= 2; }
@@ -69,6 +70,7 @@ static bool is_smooth(int n) {
   if (n < 1) return false;
   while (n % 2 == 0) n /= 2;
   while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
   return n == 1;
 }
 
@@ -111,7 +113,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (!params || !plan_out) return fail(FRSD_EINVAL, "null argument");
   const frsd_params &p = *params;
   if (p.n_grid < 32 || p.n_grid > 1024 || p.n_grid % 16 != 0 || !is_smooth(p.n_grid))
-    return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b, a multiple of 16, in [32, 1024]");
+    return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b 5^c, a multiple of 16, in [32, 1024]");
   if (p.order < 1 || p.order > 3) return fail(FRSD_EINVAL, "order must be 1 (NGP), 2 (CIC) or 3 (TSC)");
   if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(FRSD_EINVAL, "ell_max must be 0, 2 or 4");
   if (p.precision != FRSD_F32 && p.precision != FRSD_F64) return fail(FRSD_EINVAL, "precision must be 32 or 64");
@@ -147,7 +149,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     if (p.bk_grid) {
       if (p.bk_grid < need || !is_smooth(p.bk_grid) || p.bk_grid > 1024) {
         delete pl;
-        return fail(FRSD_EINVAL, "bk_grid must be 2^a 3^b > 3 n_c and <= 1024");
+        return fail(FRSD_EINVAL, "bk_grid must be 2^a 3^b 5^c > 3 n_c and <= 1024");
       }
       pl->M = p.bk_grid;
     } else {
@@ -256,6 +258,13 @@ extern "C" int frsd_bk_ntriangles(const frsd_plan *plan, int64_t *ntri) {
   clear_error();
   if (!plan || !ntri) return fail(FRSD_EINVAL, "null argument");
   *ntri = plan->ntri;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_bk_grid(const frsd_plan *plan, int32_t *m) {
+  clear_error();
+  if (!plan || !m) return fail(FRSD_EINVAL, "null argument");
+  *m = plan->M;
   return FRSD_OK;
 }
 

@@ -75,6 +75,7 @@ _proto = {
                                         ctypes.c_double, _P]),
     "frsd_pk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_pk_out), _P]),
     "frsd_bk_ntriangles": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "frsd_bk_grid": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "frsd_bk_triangles": (ctypes.c_int, [_P, _P]),
     "frsd_bk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_bk_out), _P]),
     "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
@@ -132,6 +133,12 @@ def frsd_pk_multipoles(plan, ws_ptr, out: frsd_pk_out, stream) -> None:
 def frsd_bk_ntriangles(plan) -> int:
     v = ctypes.c_int64()
     _check(_lib.frsd_bk_ntriangles(plan, ctypes.byref(v)))
+    return v.value
+
+
+def frsd_bk_grid(plan) -> int:
+    v = ctypes.c_int32()
+    _check(_lib.frsd_bk_grid(plan, ctypes.byref(v)))
     return v.value
 
 
@@ -254,6 +261,7 @@ class Plan:
             self.pk_buf[key] = torch.zeros(nb, **f64)
         self.pk_buf["scalars"] = torch.zeros(4, **f64)
         self.ntri = frsd_bk_ntriangles(self.handle) if cfg.bk_nbins > 0 else 0
+        self.bk_grid = frsd_bk_grid(self.handle)
         self.bk_buf = {}
         if self.ntri:
             for key in ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4"):

@@ -28,19 +28,19 @@ def _log(msg):
     sys.stdout.flush()
 
 
-def _cfg(F, prm: est.Params, precision, max_objects):
+def _cfg(F, prm: est.Params, precision, max_objects, m_grid=None):
     return F.Config(n_grid=prm.n_grid, box=prm.box, observer=prm.observer, order=prm.order,
                     interlace=prm.interlace, compensate=prm.compensate, ell_max=prm.ell_max,
                     precision=precision, pk_kmin=prm.pk_kmin, pk_dk=prm.pk_dk, pk_nbins=prm.pk_nbins,
-                    bk_kmin=prm.bk_kmin, bk_dk=prm.bk_dk, bk_nbins=prm.bk_nbins, bk_grid=prm.m_grid,
-                    max_objects=max_objects)
+                    bk_kmin=prm.bk_kmin, bk_dk=prm.bk_dk, bk_nbins=prm.bk_nbins,
+                    bk_grid=prm.m_grid if m_grid is None else m_grid, max_objects=max_objects)
 
 
-def _run_gpu(F, prm, precision, gal, ran, alpha, in_dtype=None):
+def _run_gpu(F, prm, precision, gal, ran, alpha, in_dtype=None, m_grid=None):
     import torch
     dev = torch.device("cuda:0")
     n = len(gal["w"]) + (len(ran["w"]) if ran is not None else 0)
-    plan = F.Plan(_cfg(F, prm, precision, max(n, 1)), device=dev)
+    plan = F.Plan(_cfg(F, prm, precision, max(n, 1), m_grid), device=dev)
     dt = in_dtype or torch.float64
     g = F.device_catalog(gal, dev, dt)
     r = F.device_catalog(ran, dev, dt) if ran is not None else None
@@ -158,6 +158,26 @@ def test_pruned_fft_passes_192(gpu_lib, precision):
         _ORACLE_CACHE["pruned192"] = (gal, ran, alpha, prm, refp, refb)
     gal, ran, alpha, prm, refp, refb = _ORACLE_CACHE["pruned192"]
     out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
+@pytest.mark.parametrize("precision,m_gpu", [(64, 50), (32, 50), (64, 360), (32, 360)])
+def test_radix5_triangle_grids(gpu_lib, precision, m_gpu):
+    """The triangle search on 5-smooth real-space grids: M = 50 (run-time
+    schedule 5, 5, 2) and M = 360 (compiled schedule 3, 3, 5, 8).  Any
+    M > 3 n_c gives the exact closed-triangle sums, so the oracle keeps its
+    own grid (M = 54 here) and the results must agree."""
+    _log(f"case: pk+bk 48^3 bk_grid={m_gpu} precision={precision}")
+    if "radix5" not in _ORACLE_CACHE:
+        gal, ran, alpha, prm = _bk_case(29)
+        fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+        refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+        refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
+        _ORACLE_CACHE["radix5"] = (gal, ran, alpha, prm, refp, refb)
+    gal, ran, alpha, prm, refp, refb = _ORACLE_CACHE["radix5"]
+    assert est.bk_grid(prm) == 54
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha, m_grid=m_gpu)
     _check_pk(out, refp, prm, precision)
     _check_bk(out, refb, prm, precision, plan)
 
