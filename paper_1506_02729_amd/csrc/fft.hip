@@ -18,6 +18,13 @@
 // kept y, the x pass transforms only columns with kept y and z and writes
 // kept x.  Kept indices form two runs, [0, ka) and [N - kb, N).  Entries
 // outside the kept set are never written and never read.
+//
+// Survey sparsity: a survey fills a fraction of the box, and every node
+// column (x, y) out of reach of all objects (colmask 0) is zero in every
+// plane, as is every x slab with no such column (xmask 0).  The z pass skips
+// those rows (no read, no write), the y pass takes them as zero and skips
+// empty x slabs, and the x pass takes empty slabs as zero.  Exact zeros in
+// the butterflies change no rounding, so the result is the dense one.
 #include <algorithm>
 
 #include "device.h"
@@ -51,14 +58,15 @@ __device__ __forceinline__ void column_block(int b, int P, int N, const Keep &k,
 template <typename T, int AXIS>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *data, const T *planar, int N, int P,
                                                            StageList st, const cplx_t<T> *tw_g,
-                                                           long long batch_stride, Keep keep) {
+                                                           long long batch_stride, Keep keep,
+                                                           const uint8_t *__restrict__ colmask,
+                                                           const uint8_t *__restrict__ xmask) {
   using C = cplx_t<T>;
   constexpr int NT = FftTune<T>::threads;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + N;
   const int ld = N + 1;
-  for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
 
   C *mesh = data + (long long)blockIdx.y * batch_stride;
   const long long NN = (long long)N * N;
@@ -66,19 +74,23 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
   if (AXIS == 2) {
     const long long q0 = (long long)blockIdx.x * P;
     const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
+    int any = 0;
+    for (int p = threadIdx.x; p < npen; p += NT) any |= colmask[q0 + p];
+    if (!__syncthreads_or(any)) return;  // every row of the block is empty
+    for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
     const int tot = npen * N;
     const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * N;
     const T *im = re + batch_stride;
     for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
-      lds[p * ld + e] = cmake<C>(re[f], im[f]);
+      lds[p * ld + e] = colmask[q0 + p] ? cmake<C>(re[f], im[f]) : cmake<C>(T(0), T(0));
     }
     __syncthreads();
     lds_fft<C, false, NT, FftTune<T>::pn>(lds, ld, N, npen, st, tw);
     C *dst = mesh + q0 * N;
     for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
-      if (kept(e, N, keep)) dst[f] = lds[p * ld + e];
+      if (colmask[q0 + p] && kept(e, N, keep)) dst[f] = lds[p * ld + e];
     }
     return;
   }
@@ -88,11 +100,15 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
   int z0, npen;
   column_block(blockIdx.x - outer_i * nzb, P, N, keep, z0, npen);
   const int outer = (AXIS == 1) ? outer_i : (outer_i < keep.ka ? outer_i : N - keep.kb + (outer_i - keep.ka));
+  if (AXIS == 1 && !xmask[outer]) return;  // empty x slab: its y-pass output is never read
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
   const long long es = (AXIS == 1) ? N : NN;
   C *col = mesh + ((AXIS == 1) ? (long long)outer * NN : (long long)outer * N) + z0;
+  // rows read as zero: empty node columns (y pass), empty x slabs (x pass)
+  const uint8_t *live = (AXIS == 1) ? colmask + (long long)outer * N : xmask;
   for (int f = threadIdx.x; f < P * N; f += NT) {
     const int e = f / P, p = f - e * P;
-    if (p < npen) lds[p * ld + e] = col[e * es + p];
+    if (p < npen) lds[p * ld + e] = live[e] ? col[e * es + p] : cmake<C>(T(0), T(0));
   }
   __syncthreads();
   lds_fft<C, false, NT, FftTune<T>::pn>(lds, ld, N, npen, st, tw);
@@ -118,49 +134,65 @@ template <typename T, int LEN> constexpr int p_row() {
 template <typename T, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data, const T *planar,
                                                                 const cplx_t<T> *tw_g, long long batch_stride,
-                                                                Keep keep) {
+                                                                Keep keep, const uint8_t *__restrict__ colmask) {
   using C = cplx_t<T>;
   constexpr int P = p_row<T, LEN>(), NT = FwdTune<T>::nt_row;
+  constexpr long long NN = (long long)LEN * LEN;
+  const long long q0 = (long long)blockIdx.x * P;
+  const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
+  // rows of this block that hold data
+  __shared__ unsigned char live[P];
+  int any = 0;
+  for (int p = threadIdx.x; p < P; p += NT) {
+    live[p] = p < npen ? colmask[q0 + p] : 0;
+    any |= live[p];
+  }
+  if (!__syncthreads_or(any)) return;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
   for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
   __syncthreads();
-  constexpr long long NN = (long long)LEN * LEN;
-  const long long q0 = (long long)blockIdx.x * P;
-  const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
   const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * LEN;
   const T *im = re + batch_stride;
   C *dst = data + (long long)blockIdx.y * batch_stride + q0 * LEN;
   fft_pencils<C, LEN, P, NT, false, false>(
-      lds, tw, npen, [&](int p, int e) { return cmake<C>(re[p * LEN + e], im[p * LEN + e]); },
+      lds, tw, npen,
+      [&](int p, int e) {
+        return live[p] ? cmake<C>(re[p * LEN + e], im[p * LEN + e]) : cmake<C>(T(0), T(0));
+      },
       [&](int p, int e, C v) {
-        if (kept(e, LEN, keep)) dst[p * LEN + e] = v;
+        if (live[p] && kept(e, LEN, keep)) dst[p * LEN + e] = v;
       });
 }
 
 template <typename T, int AXIS, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data, const cplx_t<T> *tw_g,
-                                                                long long batch_stride, Keep keep) {
+                                                                long long batch_stride, Keep keep,
+                                                                const uint8_t *__restrict__ colmask,
+                                                                const uint8_t *__restrict__ xmask) {
   using C = cplx_t<T>;
   constexpr int P = FwdTune<T>::p_col, NT = FwdTune<T>::nt_col;
-  extern __shared__ unsigned char smem_raw[];
-  C *tw = reinterpret_cast<C *>(smem_raw);
-  C *lds = tw + LEN;
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
-  __syncthreads();
   constexpr long long NN = (long long)LEN * LEN;
   const int nzb = keep.nba + keep.nbb;
   const int outer_i = blockIdx.x / nzb;
   int z0, npen;
   column_block(blockIdx.x - outer_i * nzb, P, LEN, keep, z0, npen);
   const int outer = (AXIS == 1) ? outer_i : (outer_i < keep.ka ? outer_i : LEN - keep.kb + (outer_i - keep.ka));
+  if (AXIS == 1 && !xmask[outer]) return;  // empty x slab: its y-pass output is never read
+  extern __shared__ unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *lds = tw + LEN;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  __syncthreads();
   constexpr long long es = (AXIS == 1) ? LEN : NN;
   C *col = data + (long long)blockIdx.y * batch_stride +
            ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
+  // rows read as zero: empty node columns (y pass), empty x slabs (x pass)
+  const uint8_t *live = (AXIS == 1) ? colmask + (long long)outer * LEN : xmask;
   // in place: every load happens in the first stage, every store in the last
   fft_pencils<C, LEN, P, NT, false, true>(
-      lds, tw, npen, [&](int p, int e) { return col[e * es + p]; },
+      lds, tw, npen, [&](int p, int e) { return live[e] ? col[e * es + p] : cmake<C>(T(0), T(0)); },
       [&](int p, int e, C v) {
         if (kept(e, LEN, keep)) col[e * es + p] = v;
       });
@@ -186,7 +218,8 @@ static Keep make_keep(int N, int P, int nmax) {
 }
 
 template <typename T, int LEN>
-static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, hipStream_t s) {
+static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
   using C = cplx_t<T>;
   constexpr int PR = p_row<T, LEN>(), PC = FwdTune<T>::p_col;
   constexpr long long NN = (long long)LEN * LEN;
@@ -200,18 +233,18 @@ static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int 
   const dim3 gz((unsigned)((NN + PR - 1) / PR), n_batch), gy((unsigned)LEN * nzb, n_batch),
       gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_row<T, LEN>), gz, dim3(FwdTune<T>::nt_row), sh_row, s, (C *)mesh,
-                                            (const T *)planar, (const C *)tw, bs, k));
+                                            (const T *)planar, (const C *)tw, bs, k, colmask));
   FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_col<T, 1, LEN>), gy, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
-                                            (const C *)tw, bs, k));
+                                            (const C *)tw, bs, k, colmask, xmask));
   FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_col<T, 0, LEN>), gx, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
-                                            (const C *)tw, bs, k));
+                                            (const C *)tw, bs, k, colmask, xmask));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
 static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
-                            hipStream_t s) {
+                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
   using C = cplx_t<T>;
   const int N = f.n;
   const int P = FftTune<T>::pn / N;
@@ -227,28 +260,30 @@ static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar,
   const dim3 gz((unsigned)((NN + P - 1) / P), n_batch), gy((unsigned)N * nzb, n_batch),
       gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2>), gz, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
   FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1>), gy, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
   FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0>), gx, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
-                  hipStream_t s) {
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, s);
+  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
-    default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, s);
+    default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
   }
 }
 
-template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, hipStream_t);
-template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, hipStream_t);
+template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, const uint8_t *,
+                                  const uint8_t *, hipStream_t);
+template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, const uint8_t *,
+                                   const uint8_t *, hipStream_t);
 
 }  // namespace frsd

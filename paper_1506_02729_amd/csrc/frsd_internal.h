@@ -60,6 +60,7 @@ struct Layout {
   size_t tw_fwd = 0, tw_inv = 0, tw_inv64 = 0;  // twiddle tables
   size_t scal_part = 0, scal = 0, reject = 0;    // scalar reductions
   size_t cnt = 0, scan_blk = 0;                  // per-cell counts / offsets, scan partials
+  size_t colmask = 0, xmask = 0;                 // occupied node columns (x, y) and x slabs (uint8)
   size_t slot = 0, cellkey = 0;                  // per-object rank within its cell, cell id
   size_t sorted = 0;                             // sorted object records
   size_t mesh = 0;                               // n_slot complex N^3 meshes
@@ -174,9 +175,11 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
 // FFT passes (fft.hip) --------------------------------------------------------
 // Forward c2c FFT of n_batch N^3 complex meshes given as planar real arrays
 // (re of mesh s = array 2s, im = array 2s+1); output interleaved complex.
+// Node columns (x, y) with colmask 0 and x slabs with xmask 0 are zero in
+// every mesh: they are read as zero, never from memory.
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
-                  hipStream_t s);
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s);
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);

@@ -20,6 +20,12 @@
 // processed in several chunks of the staged order; the accumulators carry
 // over.  Blocks with no object write zeros.
 //
+// Only node columns (x, y) within reach of some object (colmask, built
+// from the cell offsets before the assignment) are written; the FFT passes
+// read every other column as zero.  Blocks with no such column return at
+// once, so the empty part of the box around a survey costs neither
+// assignment nor memory traffic.
+//
 // Output packing: plane array 2s holds the real part and 2s+1 the
 // imaginary part of complex slot s.  With interlacing, the main-grid plane
 // of moment m is the real part and the twin plane the imaginary part of
@@ -94,9 +100,42 @@ __device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const
   if (has_w) acc[kMomW] += s * t0;
 }
 
+// Node columns within reach of an object: colmask[x N + y] = 1 when some
+// cell column (cx, cy) with cx - x and cy - y in [LO, HI] (periodic) holds
+// an object, i.e. offs[(cx N + cy + 1) N] > offs[(cx N + cy) N] for the
+// exclusive scan offs of the cell counts; xmask[x] = 1 when any column of
+// slab x is set.  One workgroup per x.
+template <int P>
+__global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, int N, uint8_t *colmask,
+                                                  uint8_t *xmask) {
+  constexpr int LO = Win<P>::LO, HI = Win<P>::HI;
+  const int x = blockIdx.x;
+  int any = 0;
+  for (int y = threadIdx.x; y < N; y += 256) {
+    int m = 0;
+#pragma unroll
+    for (int dx = LO; dx <= HI; ++dx) {
+      int cx = x + dx;
+      cx += cx < 0 ? N : (cx >= N ? -N : 0);
+#pragma unroll
+      for (int dy = LO; dy <= HI; ++dy) {
+        int cy = y + dy;
+        cy += cy < 0 ? N : (cy >= N ? -N : 0);
+        const long long c0 = ((long long)cx * N + cy) * N;
+        m |= offs[c0 + N] > offs[c0] ? 1 : 0;
+      }
+    }
+    colmask[(long long)x * N + y] = (uint8_t)m;
+    any |= m;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) xmask[x] = any ? 1 : 0;
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs, const Rec4<T> *__restrict__ recs,
-                                                     GridArgs ga, T *__restrict__ planar) {
+                                                     const uint8_t *__restrict__ colmask, GridArgs ga,
+                                                     T *__restrict__ planar) {
   constexpr int LO = Win<P>::LO, RW = Win<P>::HI - Win<P>::LO + 1;
   constexpr int CY = kBY + RW - 1, CZ = kBZ + RW - 1;
   constexpr int NCELL = (kBX + RW - 1) * CY * CZ;
@@ -114,6 +153,8 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
   const int bx = blockIdx.x / (nby * nbz), by = (blockIdx.x / nbz) % nby, bz = blockIdx.x % nbz;
   const int X0 = bx * kBX, Y0 = by * kBY, Z0 = bz * kBZ;
   const int lx = threadIdx.x / (kBY * kBZ), ly = (threadIdx.x / kBZ) % kBY, lz = threadIdx.x % kBZ;
+  const bool live = colmask[(long long)(X0 + lx) * N + (Y0 + ly)] != 0;
+  if (!__syncthreads_or(live)) return;  // no object within reach of any node of the block
 
   // cell table of the grown block: cell e = (ix * CY + iy) * CZ + k is the
   // floor cell (X0 + LO + ix, Y0 + LO + iy, Z0 + LO + k), periodic
@@ -256,6 +297,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
   }
 
   // write every plane of both nodes (contiguous z-runs of the planar output)
+  if (!live) return;
   const long long g = ((long long)(X0 + lx) * N + (Y0 + ly)) * N + (Z0 + lz);
   const long long ps = ga.plane_stride;
   const int n_mom = ga.n_ell_mom + ga.has_w;
@@ -288,12 +330,15 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   ga.interlace = pl->p.interlace;
   for (int d = 0; d < 3; ++d) ga.ou[d] = pl->p.observer[d] / pl->h;
   ga.plane_stride = (long long)N * N * N;
+  FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
+                                               ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
+                                               ws_ptr<uint8_t>(ws, L.xmask)));
   auto kern = k_grid<T, P>;
   FRSD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kGStageBytes));
   const unsigned nblk = (unsigned)((N / kBX) * (N / kBY) * (N / kBZ));
   FRSD_TIMED("grid", s, hipLaunchKernelGGL(kern, dim3(nblk), dim3(kGThreads), kGStageBytes, s,
-                                           ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted), ga,
-                                           ws_ptr<T>(ws, L.planar)));
+                                           ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
+                                           ws_ptr<const uint8_t>(ws, L.colmask), ga, ws_ptr<T>(ws, L.planar)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -310,7 +355,8 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   }
   if (rc) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
-                          ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax, s);
+                          ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax,
+                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
 }
 
 template int run_mesh_assign<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,

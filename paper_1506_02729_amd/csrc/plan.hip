@@ -207,6 +207,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.reject = take(8);
   L.cnt = take(4 * (NNN + 1));
   L.scan_blk = take(4 * ((NNN + 1 + 4095) / 4096 + 1));
+  L.colmask = take((size_t)N * N);
+  L.xmask = take((size_t)N);
   L.slot = take(4 * nobj);
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));
