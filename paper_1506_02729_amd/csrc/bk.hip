@@ -173,45 +173,73 @@ __device__ __forceinline__ int band_index(int e, int M, int nc) {
   return e <= nc ? e + nc : (e >= M - nc ? e - M + nc : -1);
 }
 
+// Per-pencil values of a compiled-length shell pass, set up once per
+// workgroup in LDS so that no element recomputes them.
+struct ShellPenZ {
+  int m2xy;      // n_x^2 + n_y^2 of the pencil's column
+  int col;       // offset of the column in a low-k multipole cube
+  int off[2];    // multipole cube of field a / field b of the pair
+  int lo[2], hi[2];  // |n|^2 range of the field's bin (empty: lo > hi)
+};
+
 template <typename T, bool IND, int LEN>
 __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T> *__restrict__ lowk,
-                                                                 const int16_t *__restrict__ lut, ShellArgs a,
+                                                                 const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
   using C = cplx_t<T>;
   constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
-  __syncthreads();
+  __shared__ ShellPenZ pen[P];
   const int D = a.D, nc = a.nc;
-  const long long DD = (long long)D * D, DDD = DD * D;
+  const int DD = D * D;
+  const int DDD = DD * D;
   const long long npen_all = (long long)a.npair * DD;
   const long long q0 = (long long)blockIdx.x * P;
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  if (threadIdx.x < P) {
+    // pencil q = (pair * D + ix) * D + iy of the batch
+    const int p = threadIdx.x;
+    ShellPenZ v{};
+    v.lo[0] = v.lo[1] = 1;
+    v.hi[0] = v.hi[1] = 0;
+    if (p < npen) {
+      const long long q = q0 + p;
+      const int pair = (int)(q / DD);
+      const int colq = (int)(q - (long long)pair * DD);
+      const int ix = colq / D, iy = colq - ix * D;
+      v.m2xy = (ix - nc) * (ix - nc) + (iy - nc) * (iy - nc);
+      v.col = colq * D;
+      for (int h = 0; h < 2; ++h) {
+        const int f = 2 * (a.pair0 + pair) + h;
+        if (f < a.nfield) {
+          const int2 r = bin_m2[f % a.nb];
+          v.off[h] = (f / a.nb) * DDD;
+          v.lo[h] = r.x;
+          v.hi[h] = r.y;
+        }
+      }
+    }
+    pen[p] = v;
+  }
+  __syncthreads();
   fft_pencils<C, LEN, P, NT, true, false>(
       lds, tw, npen,
       [&](int p, int e) {
         const int kz = band_index(e, LEN, nc);
         if (kz < 0) return cmake<C>(T(0), T(0));
-        const long long q = q0 + p;
-        const int pair = (int)(q / DD);
-        const int colq = (int)(q - (long long)pair * DD);
-        const int ix = colq / D, iy = colq - ix * D;
-        const int nx = ix - nc, ny = iy - nc, nz = kz - nc;
-        const long long m2 = (long long)nx * nx + (long long)ny * ny + (long long)nz * nz;
-        const int b = (m2 > 0 && m2 < a.lut_len) ? lut[m2] : -1;
-        const int fa = 2 * (a.pair0 + pair), fb = fa + 1;
+        const ShellPenZ &v = pen[p];
+        const int m2 = v.m2xy + (kz - nc) * (kz - nc);
         T ar = 0, ai = 0, br = 0, bi = 0;
-        if (b >= 0) {
-          if (fa % a.nb == b) {
-            if (IND) ar = T(1);
-            else { const C v = lowk[(fa / a.nb) * DDD + (long long)colq * D + kz]; ar = v.x; ai = v.y; }
-          }
-          if (fb < a.nfield && fb % a.nb == b) {
-            if (IND) br = T(1);
-            else { const C v = lowk[(fb / a.nb) * DDD + (long long)colq * D + kz]; br = v.x; bi = v.y; }
-          }
+        if (m2 >= v.lo[0] && m2 <= v.hi[0]) {
+          if (IND) ar = T(1);
+          else { const C z = lowk[v.off[0] + v.col + kz]; ar = z.x; ai = z.y; }
+        }
+        if (m2 >= v.lo[1] && m2 <= v.hi[1]) {
+          if (IND) br = T(1);
+          else { const C z = lowk[v.off[1] + v.col + kz]; br = z.x; bi = z.y; }
         }
         return cmake<C>(ar - bi, ai + br);  // Z = A + i B
       },
@@ -226,24 +254,28 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T>
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
-  __syncthreads();
+  // per pencil q = (pair * D + ix) * M + z: its first input element
+  // (buf1 row iy = 0) and first output element (buf2 row y = 0)
+  __shared__ long long src0[P], dst0[P];
   const int D = a.D, nc = a.nc;
   const long long npen_all = (long long)a.npair * D * LEN;
   const long long q0 = (long long)blockIdx.x * P;  // q = (pair * D + ix) * M + z
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  if (threadIdx.x < P) {
+    const long long q = q0 + threadIdx.x, pix = q / LEN, z = q - pix * LEN;
+    src0[threadIdx.x] = pix * D * LEN + z;
+    dst0[threadIdx.x] = pix * LEN * LEN + z;
+  }
+  __syncthreads();
   fft_pencils<C, LEN, P, NT, true, true>(
       lds, tw, npen,
       [&](int p, int e) {
         const int iy = band_index(e, LEN, nc);
         if (iy < 0) return cmake<C>(T(0), T(0));
-        const long long q = q0 + p, pix = q / LEN;
-        return buf1[(pix * D + iy) * LEN + (q - pix * LEN)];
+        return buf1[src0[p] + (long long)iy * LEN];
       },
-      [&](int p, int e, C v) {
-        const long long q = q0 + p, pix = q / LEN;
-        buf2[(pix * LEN + e) * LEN + (q - pix * LEN)] = v;
-      });
+      [&](int p, int e, C v) { buf2[dst0[p] + (long long)e * LEN] = v; });
 }
 
 template <typename T, typename TO, int LEN>
@@ -262,6 +294,7 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T>
   const long long q0 = (long long)blockIdx.x * P;  // q = pair * M^2 + (y * M + z)
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
   // output cell order [y][z][x] (x fastest): contiguous rows of M values
+  // (divisions by the compiled M^2 are multiplications)
   fft_pencils<C, LEN, P, NT, true, true, false>(
       lds, tw, npen,
       [&](int p, int e) {
@@ -298,7 +331,7 @@ static int shell_pipeline_ct(frsd_plan *pl, void *ws, int nfield, const void *tw
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * LEN,
                     nx = (long long)a.npair * LEN * LEN;
     FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z_ct<T, IND, LEN>), dim3((unsigned)((nz + P - 1) / P)), dim3(NT), shmem, s,
-                       ws_ptr<const C>(ws, L.lowk), ws_ptr<const int16_t>(ws, L.bk_lut), a, (const C *)tw,
+                       ws_ptr<const C>(ws, L.lowk), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw,
                        ws_ptr<C>(ws, L.buf1)));
     FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y_ct<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(NT), shmem, s,
                        ws_ptr<const C>(ws, L.buf1), a, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
@@ -572,6 +605,18 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
     FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv64), t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
     auto lb = bin_lut(pl->bk_e2, pl->bk_lut_len);
     FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.bk_lut), lb.data(), lb.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    // |n|^2 range [lo, hi] of every bispectrum bin (bins hold consecutive
+    // integers; an empty bin gets lo > hi)
+    std::vector<int2> m2r(pl->p.bk_nbins, make_int2(1, 0));
+    for (int m = 1; m < pl->bk_lut_len; ++m) {
+      const int b = lb[m];
+      if (b < 0) continue;
+      if (m2r[b].x > m2r[b].y) m2r[b] = make_int2(m, m);
+      else m2r[b].y = m;
+    }
+    for (int m = 1; m < pl->bk_lut_len; ++m)
+      if (lb[m] >= 0 && (m < m2r[lb[m]].x || m > m2r[lb[m]].y)) return fail(FRSD_EINVAL, "bin lookup not monotone");
+    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.bk_m2), m2r.data(), m2r.size() * sizeof(int2), hipMemcpyHostToDevice));
     // contraction tables: data outputs (field of b1 for each ell, b2, b3), then
     // indicator outputs (b1, b2, b3), then the raw int32 triangle list
     const int nb = pl->p.bk_nbins;

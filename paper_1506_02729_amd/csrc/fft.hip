@@ -131,39 +131,49 @@ template <typename T, int LEN> constexpr int p_row() {
   return FwdTune<T>::row_elems / LEN > 0 ? FwdTune<T>::row_elems / LEN : 1;
 }
 
+// Row pass (z), persistent: a fixed grid of workgroups walks the groups of
+// P_ROW rows, slot by slot, and moves on at once from groups whose rows are
+// all empty, so the empty part of the box costs no workgroup launches.
+constexpr unsigned kRowGrid = 4096;
+
 template <typename T, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data, const T *planar,
                                                                 const cplx_t<T> *tw_g, long long batch_stride,
-                                                                Keep keep, const uint8_t *__restrict__ colmask) {
+                                                                Keep keep, const uint8_t *__restrict__ colmask,
+                                                                int n_batch) {
   using C = cplx_t<T>;
   constexpr int P = p_row<T, LEN>(), NT = FwdTune<T>::nt_row;
   constexpr long long NN = (long long)LEN * LEN;
-  const long long q0 = (long long)blockIdx.x * P;
-  const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
-  // rows of this block that hold data
-  __shared__ unsigned char live[P];
-  int any = 0;
-  for (int p = threadIdx.x; p < P; p += NT) {
-    live[p] = p < npen ? colmask[q0 + p] : 0;
-    any |= live[p];
-  }
-  if (!__syncthreads_or(any)) return;
+  constexpr long long NG = (NN + P - 1) / P;  // row groups per mesh
+  __shared__ unsigned char live[P];            // rows of the current group that hold data
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
   for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
-  __syncthreads();
-  const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * LEN;
-  const T *im = re + batch_stride;
-  C *dst = data + (long long)blockIdx.y * batch_stride + q0 * LEN;
-  fft_pencils<C, LEN, P, NT, false, false>(
-      lds, tw, npen,
-      [&](int p, int e) {
-        return live[p] ? cmake<C>(re[p * LEN + e], im[p * LEN + e]) : cmake<C>(T(0), T(0));
-      },
-      [&](int p, int e, C v) {
-        if (live[p] && kept(e, LEN, keep)) dst[p * LEN + e] = v;
-      });
+  for (long long it = blockIdx.x; it < NG * n_batch; it += gridDim.x) {
+    const long long grp = it / n_batch;
+    const int slot = (int)(it - grp * n_batch);
+    const long long q0 = grp * P;
+    const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
+    int any = 0;
+    for (int p = threadIdx.x; p < P; p += NT) {
+      live[p] = p < npen ? colmask[q0 + p] : 0;
+      any |= live[p];
+    }
+    if (!__syncthreads_or(any)) continue;  // (the barrier also publishes tw and live)
+    const T *re = planar + 2 * (long long)slot * batch_stride + q0 * LEN;
+    const T *im = re + batch_stride;
+    C *dst = data + (long long)slot * batch_stride + q0 * LEN;
+    fft_pencils<C, LEN, P, NT, false, false>(
+        lds, tw, npen,
+        [&](int p, int e) {
+          return live[p] ? cmake<C>(re[p * LEN + e], im[p * LEN + e]) : cmake<C>(T(0), T(0));
+        },
+        [&](int p, int e, C v) {
+          if (live[p] && kept(e, LEN, keep)) dst[p * LEN + e] = v;
+        });
+    __syncthreads();  // pencils and live are rewritten by the next group
+  }
 }
 
 template <typename T, int AXIS, int LEN>
@@ -183,13 +193,18 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  // rows read as zero: empty node columns (y pass), empty x slabs (x pass);
+  // the flags sit in LDS so that no load waits on another
+  __shared__ unsigned char live[LEN];
+  const uint8_t *lsrc = (AXIS == 1) ? colmask + (long long)outer * LEN : xmask;
+  for (int i = threadIdx.x; i < LEN; i += NT) {
+    tw[i] = tw_g[i];
+    live[i] = lsrc[i];
+  }
   __syncthreads();
   constexpr long long es = (AXIS == 1) ? LEN : NN;
   C *col = data + (long long)blockIdx.y * batch_stride +
            ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
-  // rows read as zero: empty node columns (y pass), empty x slabs (x pass)
-  const uint8_t *live = (AXIS == 1) ? colmask + (long long)outer * LEN : xmask;
   // in place: every load happens in the first stage, every store in the last
   fft_pencils<C, LEN, P, NT, false, true>(
       lds, tw, npen, [&](int p, int e) { return live[e] ? col[e * es + p] : cmake<C>(T(0), T(0)); },
@@ -230,10 +245,10 @@ static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int 
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   const long long bs = NN * LEN;
-  const dim3 gz((unsigned)((NN + PR - 1) / PR), n_batch), gy((unsigned)LEN * nzb, n_batch),
+  const dim3 gz(kRowGrid), gy((unsigned)LEN * nzb, n_batch),
       gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_row<T, LEN>), gz, dim3(FwdTune<T>::nt_row), sh_row, s, (C *)mesh,
-                                            (const T *)planar, (const C *)tw, bs, k, colmask));
+                                            (const T *)planar, (const C *)tw, bs, k, colmask, n_batch));
   FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_col<T, 1, LEN>), gy, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
                                             (const C *)tw, bs, k, colmask, xmask));
   FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_col<T, 0, LEN>), gx, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,

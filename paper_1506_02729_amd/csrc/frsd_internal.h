@@ -73,6 +73,7 @@ struct Layout {
   size_t pair_tab = 0, tri_dense = 0;             // (b2, b3) of each row; dense sums of the MFMA path
   size_t nt = 0;                                 // N^T per triangle
   size_t pk_lut = 0, bk_lut = 0;                 // |n|^2 -> bin index (int16, -1 outside)
+  size_t bk_m2 = 0;                              // |n|^2 range of every bispectrum bin (int2)
   size_t total = 0;
 };
 

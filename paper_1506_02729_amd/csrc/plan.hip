@@ -241,6 +241,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (p.bk_nbins > 0) {
     pl->bk_lut_len = (int)std::ceil(pl->bk_e2.back());
     L.bk_lut = take(2 * (size_t)pl->bk_lut_len);
+    L.bk_m2 = take(8 * (size_t)p.bk_nbins);
   }
   L.total = off;
   *plan_out = pl;

@@ -182,6 +182,39 @@ def test_radix5_triangle_grids(gpu_lib, precision, m_gpu):
     _check_bk(out, refb, prm, precision, plan)
 
 
+@pytest.mark.parametrize("precision,order,interlace", [(64, 3, True), (32, 3, True), (64, 2, False)])
+def test_sparse_survey_region(gpu_lib, precision, order, interlace):
+    """Objects confined to a region that wraps the periodic x boundary and
+    covers a band of y, plus one isolated pair of objects: most node columns
+    and x slabs are empty, and the occupancy masks (from the cell counts,
+    dilated by the kernel reach across the boundary) must leave the result
+    equal to the dense oracle one."""
+    _log(f"case: sparse survey region order={order} interlace={interlace} precision={precision}")
+    rng = np.random.Generator(np.random.PCG64(31 + order))
+    box, N = 600.0, 48
+
+    def region(n, w):
+        u = rng.random((n, 3))
+        u[:, 0] = (0.25 * u[:, 0] - 0.1) % 1.0    # x in [0.9, 1) and [0, 0.15)
+        u[:, 1] = 0.3 + 0.2 * u[:, 1]             # y in [0.3, 0.5)
+        u[:2] = [[0.55, 0.8, 0.2], [0.56, 0.81, 0.9]]
+        pos = np.minimum(u * box, np.nextafter(box, 0.0))
+        return {"pos": pos, "w": w + 0.4 * rng.random(n), "nbar": np.full(n, 3e-5) * (0.5 + rng.random(n))}
+
+    gal, ran = region(3000, 0.4), region(15000, 0.4)
+    kf = 2 * math.pi / box
+    prm = est.Params(n_grid=N, box=box, observer=(-200.0, 310.0, -150.0), order=order, interlace=interlace,
+                     compensate=True, ell_max=4, pk_kmin=0.5 * kf, pk_dk=1.7 * kf, pk_nbins=13,
+                     bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=5)
+    alpha = 3000 / 15000
+    fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+    refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+    refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
 def test_ell_max_two_and_float32_inputs(gpu_lib):
     _log("case: ell_max=2, float32 catalogue into FP64 plan")
     gal, ran, alpha, prm = _bk_case(3, ell_max=2, nbk=4)
