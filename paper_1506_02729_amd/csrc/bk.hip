@@ -173,6 +173,23 @@ __device__ __forceinline__ int band_index(int e, int M, int nc) {
   return e <= nc ? e + nc : (e >= M - nc ? e - M + nc : -1);
 }
 
+// Shell radius bound of pair `pair` of the batch: the largest |n|^2 in the
+// bins of its two fields.  A column (n_x, n_y) with n_x^2 + n_y^2 above it
+// is zero after the z pass, and a row n_x with n_x^2 above it is zero after
+// the y pass; those are neither written nor read (each pass tests the same
+// bound), so the passes skip them.
+__device__ __forceinline__ int pair_m2max(const int2 *bin_m2, const ShellArgs &a, int pair) {
+  int h = -1;
+  for (int k = 0; k < 2; ++k) {
+    const int f = 2 * (a.pair0 + pair) + k;
+    if (f < a.nfield) {
+      const int2 r = bin_m2[f % a.nb];
+      if (r.x <= r.y) h = max(h, r.y);
+    }
+  }
+  return h;
+}
+
 // Per-pencil values of a compiled-length shell pass, set up once per
 // workgroup in LDS so that no element recomputes them.
 struct ShellPenZ {
@@ -180,6 +197,7 @@ struct ShellPenZ {
   int col;       // offset of the column in a low-k multipole cube
   int off[2];    // multipole cube of field a / field b of the pair
   int lo[2], hi[2];  // |n|^2 range of the field's bin (empty: lo > hi)
+  int live;      // column within the pair's shell radius
 };
 
 template <typename T, bool IND, int LEN>
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T>
   const long long npen_all = (long long)a.npair * DD;
   const long long q0 = (long long)blockIdx.x * P;
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  int live = 0;
   if (threadIdx.x < P) {
     // pencil q = (pair * D + ix) * D + iy of the batch
     const int p = threadIdx.x;
@@ -221,9 +239,13 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T>
           v.hi[h] = r.y;
         }
       }
+      v.live = v.m2xy <= pair_m2max(bin_m2, a, pair) ? 1 : 0;
     }
     pen[p] = v;
+    live = v.live;
   }
+  if (!__syncthreads_or(live)) return;  // every column of the block lies outside its shells
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
   __syncthreads();
   fft_pencils<C, LEN, P, NT, true, false>(
       lds, tw, npen,
@@ -231,6 +253,7 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T>
         const int kz = band_index(e, LEN, nc);
         if (kz < 0) return cmake<C>(T(0), T(0));
         const ShellPenZ &v = pen[p];
+        if (!v.live) return cmake<C>(T(0), T(0));
         const int m2 = v.m2xy + (kz - nc) * (kz - nc);
         T ar = 0, ai = 0, br = 0, bi = 0;
         if (m2 >= v.lo[0] && m2 <= v.hi[0]) {
@@ -243,43 +266,59 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T>
         }
         return cmake<C>(ar - bi, ai + br);  // Z = A + i B
       },
-      [&](int p, int e, C v) { buf1[(q0 + p) * LEN + e] = v; });
+      [&](int p, int e, C v) {
+        if (pen[p].live) buf1[(q0 + p) * LEN + e] = v;
+      });
 }
 
 template <typename T, int LEN>
-__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T> *__restrict__ buf1, ShellArgs a,
+__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T> *__restrict__ buf1,
+                                                                 const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
   using C = cplx_t<T>;
   constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
-  // per pencil q = (pair * D + ix) * M + z: its first input element
-  // (buf1 row iy = 0) and first output element (buf2 row y = 0)
+  // per pencil q = (pair * D + ix) * M + z: its first input element (buf1
+  // row iy = 0), first output element (buf2 row y = 0), n_x^2 and the
+  // pair's shell radius bound (rows with n_x^2 + n_y^2 above it are zero;
+  // a pencil with n_x^2 above it is zero and not written)
   __shared__ long long src0[P], dst0[P];
+  __shared__ int nx2[P], hmax[P];
   const int D = a.D, nc = a.nc;
   const long long npen_all = (long long)a.npair * D * LEN;
   const long long q0 = (long long)blockIdx.x * P;  // q = (pair * D + ix) * M + z
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
-  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
+  int live = 0;
   if (threadIdx.x < P) {
-    const long long q = q0 + threadIdx.x, pix = q / LEN, z = q - pix * LEN;
-    src0[threadIdx.x] = pix * D * LEN + z;
-    dst0[threadIdx.x] = pix * LEN * LEN + z;
+    const int p = threadIdx.x;
+    const long long q = q0 + p, pix = q / LEN, z = q - pix * LEN;
+    const int pair = (int)(pix / D), ix = (int)(pix - (long long)pair * D);
+    src0[p] = pix * D * LEN + z;
+    dst0[p] = pix * LEN * LEN + z;
+    nx2[p] = (ix - nc) * (ix - nc);
+    hmax[p] = p < npen ? pair_m2max(bin_m2, a, pair) : -1;
+    live = nx2[p] <= hmax[p];
   }
+  if (!__syncthreads_or(live)) return;
+  for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
   __syncthreads();
   fft_pencils<C, LEN, P, NT, true, true>(
       lds, tw, npen,
       [&](int p, int e) {
         const int iy = band_index(e, LEN, nc);
-        if (iy < 0) return cmake<C>(T(0), T(0));
+        if (iy < 0 || nx2[p] + (iy - nc) * (iy - nc) > hmax[p]) return cmake<C>(T(0), T(0));
         return buf1[src0[p] + (long long)iy * LEN];
       },
-      [&](int p, int e, C v) { buf2[dst0[p] + (long long)e * LEN] = v; });
+      [&](int p, int e, C v) {
+        if (nx2[p] <= hmax[p]) buf2[dst0[p] + (long long)e * LEN] = v;
+      });
 }
 
 template <typename T, typename TO, int LEN>
-__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T> *__restrict__ buf2, ShellArgs a,
+__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T> *__restrict__ buf2,
+                                                                 const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, TO *shells) {
   using C = cplx_t<T>;
   constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
@@ -293,14 +332,23 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T>
   const long long npen_all = (long long)a.npair * MM;
   const long long q0 = (long long)blockIdx.x * P;  // q = pair * M^2 + (y * M + z)
   const int npen = (int)((q0 + P <= npen_all) ? P : (npen_all - q0));
+  // rows n_x beyond the pair's shell radius were not written by the y pass.
+  // The P pencils span at most two pairs (P < M^2): their bounds are kept
+  // in registers, h0 below pencil index qb and h1 from it on.
+  const int pair0 = (int)(q0 / MM);
+  const long long qb = (long long)(pair0 + 1) * MM;
+  const int h0 = pair_m2max(bin_m2, a, pair0);
+  const int h1 = pair0 + 1 < a.npair ? pair_m2max(bin_m2, a, pair0 + 1) : -1;
   // output cell order [y][z][x] (x fastest): contiguous rows of M values
   // (divisions by the compiled M^2 are multiplications)
   fft_pencils<C, LEN, P, NT, true, true, false>(
       lds, tw, npen,
       [&](int p, int e) {
         const int ix = band_index(e, LEN, nc);
-        if (ix < 0) return cmake<C>(T(0), T(0));
-        const long long q = q0 + p, pair = q / MM;
+        const long long q = q0 + p;
+        const int hm = q < qb ? h0 : h1;
+        if (ix < 0 || (ix - nc) * (ix - nc) > hm) return cmake<C>(T(0), T(0));
+        const long long pair = q / MM;
         return buf2[(pair * D + ix) * MM + (q - pair * MM)];
       },
       [&](int p, int e, C v) {
@@ -334,9 +382,10 @@ static int shell_pipeline_ct(frsd_plan *pl, void *ws, int nfield, const void *tw
                        ws_ptr<const C>(ws, L.lowk), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw,
                        ws_ptr<C>(ws, L.buf1)));
     FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y_ct<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(NT), shmem, s,
-                       ws_ptr<const C>(ws, L.buf1), a, (const C *)tw, ws_ptr<C>(ws, L.buf2)));
+                       ws_ptr<const C>(ws, L.buf1), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw,
+                       ws_ptr<C>(ws, L.buf2)));
     FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x_ct<T, TO, LEN>), dim3((unsigned)((nx + P - 1) / P)), dim3(NT), shmem, s,
-                       ws_ptr<const C>(ws, L.buf2), a, (const C *)tw, shells));
+                       ws_ptr<const C>(ws, L.buf2), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw, shells));
     FRSD_LAUNCH_CHECK();
   }
   return FRSD_OK;
