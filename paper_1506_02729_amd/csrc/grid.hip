@@ -31,6 +31,8 @@
 // of moment m is the real part and the twin plane the imaginary part of
 // slot m; without interlacing, moments 2s and 2s+1 share slot s.  The first
 // FFT pass reads the planar arrays and writes interleaved complex meshes.
+#include <type_traits>
+
 #include "device.h"
 #include "frsd_internal.h"
 
@@ -130,6 +132,27 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
   }
   any = __syncthreads_or(any);
   if (threadIdx.x == 0) xmask[x] = any ? 1 : 0;
+}
+
+// The same sum with the rank-4 monomials taken as (s q_a) q_b, a < 3: no
+// rank-4 table is held across a ring of nodes.
+__device__ __forceinline__ void add_moments_u(float *acc, float s, float t0, const float *q, int n_ell_mom,
+                                              bool has_w) {
+  acc[0] += s;
+  if (n_ell_mom > 1) {
+    const float u0 = s * q[0], u1 = s * q[1], u2 = s * q[2];
+    acc[1] += u0; acc[2] += u1; acc[3] += u2;
+    acc[4] += s * q[3]; acc[5] += s * q[4]; acc[6] += s * q[5];
+    if (n_ell_mom > 7) {
+      // xxxx yyyy zzzz xxxy xxxz yyyx yyyz zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy
+      acc[7] += u0 * q[0]; acc[8] += u1 * q[1]; acc[9] += u2 * q[2];
+      acc[10] += u0 * q[3]; acc[11] += u0 * q[5]; acc[12] += u1 * q[3];
+      acc[13] += u1 * q[4]; acc[14] += u2 * q[5]; acc[15] += u2 * q[4];
+      acc[16] += u0 * q[1]; acc[17] += u1 * q[2]; acc[18] += u2 * q[0];
+      acc[19] += u0 * q[4]; acc[20] += u1 * q[5]; acc[21] += u2 * q[3];
+    }
+  }
+  if (has_w) acc[kMomW] += s * t0;
 }
 
 template <typename T, int P>
@@ -316,6 +339,254 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
   if (!ga.interlace && (n_mom & 1)) planar[(long long)n_mom * ps + g] = T(0);
 }
 
+// ---------------------------------------------------------------------------
+// x-sweep assignment (FP32 plans, N a multiple of 64).
+//
+// A workgroup owns a 4 (y) x 64 (z) patch of node columns and sweeps it
+// along x over 64 nodes.  At each cell slab x = c it stages the objects of
+// the slab cells that reach the patch, and every thread adds each object of
+// its window to the ring of the RING nodes of its column that the slab
+// reaches (nodes c - HI .. c - LO); the lowest ring node is then complete
+// and is written out.  Per visit the line of sight, the moments and the y
+// and z kernel weights are computed once for all ring nodes, and the x
+// weights (times the object weight) once per staged object, which makes
+// the sweep several times cheaper in instructions than the per-node gather
+// above.  Main and twin grids are separate passes (separate windows and
+// rings).  The ring slots are compile-time indices: the cell loop is
+// unrolled by RING.
+// ---------------------------------------------------------------------------
+constexpr int kSY = 4, kSZ = 64, kSX = 64;
+constexpr int kSThreads = kSY * kSZ;                   // one node column per thread
+constexpr int kSCap = 1536;                            // staged objects per chunk (32 B each)
+constexpr int kSCellsMax = (kSY + 3) * (kSZ + 3);      // slab cells for a ring of 4
+static_assert(kSThreads == kSX * kSY, "one liveness test per thread");
+
+// Cells [LO, HI] (relative to node n) reaching the main node n or the twin
+// node n + 1/2 of each assignment order.
+template <int P, bool TWIN> struct SweepWin;
+template <> struct SweepWin<3, false> { static constexpr int LO = -2, HI = 1; };
+template <> struct SweepWin<3, true> { static constexpr int LO = -1, HI = 1; };
+template <> struct SweepWin<2, false> { static constexpr int LO = -1, HI = 0; };
+template <> struct SweepWin<2, true> { static constexpr int LO = -1, HI = 1; };
+template <> struct SweepWin<1, false> { static constexpr int LO = -1, HI = 0; };
+template <> struct SweepWin<1, true> { static constexpr int LO = 0, HI = 0; };
+
+// Staged object: a = (x fraction in cell c, y and z relative to the patch
+// origin, t0); w[r] = t0 W(x - node_r) for the ring nodes r of cell c.
+struct SweepRec {
+  float4 a;
+  float4 w;
+};
+
+template <int P, bool TWIN>
+__global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict__ offs,
+                                                          const Rec4<float> *__restrict__ recs,
+                                                          const uint8_t *__restrict__ colmask, GridArgs ga,
+                                                          float *__restrict__ planar) {
+  using Wn = SweepWin<P, TWIN>;
+  constexpr int LO = Wn::LO, HI = Wn::HI, RING = HI - LO + 1;
+  constexpr int CY = kSY + RING - 1, CZ = kSZ + RING - 1, NSC = CY * CZ;
+  static_assert(NSC <= kSCellsMax && RING <= 4, "slab too large");
+  constexpr float SH = TWIN ? 0.5f : 0.0f;  // node offset of the pass
+  __shared__ SweepRec st[kSCap];
+  __shared__ int cst[kSCellsMax + 1];  // staged start of each slab cell (e = iy * CZ + iz)
+  __shared__ int gsrc[kSCellsMax];     // first sorted record of each slab cell
+  __shared__ int wtot[kSThreads / 64];
+
+  const int N = ga.N;
+  const int nyb = N / kSY, nzb = N / kSZ;
+  const int bz = blockIdx.x % nzb, by = (blockIdx.x / nzb) % nyb, bx = blockIdx.x / (nzb * nyb);
+  const int X0 = bx * kSX, Y0 = by * kSY, Z0 = bz * kSZ;
+  const int ly = threadIdx.x / kSZ, lz = threadIdx.x % kSZ;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  {  // patches with no node in reach of an object write nothing
+    const int t = threadIdx.x;
+    const int live = colmask[(long long)(X0 + t / kSY) * N + (Y0 + t % kSY)];
+    if (!__syncthreads_or(live)) return;
+  }
+  const bool has_w = ga.has_w != 0;
+  const int nmom = ga.n_ell_mom;
+  const float ny_ = (float)ly + SH, nz_ = (float)lz + SH;  // node position relative to (Y0, Z0)
+  const float nf = (float)N;
+  const float oyr = (float)((double)Y0 - ga.ou[1]), ozr = (float)((double)Z0 - ga.ou[2]);
+  // patches whose slab crosses the periodic boundary in y or z rebuild the
+  // true position of the object for the line of sight
+  const bool edge = Y0 + LO < 0 || Z0 + LO < 0 || Y0 + kSY - 1 + HI >= N || Z0 + kSZ - 1 + HI >= N;
+  const float loy = (float)(-Y0), loz = (float)(-Z0), hiy = (float)(N - Y0), hiz = (float)(N - Z0);
+
+  float acc[RING][kMaxMom];
+#pragma unroll
+  for (int r = 0; r < RING; ++r)
+#pragma unroll
+    for (int m = 0; m < kMaxMom; ++m) acc[r][m] = 0.f;
+
+  const long long ps = ga.plane_stride;
+  constexpr int NSTEP = kSX + RING - 1;
+
+  auto step = [&](const int sidx, auto kc) {
+    constexpr int k = decltype(kc)::value;  // sidx % RING
+    const int c = X0 + LO + sidx;            // cell slab (unwrapped)
+    const int cw = c < 0 ? c + N : (c >= N ? c - N : c);
+    const float xo = (float)((double)cw - ga.ou[0]);
+
+    // ---- slab cell table and exclusive scan of the counts ----
+    int cnt[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + h * kSThreads;
+      if (e < NSC) {
+        const int iy = e / CZ, iz = e - iy * CZ;
+        int cy = Y0 + LO + iy, cz = Z0 + LO + iz;
+        cy += cy < 0 ? N : (cy >= N ? -N : 0);
+        cz += cz < 0 ? N : (cz >= N ? -N : 0);
+        const long long idx = ((long long)cw * N + cy) * N + cz;
+        const int a0 = offs[idx];
+        gsrc[e] = a0;
+        cnt[h] = offs[idx + 1] - a0;
+      }
+    }
+    // thread t holds cells t and t + 256: scan the 512 slots in two halves
+    int incl0 = cnt[0], incl1 = cnt[1];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t0 = __shfl_up(incl0, o, 64), t1 = __shfl_up(incl1, o, 64);
+      if (lane >= o) { incl0 += t0; incl1 += t1; }
+    }
+    if (lane == 63) wtot[wave] = incl0;
+    __syncthreads();
+    int pre0 = 0, tot0 = 0;
+#pragma unroll
+    for (int w = 0; w < kSThreads / 64; ++w) {
+      const int v = wtot[w];
+      pre0 += w < wave ? v : 0;
+      tot0 += v;
+    }
+    __syncthreads();
+    if (lane == 63) wtot[wave] = incl1;
+    __syncthreads();
+    int pre1 = tot0, total = tot0;
+#pragma unroll
+    for (int w = 0; w < kSThreads / 64; ++w) {
+      const int v = wtot[w];
+      pre1 += w < wave ? v : 0;
+      total += v;
+    }
+    {
+      const int e0 = threadIdx.x, e1 = threadIdx.x + kSThreads;
+      if (e0 < NSC) cst[e0] = pre0 + incl0 - cnt[0];
+      if (e1 < NSC) cst[e1] = pre1 + incl1 - cnt[1];
+      if (threadIdx.x == 0) cst[NSC] = total;
+    }
+
+    for (int s0 = 0; s0 < total; s0 += kSCap) {
+      const int s1 = min(total, s0 + kSCap);
+      __syncthreads();  // cell table ready / previous chunk consumed
+      for (int i = s0 + (int)threadIdx.x; i < s1; i += kSThreads) {
+        int lo = 0, hi = NSC;  // cst[lo] <= i < cst[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (cst[mid] <= i) lo = mid; else hi = mid;
+        }
+        const Rec4<float> g = recs[gsrc[lo] + (i - cst[lo])];
+        const int iy = lo / CZ, iz = lo - iy * CZ;
+        SweepRec r;
+        r.a = make_float4(g.x, (float)(LO + iy) + g.y, (float)(LO + iz) + g.z, g.w);
+        float wx[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < RING; ++q) wx[q] = g.w * kernel_w<float, P>(g.x + (float)(HI - q) - SH);
+        r.w = make_float4(wx[0], wx[1], wx[2], wx[3]);
+        st[i - s0] = r;
+      }
+      __syncthreads();
+
+      // this thread's window: RING runs (y cells ly..ly+RING-1), each the
+      // RING z cells lz..lz+RING-1; one flat stream, uniform trip count per
+      // wavefront (finished threads add zero)
+      int mine = 0;
+#pragma unroll
+      for (int j = 0; j < RING; ++j) {
+        const int e = (ly + j) * CZ + lz;
+        mine += max(0, min(cst[e + RING], s1) - max(cst[e], s0));
+      }
+      int trips = mine;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) trips = max(trips, __shfl_xor(trips, o, 64));
+      int wi = 0, j = 0, je = 0;
+      auto advance = [&]() {
+#pragma unroll 1
+        while (j >= je && wi < RING) {
+          const int e = (ly + wi) * CZ + lz;
+          j = max(cst[e], s0) - s0;
+          je = min(cst[e + RING], s1) - s0;
+          ++wi;
+        }
+      };
+      advance();
+      bool nvalid = j < je;
+      SweepRec nr = st[nvalid ? j : 0];
+#pragma unroll 1
+      for (int t = 0; t < trips; ++t) {
+        SweepRec r = nr;
+        if (!nvalid) {
+          r.a.w = 0.f;
+          r.w = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        j += nvalid ? 1 : 0;
+        advance();
+        nvalid = j < je;
+        nr = st[nvalid ? j : 0];
+        const float wyz = kernel_w<float, P>(r.a.y - ny_) * kernel_w<float, P>(r.a.z - nz_);
+        // line of sight from the true position
+        float px = xo + r.a.x, py = oyr + r.a.y, pz = ozr + r.a.z;
+        if (edge) {
+          py += r.a.y < loy ? nf : (r.a.y >= hiy ? -nf : 0.f);
+          pz += r.a.z < loz ? nf : (r.a.z >= hiz ? -nf : 0.f);
+        }
+        const float r2 = px * px + py * py + pz * pz;
+        const float ir = r2 > 0.f ? rsqrt_t(r2) : 0.f;
+        const float hx = px * ir, hy = py * ir, hz = pz * ir;
+        const float q[6] = {hx * hx, hy * hy, hz * hz, hx * hy, hy * hz, hz * hx};
+        const float wr[4] = {r.w.x, r.w.y, r.w.z, r.w.w};
+#pragma unroll
+        for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w);
+      }
+    }
+
+    // the lowest ring node (c - HI) is complete: written when it belongs to
+    // the workgroup (the first RING - 1 steps only warm the ring up), and its
+    // slot is cleared for the node entering the ring at the next step
+    float *a = acc[k % RING];
+    if (sidx >= RING - 1) {
+      const int n = X0 + sidx - (RING - 1);
+      if (colmask[(long long)n * N + Y0 + ly]) {
+        const long long g = ((long long)n * N + (Y0 + ly)) * N + (Z0 + lz);
+#pragma unroll
+        for (int id = 0; id < kMaxMom; ++id) {
+          const bool present = id < nmom || (id == kMomW && has_w);
+          if (!present) continue;
+          const int pos = id < nmom ? id : nmom;
+          if (ga.interlace) planar[(2LL * pos + (TWIN ? 1 : 0)) * ps + g] = a[id];
+          else planar[(long long)pos * ps + g] = a[id];
+        }
+        if (!TWIN && !ga.interlace && ((nmom + (has_w ? 1 : 0)) & 1))
+          planar[(long long)(nmom + (has_w ? 1 : 0)) * ps + g] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxMom; ++m) a[m] = 0.f;
+    __syncthreads();  // slab buffers are rewritten by the next step
+  };
+
+#pragma unroll 1
+  for (int s0 = 0; s0 < NSTEP; s0 += RING) {
+    if (s0 + 0 < NSTEP) step(s0 + 0, std::integral_constant<int, 0>{});
+    if constexpr (RING > 1) if (s0 + 1 < NSTEP) step(s0 + 1, std::integral_constant<int, 1>{});
+    if constexpr (RING > 2) if (s0 + 2 < NSTEP) step(s0 + 2, std::integral_constant<int, 2>{});
+    if constexpr (RING > 3) if (s0 + 3 < NSTEP) step(s0 + 3, std::integral_constant<int, 3>{});
+  }
+}
+
 template <typename T, int P>
 static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   const Layout &L = pl->L;
@@ -333,6 +604,22 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
                                                ws_ptr<uint8_t>(ws, L.xmask)));
+  if constexpr (std::is_same<T, float>::value) {
+    if (N % kSX == 0 && N % kSZ == 0) {
+      const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
+      FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<P, false>), dim3(nblk), dim3(kSThreads), 0, s,
+                                               ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<float>>(ws, L.sorted),
+                                               ws_ptr<const uint8_t>(ws, L.colmask), ga, ws_ptr<float>(ws, L.planar)));
+      if (ga.interlace)
+        FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<P, true>), dim3(nblk), dim3(kSThreads), 0, s,
+                                                      ws_ptr<const int>(ws, L.cnt),
+                                                      ws_ptr<const Rec4<float>>(ws, L.sorted),
+                                                      ws_ptr<const uint8_t>(ws, L.colmask), ga,
+                                                      ws_ptr<float>(ws, L.planar)));
+      FRSD_LAUNCH_CHECK();
+      return FRSD_OK;
+    }
+  }
   auto kern = k_grid<T, P>;
   FRSD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kGStageBytes));
   const unsigned nblk = (unsigned)((N / kBX) * (N / kBY) * (N / kBZ));

@@ -215,6 +215,20 @@ def test_sparse_survey_region(gpu_lib, precision, order, interlace):
     _check_bk(out, refb, prm, precision, plan)
 
 
+@pytest.mark.parametrize("order,interlace", [(1, True), (2, True), (3, True), (1, False), (3, False)])
+def test_fp32_assignment_orders_64(gpu_lib, order, interlace):
+    """FP32 plans on N = 64 (a multiple of 64: the x-sweep assignment) for
+    every order with and without interlacing, against the FP64 oracle."""
+    _log(f"case: pk+bk 64^3 FP32 order={order} interlace={interlace}")
+    gal, ran, alpha, prm = _bk_case(41 + order, N=64, order=order, interlace=interlace, n_gal=4000, n_ran=20000)
+    fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+    refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+    refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
+    out, plan = _run_gpu(gpu_lib, prm, 32, gal, ran, alpha)
+    _check_pk(out, refp, prm, 32)
+    _check_bk(out, refb, prm, 32, plan)
+
+
 def test_ell_max_two_and_float32_inputs(gpu_lib):
     _log("case: ell_max=2, float32 catalogue into FP64 plan")
     gal, ran, alpha, prm = _bk_case(3, ell_max=2, nbk=4)
