@@ -4,7 +4,7 @@ One step = one request: a synthetic BOSS-like mock through the whole hot path:
 ingest + sort, interlaced TSC assignment of the 22 moment meshes and the
 w^2 mesh, their forward FFTs, multipole combination and binning into
 P_0, P_2, P_4 (60 bins to k = 0.3 h/Mpc), shell-filtered inverse FFTs on the
-M = 360 grid and the triple-product sums of B_0, B_2, B_4 over all 5416
+M = 343 grid and the triple-product sums of B_0, B_2, B_4 over all 5416
 triangles of 37 bins of width 3 k_f up to k = 0.2 h/Mpc.  The served FP32
 measurement is a closed loop of --steps requests cycling a pool of --mocks
 distinct mocks (galaxy catalogues of distinct seeds sharing one random
@@ -46,12 +46,12 @@ def workload(quick: bool):
     kf = 2 * math.pi / box
     if quick:
         return dict(name="Q256: lognormal mock 2.0e5 galaxies + 1.0e7 randoms, N=256 TSC interlaced, "
-                         "P_ell 45 bins to k=0.225, B_ell 37 bins of 3k_f (5416 triangles), M=360",
+                         "P_ell 45 bins to k=0.225, B_ell 37 bins of 3k_f (5416 triangles), M=343",
                     n_mesh=256, n_gal=2.0e5, n_ran=10_000_000, pk_dk=0.005, pk_nbins=45,
                     bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
     return dict(name="H512: lognormal mock 8.0e5 galaxies + 4.0e7 randoms in a 3500 Mpc/h box, N=512 TSC "
                      "interlaced, 23 moment meshes, P_ell l=0,2,4 in 60 bins of 0.005 to k=0.3, B_ell l=0,2,4 "
-                     "over 5416 triangles of 37 bins of 3k_f to k=0.202, M=360",
+                     "over 5416 triangles of 37 bins of 3k_f to k=0.202, M=343",
                 n_mesh=512, n_gal=8.0e5, n_ran=40_000_000, pk_dk=0.005, pk_nbins=60,
                 bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
 

@@ -60,7 +60,7 @@ typedef struct frsd_plan frsd_plan;
 
 /* Estimator parameters (host struct, copied by frsd_plan_create). */
 typedef struct {
-  int32_t n_grid;      /* N, FFT mesh side: 2^a 3^b 5^c, multiple of 16, 32..1024     */
+  int32_t n_grid;      /* N, FFT mesh side: 2^a 3^b 5^c 7^d, multiple of 16, 32..1024 */
   int32_t order;       /* mass assignment order p: 1 NGP, 2 CIC, 3 TSC                 */
   int32_t interlace;   /* 1: interlaced twin grid at half-cell offset (Sec. III.A)    */
   int32_t compensate;  /* 1: divide by prod_d sinc(pi n_d / N)^p                      */
@@ -73,7 +73,7 @@ typedef struct {
   double bk_kmin, bk_dk; /* bispectrum bins (h/Mpc); top edge <= k_Nyquist            */
   int32_t bk_nbins;      /* 0: no bispectrum                                          */
   int32_t bk_grid;       /* M, real-space grid of the triangle search; 0: smallest
-                            2^a 3^b 5^c with M > 3 n_c (n_c = largest integer below the
+                            2^a 3^b 5^c 7^d with M > 3 n_c (n_c = largest integer below the
                             top bispectrum edge in k_f units), which makes the grid
                             sum equal to the exact closed-triangle sum              */
   int64_t max_objects;   /* capacity: galaxies + randoms per frsd_mesh_assign call    */
@@ -147,7 +147,7 @@ int frsd_bk_ntriangles(const frsd_plan *plan, int64_t *ntri);
 int frsd_bk_triangles(const frsd_plan *plan, int32_t *b123);
 
 /* Side M of the real-space grid of the triangle search (Sec. III.B eqs.
- * (Factorize),(F_k)): params.bk_grid, or the smallest 2^a 3^b 5^c above
+ * (Factorize),(F_k)): params.bk_grid, or the smallest 2^a 3^b 5^c 7^d above
  * 3 n_c; 0 without bispectrum.  FRSD_EINVAL on a null argument. */
 int frsd_bk_grid(const frsd_plan *plan, int32_t *m);
 

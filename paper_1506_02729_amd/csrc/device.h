@@ -92,6 +92,35 @@ template <typename C, bool INV> __device__ __forceinline__ void dft5(C *v) {
   v[2] = cadd(a2, b2); v[3] = csub(a2, b2);
 }
 
+// 7-point DFT, the same split over the 3 conjugate pairs: with t_j =
+// x_j + x_{7-j}, d_j = x_j - x_{7-j} (j = 1, 2, 3), c_k = cos(2 pi k / 7),
+// s_k = sin(2 pi k / 7),
+//   X_m, X_{7-m} = x0 + sum_j c_{mj} t_j -/+ i sum_j s_{mj} d_j   (m = 1, 2, 3),
+// indices mj taken mod 7 with c_{7-k} = c_k and s_{7-k} = -s_k (signs of i
+// swapped for INV).
+template <typename C, bool INV> __device__ __forceinline__ void dft7(C *v) {
+  using S = decltype(C{}.x);
+  const S c1 = S(0.6234898018587335305250048840042398106323);   // cos(2 pi / 7)
+  const S c2 = S(-0.2225209339563144042889025644967947594664);  // cos(4 pi / 7)
+  const S c3 = S(-0.9009688679024191262361023195074450511659);  // cos(6 pi / 7)
+  const S s1 = S(0.7818314824680298087084445266740577502323);   // sin(2 pi / 7)
+  const S s2 = S(0.9749279121818236070181316829939312172327);   // sin(4 pi / 7)
+  const S s3 = S(0.4338837391175581204757683328483587546099);   // sin(6 pi / 7)
+  const C x0 = v[0];
+  const C t1 = cadd(v[1], v[6]), t2 = cadd(v[2], v[5]), t3 = cadd(v[3], v[4]);
+  const C d1 = csub(v[1], v[6]), d2 = csub(v[2], v[5]), d3 = csub(v[3], v[4]);
+  const C a1 = cadd(x0, cadd(cadd(cscale(t1, c1), cscale(t2, c2)), cscale(t3, c3)));
+  const C a2 = cadd(x0, cadd(cadd(cscale(t1, c2), cscale(t2, c3)), cscale(t3, c1)));
+  const C a3 = cadd(x0, cadd(cadd(cscale(t1, c3), cscale(t2, c1)), cscale(t3, c2)));
+  const C b1 = cmul_mi<C, INV>(cadd(cadd(cscale(d1, s1), cscale(d2, s2)), cscale(d3, s3)));
+  const C b2 = cmul_mi<C, INV>(csub(csub(cscale(d1, s2), cscale(d2, s3)), cscale(d3, s1)));
+  const C b3 = cmul_mi<C, INV>(cadd(csub(cscale(d1, s3), cscale(d2, s1)), cscale(d3, s2)));
+  v[0] = cadd(x0, cadd(cadd(t1, t2), t3));
+  v[1] = cadd(a1, b1); v[6] = csub(a1, b1);
+  v[2] = cadd(a2, b2); v[5] = csub(a2, b2);
+  v[3] = cadd(a3, b3); v[4] = csub(a3, b3);
+}
+
 template <typename C, bool INV> __device__ __forceinline__ void dft8(C *v) {
   using S = decltype(C{}.x);
   const S r = S(0.7071067811865475244008443621048490392848);  // 1/sqrt(2)
@@ -117,6 +146,7 @@ template <typename C, int R, bool INV> __device__ __forceinline__ void dftR(C *v
   else if constexpr (R == 3) dft3<C, INV>(v[0], v[1], v[2]);
   else if constexpr (R == 4) dft4<C, INV>(v[0], v[1], v[2], v[3]);
   else if constexpr (R == 5) dft5<C, INV>(v);
+  else if constexpr (R == 7) dft7<C, INV>(v);
   else dft8<C, INV>(v);
 }
 
@@ -176,12 +206,14 @@ struct StageList {
   int radix[12];
 };
 
-// Compile-time radix schedule of a length LEN = 2^a 3^b 5^c (same order as
-// the host schedule: all factors 3, then 5s, then 8s, then one 4 and/or one 2).
+// Compile-time radix schedule of a length LEN = 2^a 3^b 5^c 7^d (same order
+// as the host schedule: all factors 3, then 5s, then 7s, then 8s, then one 4
+// and/or one 2).
 constexpr int ct_radix(int len, int s) {
   int m = len, k = 0;
   while (m % 3 == 0) { if (k == s) return 3; m /= 3; ++k; }
   while (m % 5 == 0) { if (k == s) return 5; m /= 5; ++k; }
+  while (m % 7 == 0) { if (k == s) return 7; m /= 7; ++k; }
   while (m % 8 == 0) { if (k == s) return 8; m /= 8; ++k; }
   if (m % 4 == 0) { if (k == s) return 4; m /= 4; ++k; }
   if (m % 2 == 0) { if (k == s) return 2; m /= 2; ++k; }
@@ -204,6 +236,7 @@ __device__ void lds_fft(C *lds, int ld, int n, int P, const StageList &st, const
     else if (R == 4) stockham_stage<C, 4, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else if (R == 2) stockham_stage<C, 2, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else if (R == 5) stockham_stage<C, 5, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
+    else if (R == 7) stockham_stage<C, 7, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     else stockham_stage<C, 3, INV, THREADS, PN>(lds, ld, n, P, Ns, tw);
     Ns *= R;
   }
@@ -304,10 +337,10 @@ template <typename T> struct FftTune {
   static constexpr int pn = sizeof(T) == 4 ? 8192 : 4096;
 };
 
-// Lengths with a compile-time kernel; other 2^a 3^b 5^c lengths use the
+// Lengths with a compile-time kernel; other 2^a 3^b 5^c 7^d lengths use the
 // run-time one.  Forward mesh sides (multiples of 16) and the real-space
 // grids of the triangle search.
 #define FRSD_FFT_LENGTHS(X) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
-#define FRSD_SHELL_LENGTHS(X) FRSD_FFT_LENGTHS(X) X(360)
+#define FRSD_SHELL_LENGTHS(X) FRSD_FFT_LENGTHS(X) X(343) X(360)
 
 }  // namespace frsd

@@ -61,6 +61,7 @@ struct Layout {
   size_t scal_part = 0, scal = 0, reject = 0;    // scalar reductions
   size_t cnt = 0, scan_blk = 0;                  // per-cell counts / offsets, scan partials
   size_t colmask = 0, xmask = 0;                 // occupied node columns (x, y) and x slabs (uint8)
+  size_t colocc = 0;                             // cell columns (x, y) holding an object (uint8)
   size_t slot = 0, cellkey = 0;                  // per-object rank within its cell, cell id
   size_t sorted = 0;                             // sorted object records
   size_t mesh = 0;                               // n_slot complex N^3 meshes

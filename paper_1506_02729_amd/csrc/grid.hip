@@ -105,15 +105,17 @@ __device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const
 // Node columns within reach of an object: colmask[x N + y] = 1 when some
 // cell column (cx, cy) with cx - x and cy - y in [LO, HI] (periodic) holds
 // an object, i.e. offs[(cx N + cy + 1) N] > offs[(cx N + cy) N] for the
-// exclusive scan offs of the cell counts; xmask[x] = 1 when any column of
-// slab x is set.  One workgroup per x.
+// exclusive scan offs of the cell counts (colocc[cx N + cy]); xmask[x] = 1
+// when any column of slab x is set.  One workgroup per x.
 template <int P>
 __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, int N, uint8_t *colmask,
-                                                  uint8_t *xmask) {
+                                                  uint8_t *xmask, uint8_t *colocc) {
   constexpr int LO = Win<P>::LO, HI = Win<P>::HI;
   const int x = blockIdx.x;
   int any = 0;
   for (int y = threadIdx.x; y < N; y += 256) {
+    const long long c0 = ((long long)x * N + y) * N;
+    colocc[(long long)x * N + y] = offs[c0 + N] > offs[c0] ? 1 : 0;
     int m = 0;
 #pragma unroll
     for (int dx = LO; dx <= HI; ++dx) {
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 // ---------------------------------------------------------------------------
 // x-sweep assignment (FP32 plans, N a multiple of 64).
 //
-// A workgroup owns a 4 (y) x 64 (z) patch of node columns and sweeps it
+// A workgroup owns a 4 (y) x 32 (z) patch of node columns and sweeps it
 // along x over 64 nodes.  At each cell slab x = c it stages the objects of
 // the slab cells that reach the patch, and every thread adds each object of
 // its window to the ring of the RING nodes of its column that the slab
@@ -355,11 +357,12 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 // rings).  The ring slots are compile-time indices: the cell loop is
 // unrolled by RING.
 // ---------------------------------------------------------------------------
-constexpr int kSY = 4, kSZ = 64, kSX = 64;
+constexpr int kSY = 4, kSZ = 32, kSX = 64;
 constexpr int kSThreads = kSY * kSZ;                   // one node column per thread
-constexpr int kSCap = 1536;                            // staged objects per chunk (32 B each)
+constexpr int kSCap = 768;                            // staged objects per chunk (32 B each)
 constexpr int kSCellsMax = (kSY + 3) * (kSZ + 3);      // slab cells for a ring of 4
-static_assert(kSThreads == kSX * kSY, "one liveness test per thread");
+constexpr int kSStepsMax = kSX + 3;
+static_assert(kSCellsMax <= 2 * kSThreads, "two slab cells per thread");
 
 // Cells [LO, HI] (relative to node n) reaching the main node n or the twin
 // node n + 1/2 of each assignment order.
@@ -379,9 +382,10 @@ struct SweepRec {
 };
 
 template <int P, bool TWIN>
-__global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict__ offs,
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_grid_sweep(const int *__restrict__ offs,
                                                           const Rec4<float> *__restrict__ recs,
-                                                          const uint8_t *__restrict__ colmask, GridArgs ga,
+                                                          const uint8_t *__restrict__ colmask,
+                                                          const uint8_t *__restrict__ colocc, GridArgs ga,
                                                           float *__restrict__ planar) {
   using Wn = SweepWin<P, TWIN>;
   constexpr int LO = Wn::LO, HI = Wn::HI, RING = HI - LO + 1;
@@ -392,6 +396,7 @@ __global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict_
   __shared__ int cst[kSCellsMax + 1];  // staged start of each slab cell (e = iy * CZ + iz)
   __shared__ int gsrc[kSCellsMax];     // first sorted record of each slab cell
   __shared__ int wtot[kSThreads / 64];
+  __shared__ uint8_t step_live[kSStepsMax];  // slab of the step holds an object in the patch's y range
 
   const int N = ga.N;
   const int nyb = N / kSY, nzb = N / kSZ;
@@ -400,11 +405,24 @@ __global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict_
   const int ly = threadIdx.x / kSZ, lz = threadIdx.x % kSZ;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
+  constexpr int NSTEP = kSX + RING - 1;
+  for (int i = threadIdx.x; i < NSTEP; i += kSThreads) step_live[i] = 0;
   {  // patches with no node in reach of an object write nothing
-    const int t = threadIdx.x;
-    const int live = colmask[(long long)(X0 + t / kSY) * N + (Y0 + t % kSY)];
+    int live = 0;
+    for (int t = threadIdx.x; t < kSX * kSY; t += kSThreads)
+      live |= colmask[(long long)(X0 + t / kSY) * N + (Y0 + t % kSY)];
     if (!__syncthreads_or(live)) return;
   }
+  // steps whose slab has no object in the y range of the patch skip the
+  // staging and the visits (the ring is still flushed)
+  for (int t = threadIdx.x; t < NSTEP * CY; t += kSThreads) {
+    const int sx = t / CY, iy = t - sx * CY;
+    int c = X0 + LO + sx, cy = Y0 + LO + iy;
+    c += c < 0 ? N : (c >= N ? -N : 0);
+    cy += cy < 0 ? N : (cy >= N ? -N : 0);
+    if (colocc[(long long)c * N + cy]) step_live[sx] = 1;
+  }
+  __syncthreads();
   const bool has_w = ga.has_w != 0;
   const int nmom = ga.n_ell_mom;
   const float ny_ = (float)ly + SH, nz_ = (float)lz + SH;  // node position relative to (Y0, Z0)
@@ -422,7 +440,6 @@ __global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict_
     for (int m = 0; m < kMaxMom; ++m) acc[r][m] = 0.f;
 
   const long long ps = ga.plane_stride;
-  constexpr int NSTEP = kSX + RING - 1;
 
   auto step = [&](const int sidx, auto kc) {
     constexpr int k = decltype(kc)::value;  // sidx % RING
@@ -430,6 +447,7 @@ __global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict_
     const int cw = c < 0 ? c + N : (c >= N ? c - N : c);
     const float xo = (float)((double)cw - ga.ou[0]);
 
+    if (step_live[sidx]) {
     // ---- slab cell table and exclusive scan of the counts ----
     int cnt[2] = {0, 0};
 #pragma unroll
@@ -552,6 +570,7 @@ __global__ __launch_bounds__(kSThreads) void k_grid_sweep(const int *__restrict_
         for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w);
       }
     }
+    }  // step_live
 
     // the lowest ring node (c - HI) is complete: written when it belongs to
     // the workgroup (the first RING - 1 steps only warm the ring up), and its
@@ -603,18 +622,20 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   ga.plane_stride = (long long)N * N * N;
   FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
-                                               ws_ptr<uint8_t>(ws, L.xmask)));
+                                               ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
   if constexpr (std::is_same<T, float>::value) {
     if (N % kSX == 0 && N % kSZ == 0) {
       const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
       FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<P, false>), dim3(nblk), dim3(kSThreads), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<float>>(ws, L.sorted),
-                                               ws_ptr<const uint8_t>(ws, L.colmask), ga, ws_ptr<float>(ws, L.planar)));
+                                               ws_ptr<const uint8_t>(ws, L.colmask), ws_ptr<const uint8_t>(ws, L.colocc),
+                                               ga, ws_ptr<float>(ws, L.planar)));
       if (ga.interlace)
         FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<P, true>), dim3(nblk), dim3(kSThreads), 0, s,
                                                       ws_ptr<const int>(ws, L.cnt),
                                                       ws_ptr<const Rec4<float>>(ws, L.sorted),
-                                                      ws_ptr<const uint8_t>(ws, L.colmask), ga,
+                                                      ws_ptr<const uint8_t>(ws, L.colmask),
+                                                      ws_ptr<const uint8_t>(ws, L.colocc), ga,
                                                       ws_ptr<float>(ws, L.planar)));
       FRSD_LAUNCH_CHECK();
       return FRSD_OK;

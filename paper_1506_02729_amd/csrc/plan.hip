@@ -57,6 +57,7 @@ bool make_fft_len(int n, FftLen *out) {
   int ns = 0;
   while (m % 3 == 0) { f.radix[ns++] = 3; m /= 3; }
   while (m % 5 == 0) { f.radix[ns++] = 5; m /= 5; }
+  while (m % 7 == 0) { f.radix[ns++] = 7; m /= 7; }
   while (m % 8 == 0) { f.radix[ns++] = 8; m /= 8; }
   if (m % 4 == 0) { f.radix[ns++] = 4; m /= 4; }
   if (m % 2 == 0) { f.radix[ns++] = 2; m /= 2; }
@@ -71,6 +72,7 @@ static bool is_smooth(int n) {
   while (n % 2 == 0) n /= 2;
   while (n % 3 == 0) n /= 3;
   while (n % 5 == 0) n /= 5;
+  while (n % 7 == 0) n /= 7;
   return n == 1;
 }
 
@@ -113,7 +115,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (!params || !plan_out) return fail(FRSD_EINVAL, "null argument");
   const frsd_params &p = *params;
   if (p.n_grid < 32 || p.n_grid > 1024 || p.n_grid % 16 != 0 || !is_smooth(p.n_grid))
-    return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b 5^c, a multiple of 16, in [32, 1024]");
+    return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b 5^c 7^d, a multiple of 16, in [32, 1024]");
   if (p.order < 1 || p.order > 3) return fail(FRSD_EINVAL, "order must be 1 (NGP), 2 (CIC) or 3 (TSC)");
   if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(FRSD_EINVAL, "ell_max must be 0, 2 or 4");
   if (p.precision != FRSD_F32 && p.precision != FRSD_F64) return fail(FRSD_EINVAL, "precision must be 32 or 64");
@@ -149,7 +151,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     if (p.bk_grid) {
       if (p.bk_grid < need || !is_smooth(p.bk_grid) || p.bk_grid > 1024) {
         delete pl;
-        return fail(FRSD_EINVAL, "bk_grid must be 2^a 3^b 5^c > 3 n_c and <= 1024");
+        return fail(FRSD_EINVAL, "bk_grid must be 2^a 3^b 5^c 7^d > 3 n_c and <= 1024");
       }
       pl->M = p.bk_grid;
     } else {
@@ -209,6 +211,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.scan_blk = take(4 * ((NNN + 1 + 4095) / 4096 + 1));
   L.colmask = take((size_t)N * N);
   L.xmask = take((size_t)N);
+  L.colocc = take((size_t)N * N);
   L.slot = take(4 * nobj);
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));

@@ -72,26 +72,26 @@ def test_triangle_list_matches_oracle_rule():
 
 
 def test_triangle_grid_choice():
-    """Default M is the smallest 2^a 3^b 5^c above 3 n_c (n_c = 112 for a top
-    edge of 112.5 k_f); an explicit 5-smooth M is kept, other M rejected."""
+    """Default M is the smallest 2^a 3^b 5^c 7^d above 3 n_c (n_c = 112 for a
+    top edge of 112.5 k_f); an explicit 7-smooth M is kept, other M rejected."""
     from paper_1506_02729_amd import fastrsd as F
     kf = 2 * math.pi / 3500.0
     base = dict(n_grid=256, box=3500.0, observer=(0, 0, 0), pk_dk=0.005, pk_nbins=40,
                 bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, max_objects=10)
 
     def smooth(m):
-        for p in (2, 3, 5):
+        for p in (2, 3, 5, 7):
             while m % p == 0:
                 m //= p
         return m == 1
 
     expect = next(m for m in range(3 * 112 + 1, 2000) if smooth(m))
-    assert expect == 360
-    for bk_grid, want in ((0, expect), (375, 375), (384, 384)):
+    assert expect == 343
+    for bk_grid, want in ((0, expect), (350, 350), (360, 360), (384, 384)):
         h = F.frsd_plan_create(F.Config(**base, bk_grid=bk_grid).to_c())
         assert F.frsd_bk_grid(h) == want
         F.frsd_plan_destroy(h)
-    for bad in (350, 336):   # a factor 7; below 3 n_c + 1
+    for bad in (351, 336):   # a factor 13; below 3 n_c + 1
         with pytest.raises(F.FrsdError) as ei:
             F.frsd_plan_create(F.Config(**base, bk_grid=bad).to_c())
         assert ei.value.code == F.FRSD_EINVAL

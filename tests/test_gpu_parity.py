@@ -162,12 +162,14 @@ def test_pruned_fft_passes_192(gpu_lib, precision):
     _check_bk(out, refb, prm, precision, plan)
 
 
-@pytest.mark.parametrize("precision,m_gpu", [(64, 50), (32, 50), (64, 360), (32, 360)])
+@pytest.mark.parametrize("precision,m_gpu", [(64, 50), (32, 50), (64, 56), (32, 56), (64, 343), (32, 343),
+                                             (64, 360), (32, 360)])
 def test_radix5_triangle_grids(gpu_lib, precision, m_gpu):
-    """The triangle search on 5-smooth real-space grids: M = 50 (run-time
-    schedule 5, 5, 2) and M = 360 (compiled schedule 3, 3, 5, 8).  Any
-    M > 3 n_c gives the exact closed-triangle sums, so the oracle keeps its
-    own grid (M = 54 here) and the results must agree."""
+    """The triangle search on 5- and 7-smooth real-space grids: M = 50 and
+    56 (run-time schedules 5, 5, 2 and 7, 8), M = 343 and 360 (compiled
+    schedules 7, 7, 7 and 3, 3, 5, 8).  Any M > 3 n_c gives the exact
+    closed-triangle sums, so the oracle keeps its own grid (M = 54 here) and
+    the results must agree."""
     _log(f"case: pk+bk 48^3 bk_grid={m_gpu} precision={precision}")
     if "radix5" not in _ORACLE_CACHE:
         gal, ran, alpha, prm = _bk_case(29)
