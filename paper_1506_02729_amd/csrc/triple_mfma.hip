@@ -30,6 +30,7 @@ namespace frsd {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kXThreads = 1024;
 constexpr int kXWaves = kXThreads / 64;
@@ -55,11 +56,23 @@ struct XArgs {
   int nb, n_ell, ncol, npair, njobs;
 };
 
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
-  hi = (__bf16)v;
-  lo = (__bf16)(v - (float)hi);
+// Split of FP32 values into bfloat16 pairs, two values at once: one packed
+// rounding gives both hi parts, which are widened back to FP32 by shifting
+// and masking the packed word (no second rounding per value), and the
+// residuals x - hi are packed the same way.  For a product a*b the residual
+// is formed by an FMA, so it is exact.
+__device__ __forceinline__ void split2_bf16(float x0, float x1, bf16x2_t &hi, bf16x2_t &lo) {
+  hi = bf16x2_t{(__bf16)x0, (__bf16)x1};
+  const unsigned u = __builtin_bit_cast(unsigned, hi);
+  const float h0 = __uint_as_float(u << 16), h1 = __uint_as_float(u & 0xffff0000u);
+  lo = bf16x2_t{(__bf16)(x0 - h0), (__bf16)(x1 - h1)};
+}
+__device__ __forceinline__ void split2_prod_bf16(float a0, float b0, float a1, float b1, bf16x2_t &hi,
+                                                 bf16x2_t &lo) {
+  hi = bf16x2_t{(__bf16)(a0 * b0), (__bf16)(a1 * b1)};
+  const unsigned u = __builtin_bit_cast(unsigned, hi);
+  const float h0 = __uint_as_float(u << 16), h1 = __uint_as_float(u & 0xffff0000u);
+  lo = bf16x2_t{(__bf16)__builtin_fmaf(a0, b0, -h0), (__bf16)__builtin_fmaf(a1, b1, -h1)};
 }
 
 // One workgroup: a contiguous range of cells, all jobs.  Per stage of kXKC
@@ -85,6 +98,13 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   const int li = lane & 15;     // row (A) / column (B) inside a 16-tile
   const int lk = lane >> 4;     // 8-wide k group of the 32-wide k-step
   const int nj = jobs.nj[wave];
+  // the wave's job tiles, read once into scalar registers
+  int jrt[kXMaxJobs], jct[kXMaxJobs];
+#pragma unroll
+  for (int j = 0; j < kXMaxJobs; ++j) {
+    jrt[j] = __builtin_amdgcn_readfirstlane((int)jobs.rt[wave][j]);
+    jct[j] = __builtin_amdgcn_readfirstlane((int)jobs.ct[wave][j]);
+  }
 
   // hi*hi products in acc, the two cross terms in acc2: two independent
   // accumulation chains per tile keep consecutive MFMAs independent
@@ -149,11 +169,10 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
       if (e < npe) {
         const int fl = e >> 5, k = 2 * (e & 31);
         const int col = cmap[fl];
-        __bf16 h0, l0, h1, l1;
-        split_bf16(pf[q].x, h0, l0);
-        split_bf16(pf[q].y, h1, l1);
-        *reinterpret_cast<bf16x2_t *>(&Bh[col][k]) = bf16x2_t{h0, h1};
-        *reinterpret_cast<bf16x2_t *>(&Bl[col][k]) = bf16x2_t{l0, l1};
+        bf16x2_t h, l;
+        split2_bf16(pf[q].x, pf[q].y, h, l);
+        *reinterpret_cast<bf16x2_t *>(&Bh[col][k]) = h;
+        *reinterpret_cast<bf16x2_t *>(&Bl[col][k]) = l;
         if (fl < a.nb) *reinterpret_cast<float2 *>(&U[fl][k]) = pf[q];
       }
     }
@@ -183,7 +202,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 #pragma unroll
       for (int j = 0; j < kXMaxJobs; ++j) {
         if (j < nj) {
-          const int rt = jobs.rt[wave][j], ct = jobs.ct[wave][j];
+          const int rt = jrt[j], ct = jct[j];
           if (rt != cur_rt) {
             cur_rt = rt;
             const unsigned pr = prs[rt * 16 + li];
@@ -192,14 +211,15 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
             const float4 x1 = *reinterpret_cast<const float4 *>(&U[b2][k0 + 4]);
             const float4 y0 = *reinterpret_cast<const float4 *>(&U[b3][k0]);
             const float4 y1 = *reinterpret_cast<const float4 *>(&U[b3][k0 + 4]);
-            const float v[8] = {x0.x * y0.x, x0.y * y0.y, x0.z * y0.z, x0.w * y0.w,
-                                x1.x * y1.x, x1.y * y1.y, x1.z * y1.z, x1.w * y1.w};
+            bf16x2_t h[4], l[4];
+            split2_prod_bf16(x0.x, y0.x, x0.y, y0.y, h[0], l[0]);
+            split2_prod_bf16(x0.z, y0.z, x0.w, y0.w, h[1], l[1]);
+            split2_prod_bf16(x1.x, y1.x, x1.y, y1.y, h[2], l[2]);
+            split2_prod_bf16(x1.z, y1.z, x1.w, y1.w, h[3], l[3]);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              __bf16 h, lo;
-              split_bf16(v[e], h, lo);
-              ah[e] = h;
-              al[e] = lo;
+            for (int e = 0; e < 4; ++e) {
+              ah[2 * e] = h[e][0]; ah[2 * e + 1] = h[e][1];
+              al[2 * e] = l[e][0]; al[2 * e + 1] = l[e][1];
             }
           }
           const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(&Bh[ct * 16 + li][k0]);
