@@ -350,16 +350,16 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 // its window to the ring of the RING nodes of its column that the slab
 // reaches (nodes c - HI .. c - LO); the lowest ring node is then complete
 // and is written out.  Per visit the line of sight, the moments and the y
-// and z kernel weights are computed once for all ring nodes, and the x
-// weights (times the object weight) once per staged object, which makes
-// the sweep several times cheaper in instructions than the per-node gather
-// above.  Main and twin grids are separate passes (separate windows and
-// rings).  The ring slots are compile-time indices: the cell loop is
-// unrolled by RING.
+// and z kernel weights are computed once for all ring nodes, which makes the
+// sweep several times cheaper in instructions than the per-node gather
+// above.  Staged records stay 16 bytes (each lane reads its own record, so
+// LDS bandwidth, not arithmetic, decides the record size).  Main and twin
+// grids are separate passes (separate windows and rings).  The ring slots
+// are compile-time indices: the cell loop is unrolled by RING.
 // ---------------------------------------------------------------------------
 constexpr int kSY = 4, kSZ = 32, kSX = 64;
 constexpr int kSThreads = kSY * kSZ;                   // one node column per thread
-constexpr int kSCap = 768;                            // staged objects per chunk (32 B each)
+constexpr int kSCap = 1024;                            // staged objects per chunk (16 B each)
 constexpr int kSCellsMax = (kSY + 3) * (kSZ + 3);      // slab cells for a ring of 4
 constexpr int kSStepsMax = kSX + 3;
 static_assert(kSCellsMax <= 2 * kSThreads, "two slab cells per thread");
@@ -375,10 +375,9 @@ template <> struct SweepWin<1, false> { static constexpr int LO = -1, HI = 0; };
 template <> struct SweepWin<1, true> { static constexpr int LO = 0, HI = 0; };
 
 // Staged object: a = (x fraction in cell c, y and z relative to the patch
-// origin, t0); w[r] = t0 W(x - node_r) for the ring nodes r of cell c.
+// origin, t0).
 struct SweepRec {
   float4 a;
-  float4 w;
 };
 
 template <int P, bool TWIN>
@@ -510,10 +509,6 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const int iy = lo / CZ, iz = lo - iy * CZ;
         SweepRec r;
         r.a = make_float4(g.x, (float)(LO + iy) + g.y, (float)(LO + iz) + g.z, g.w);
-        float wx[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < RING; ++q) wx[q] = g.w * kernel_w<float, P>(g.x + (float)(HI - q) - SH);
-        r.w = make_float4(wx[0], wx[1], wx[2], wx[3]);
         st[i - s0] = r;
       }
       __syncthreads();
@@ -546,10 +541,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
 #pragma unroll 1
       for (int t = 0; t < trips; ++t) {
         SweepRec r = nr;
-        if (!nvalid) {
-          r.a.w = 0.f;
-          r.w = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+        if (!nvalid) r.a.w = 0.f;
         j += nvalid ? 1 : 0;
         advance();
         nvalid = j < je;
@@ -565,7 +557,9 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const float ir = r2 > 0.f ? rsqrt_t(r2) : 0.f;
         const float hx = px * ir, hy = py * ir, hz = pz * ir;
         const float q[6] = {hx * hx, hy * hy, hz * hz, hx * hy, hy * hz, hz * hx};
-        const float wr[4] = {r.w.x, r.w.y, r.w.z, r.w.w};
+        float wr[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < RING; ++q) wr[q] = r.a.w * kernel_w<float, P>(r.a.x + (float)(HI - q) - SH);
 #pragma unroll
         for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w);
       }

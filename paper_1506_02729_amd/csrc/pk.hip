@@ -279,17 +279,21 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
   for (int i = threadIdx.x; i < nall * NV; i += kBinThreads) part[(long long)i * gridDim.x + blockIdx.x] = bins[i];
 }
 
-// Sum of the per-block partials, one thread per (bin, quantity), into the
-// kBinSums slots of the bin: geometry into slots 0-1, data sums into 2-4
-// (P_ell bins) or 5-7 (bispectrum bins).
-__global__ void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb, int geom, double *sum) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nall * nv) return;
+// Sum of the per-block partials, one wavefront per (bin, quantity) reading
+// its nblk contiguous partials, into the kBinSums slots of the bin: geometry
+// into slots 0-1, data sums into 2-4 (P_ell bins) or 5-7 (bispectrum bins).
+__global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb,
+                                                    int geom, double *sum) {
+  const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= nall * nv) return;  // whole wavefronts
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += part[(long long)i * nblk + b];
-  const int bin = i / nv, q = i - bin * nv;
-  const int slot = geom ? q : (bin < pk_nb ? 2 + q : 5 + q);
-  sum[bin * kBinSums + slot] = s;
+  for (int b = lane; b < nblk; b += 64) s += part[(long long)i * nblk + b];
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int bin = i / nv, q = i - bin * nv;
+    const int slot = geom ? q : (bin < pk_nb ? 2 + q : 5 + q);
+    sum[bin * kBinSums + slot] = s;
+  }
 }
 
 __global__ void k_pk_final(const double *sum, const double *scal, int nb, int ell_max, int64_t *n_modes, double *k_eff,
@@ -353,7 +357,7 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
                                                ws_ptr<const int16_t>(ws, L.pk_lut),
                                                p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                                (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part)));
-  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 255) / 256), dim3(256), 0, s,
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_LAUNCH_CHECK();
@@ -378,7 +382,7 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
                                           p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                           p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr,
                                           ws_ptr<double>(ws, L.bin_part)));
-  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 255) / 256), dim3(256), 0, s,
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),

@@ -250,9 +250,15 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 __global__ void k_triple_mfma_reduce(const float *__restrict__ part, int nwg, int nvals, double *__restrict__ sum) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvals) return;
-  double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += (double)part[(long long)w * nvals + i];
-  sum[i] = s;
+  // four interleaved sums keep several loads in flight
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int w = 0;
+  for (; w + 4 <= nwg; w += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += (double)part[(long long)(w + k) * nvals + i];
+  }
+  for (; w < nwg; ++w) s[0] += (double)part[(long long)w * nvals + i];
+  sum[i] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // Gather the listed outputs (triangle t, multipole l) from the job tiles.
