@@ -34,9 +34,9 @@ METRIC = "mocks/s for P_0,2,4+B_0,2,4 at 512^3 (served FP32 vs plain FP64), HBM 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30                 # calibration copy: reads and writes 1 GiB
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = {"grid": "grid.hip", "fft_z": "fft.hip", "fft_y": "fft.hip", "fft_x": "fft.hip",
-                  "triple": "triple_mfma.hip", "bin": "pk.hip", "shell_x": "bk.hip", "shell_y": "bk.hip",
-                  "shell_z": "bk.hip"}
+KERNEL_SOURCES = {"grid": "grid.hip", "grid_twin": "grid.hip", "fft_z": "fft.hip", "fft_y": "fft.hip",
+                  "fft_x": "fft.hip", "triple": "triple_mfma.hip", "bin": "pk.hip", "shell_x": "bk.hip",
+                  "shell_y": "bk.hip", "shell_z": "bk.hip"}
 FP32_VEC_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
@@ -68,8 +68,8 @@ def algorithmic_cost(name, plan_cfg, n_obj, n_slot, M, n_out, tbytes):
     N = plan_cfg.n_grid
     cplx = 2 * tbytes
     mesh = n_slot * N**3 * cplx
-    if name == "grid":          # write every moment plane once, read every 4-value object record once
-        return "hbm", mesh + n_obj * 4 * tbytes
+    if name in ("grid", "grid_twin"):  # one grid's planes (half the mesh) written once, every record read once
+        return "hbm", mesh // 2 + n_obj * 4 * tbytes
     if name.startswith("fft_"):  # read + write every mesh once per pass
         return "hbm", 2 * mesh
     if name == "shell_x":       # write two real M^3 fields per pair, read the y-pass rows
