@@ -125,13 +125,15 @@ __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, cons
 
 // I22 = alpha S_r[nbar w^2], N0 = S_g[w^2] + alpha^2 S_r[w^2],
 // I33 = alpha S_r[nbar^2 w^3], W3 = S_g[w^3] - alpha^3 S_r[w^3].
-__global__ void k_scal_final(const double *part, int nblk, double alpha, double *scal) {
+// One wavefront per partial column (6 columns, 384 threads), then the
+// scalars.
+__global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk, double alpha, double *scal) {
   __shared__ double col[6];
-  if (threadIdx.x < 6) {
-    double s = 0;
-    for (int b = 0; b < nblk; ++b) s += part[threadIdx.x * nblk + b];
-    col[threadIdx.x] = s;
-  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double s = 0;
+  for (int b = lane; b < nblk; b += 64) s += part[w * nblk + b];
+  s = wave_sum(s);
+  if (lane == 0) col[w] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     scal[0] = alpha * col[2];
@@ -162,53 +164,81 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const int *a, long long n, 
   if (threadIdx.x == 0) blk[blockIdx.x] = red[0];
 }
 
-// block-wide exclusive scan of one int per thread (256 threads); returns total
-__device__ int block_exscan256(int v, int *tmp, int &total) {
-  tmp[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int t = (threadIdx.x >= o) ? tmp[threadIdx.x - o] : 0;
-    __syncthreads();
-    tmp[threadIdx.x] += t;
-    __syncthreads();
+// Exclusive scan of the 256 per-thread values v of a block (wavefront
+// shuffles, then the 4 wavefront totals); returns the exclusive prefix and
+// the block total.
+__device__ __forceinline__ int block_exscan256_fast(int v, int *wtot, int &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
   }
-  total = tmp[255];
-  const int incl = tmp[threadIdx.x];
+  if (lane == 63) wtot[w] = incl;
   __syncthreads();
-  return incl - v;
+  int pre = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int t = wtot[k];
+    pre += k < w ? t : 0;
+    total += t;
+  }
+  __syncthreads();
+  return pre + incl - v;
 }
 
+// Block partials: thread t owns a contiguous run of them.
 __global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb) {
-  __shared__ int tmp[256];
-  int carry = 0;
-  for (int base = 0; base < nb; base += 256) {
-    const int i = base + threadIdx.x;
-    const int v = (i < nb) ? blk[i] : 0;
-    int total;
-    const int ex = block_exscan256(v, tmp, total);
-    if (i < nb) blk[i] = carry + ex;
-    carry += total;
+  __shared__ int wtot[4];
+  const int per = (nb + 255) / 256;
+  const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += blk[i];
+  int total;
+  int run = block_exscan256_fast(s, wtot, total);
+  for (int i = b0; i < b1; ++i) {
+    const int v = blk[i];
+    blk[i] = run;
+    run += v;
   }
 }
+
+// One chunk of 4096 counts per block: coalesced through LDS (one pad word
+// per 16 so that each thread's 16 consecutive counts sit in distinct banks),
+// scanned, and written back coalesced.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const int *blk) {
-  __shared__ int tmp[256];
-  const long long base = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * 16;
+  __shared__ int buf[kScanChunk + kScanChunk / 16];
+  __shared__ int wtot[4];
+  const long long base = (long long)blockIdx.x * kScanChunk;
+#pragma unroll
+  for (int k = 0; k < kScanChunk / 256; ++k) {
+    const int e = k * 256 + threadIdx.x;
+    buf[scan_pad(e)] = base + e < n ? a[base + e] : 0;
+  }
+  __syncthreads();
   int v[16];
   int s = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const long long i = base + k;
-    v[k] = (i < n) ? a[i] : 0;
+    v[k] = buf[scan_pad(threadIdx.x * 16 + k)];
     s += v[k];
   }
   int total;
-  int run = block_exscan256(s, tmp, total) + blk[blockIdx.x];
+  int run = block_exscan256_fast(s, wtot, total) + blk[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const long long i = base + k;
-    if (i < n) a[i] = run;
+    buf[scan_pad(threadIdx.x * 16 + k)] = run;
     run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanChunk / 256; ++k) {
+    const int e = k * 256 + threadIdx.x;
+    if (base + e < n) a[base + e] = buf[scan_pad(e)];
   }
 }
 
@@ -263,7 +293,7 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
     else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s);
     off += cats[k]->n;
   }
-  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(64), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(384), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
                      ws_ptr<double>(ws, L.scal)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
