@@ -19,6 +19,10 @@
 // kept x.  Kept indices form two runs, [0, ka) and [N - kb, N).  Entries
 // outside the kept set are never written and never read.
 //
+// Sphere: the binning reads only modes with |n|^2 <= m2max.  The y pass
+// writes only (n_y, n_z) with n_y^2 + n_z^2 <= m2max, the x pass transforms
+// only those columns and writes only modes inside the sphere.
+//
 // Survey sparsity: a survey fills a fraction of the box, and every node
 // column (x, y) out of reach of all objects (colmask 0) is zero in every
 // plane, as is every x slab with no such column (xmask 0).  The z pass skips
@@ -35,7 +39,11 @@ namespace frsd {
 struct Keep {
   int ka, kb;    // kept runs [0, ka) and [N - kb, N) (kb = 0: one run [0, ka))
   int nba, nbb;  // workgroups of P columns over each run
+  int m2max;     // largest |n|^2 read after the transform (compiled-length passes)
 };
+
+// Signed frequency of index e of a length-N axis.
+__device__ __forceinline__ int sfreq(int e, int N) { return 2 * e <= N ? e : e - N; }
 
 __device__ __forceinline__ bool kept(int e, int N, const Keep &k) { return e < k.ka || e >= N - k.kb; }
 
@@ -190,6 +198,14 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   column_block(blockIdx.x - outer_i * nzb, P, LEN, keep, z0, npen);
   const int outer = (AXIS == 1) ? outer_i : (outer_i < keep.ka ? outer_i : LEN - keep.kb + (outer_i - keep.ka));
   if (AXIS == 1 && !xmask[outer]) return;  // empty x slab: its y-pass output is never read
+  // x pass: n_y of the block and the smallest n_z^2 of its columns; a block
+  // wholly outside the sphere's (n_y, n_z) disc has nothing to transform
+  const int ny2 = (AXIS == 0) ? sfreq(outer, LEN) * sfreq(outer, LEN) : 0;
+  if (AXIS == 0) {
+    int nz2min = 1 << 30;
+    for (int p = 0; p < npen; ++p) nz2min = min(nz2min, sfreq(z0 + p, LEN) * sfreq(z0 + p, LEN));
+    if (ny2 + nz2min > keep.m2max) return;
+  }
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
@@ -206,10 +222,19 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   C *col = data + (long long)blockIdx.y * batch_stride +
            ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
   // in place: every load happens in the first stage, every store in the last
+  // (y pass: columns (n_y = e, n_z) outside the disc are not written; x
+  // pass: those columns are read as zero and only modes inside the sphere
+  // are written)
   fft_pencils<C, LEN, P, NT, false, true>(
-      lds, tw, npen, [&](int p, int e) { return live[e] ? col[e * es + p] : cmake<C>(T(0), T(0)); },
+      lds, tw, npen,
+      [&](int p, int e) {
+        const int nz = sfreq(z0 + p, LEN);
+        const bool in = AXIS == 1 || ny2 + nz * nz <= keep.m2max;
+        return live[e] && in ? col[e * es + p] : cmake<C>(T(0), T(0));
+      },
       [&](int p, int e, C v) {
-        if (kept(e, LEN, keep)) col[e * es + p] = v;
+        const int nz = sfreq(z0 + p, LEN), ne = sfreq(e, LEN);
+        if (kept(e, LEN, keep) && ny2 + nz * nz + ne * ne <= keep.m2max) col[e * es + p] = v;
       });
 }
 
@@ -223,6 +248,7 @@ static StageList stages_of(const FftLen &f) {
 static Keep make_keep(int N, int P, int nmax) {
   // kept runs [0, nmax] and [N - nmax, N), widened to whole blocks of P columns
   Keep k{};
+  k.m2max = 3 * N * N;  // no sphere limit unless the caller sets one
   k.ka = std::min(N, (nmax + 1 + P - 1) / P * P);
   const int b0 = std::max(k.ka, (N - nmax) / P * P);
   k.kb = N - b0;
@@ -233,12 +259,13 @@ static Keep make_keep(int N, int P, int nmax) {
 }
 
 template <typename T, int LEN>
-static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
                             const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
   using C = cplx_t<T>;
   constexpr int PR = p_row<T, LEN>(), PC = FwdTune<T>::p_col;
   constexpr long long NN = (long long)LEN * LEN;
-  const Keep k = make_keep(LEN, PC, nmax);
+  Keep k = make_keep(LEN, PC, nmax);
+  k.m2max = m2max;
   const unsigned nzb = (unsigned)(k.nba + k.nbb);
   constexpr size_t sh_row = fft_pencils_lds<C, LEN, PR>(), sh_col = fft_pencils_lds<C, LEN, PC>();
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_row<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_row));
@@ -285,20 +312,20 @@ static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar,
 }
 
 template <typename T>
-int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
                   const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
+  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, m2max, colmask, xmask, s);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
     default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
   }
 }
 
-template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, const uint8_t *,
+template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
                                   const uint8_t *, hipStream_t);
-template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, const uint8_t *,
+template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
                                    const uint8_t *, hipStream_t);
 
 }  // namespace frsd

@@ -178,9 +178,10 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
 // Forward c2c FFT of n_batch N^3 complex meshes given as planar real arrays
 // (re of mesh s = array 2s, im = array 2s+1); output interleaved complex.
 // Node columns (x, y) with colmask 0 and x slabs with xmask 0 are zero in
-// every mesh: they are read as zero, never from memory.
+// every mesh: they are read as zero, never from memory.  Only modes with
+// |n|^2 <= m2max are guaranteed in the output.
 template <typename T>
-int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
+int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
                   const uint8_t *colmask, const uint8_t *xmask, hipStream_t s);
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).

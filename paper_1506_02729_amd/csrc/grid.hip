@@ -31,6 +31,7 @@
 // of moment m is the real part and the twin plane the imaginary part of
 // slot m; without interlacing, moments 2s and 2s+1 share slot s.  The first
 // FFT pass reads the planar arrays and writes interleaved complex meshes.
+#include <algorithm>
 #include <type_traits>
 
 #include "device.h"
@@ -658,6 +659,7 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   if (rc) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
                           ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax,
+                          std::max(pl->pk_lut_len, pl->p.bk_nbins > 0 ? pl->bk_lut_len : 0) - 1,
                           ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
 }
 
