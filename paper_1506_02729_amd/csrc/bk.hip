@@ -164,9 +164,13 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_shell_x(const cplx_t<T>
 // Compiled-length shell passes on the register-resident core (fft_pencils);
 // same pencils and buffers as the run-time kernels above.  A pencil element
 // e holds frequency e (e <= nc) or e - M (e >= M - nc) and is zero between.
-template <typename T> struct ShellTune {
-  static constexpr int nt = sizeof(T) == 4 ? 512 : 256;
-  static constexpr int p = sizeof(T) == 4 ? 16 : 8;
+// Pencils per workgroup: the y and x passes of FP32 plans take 32 pencils
+// (1024 threads) when their LDS fits, the z pass and FP64 plans 16 or 8.
+template <typename T, int LEN, int PASS> struct ShellTune {
+  static constexpr bool wide =
+      sizeof(T) == 4 && PASS != 0 && fft_pencils_lds<cplx_t<T>, LEN, 32>() <= (size_t)112 * 1024;
+  static constexpr int nt = wide ? 1024 : (sizeof(T) == 4 ? 512 : 256);
+  static constexpr int p = wide ? 32 : (sizeof(T) == 4 ? 16 : 8);
 };
 
 __device__ __forceinline__ int band_index(int e, int M, int nc) {
@@ -201,11 +205,11 @@ struct ShellPenZ {
 };
 
 template <typename T, bool IND, int LEN>
-__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T> *__restrict__ lowk,
+__global__ __launch_bounds__((ShellTune<T, LEN, 0>::nt)) void k_shell_z_ct(const cplx_t<T> *__restrict__ lowk,
                                                                  const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, cplx_t<T> *buf1) {
   using C = cplx_t<T>;
-  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  constexpr int P = ShellTune<T, LEN, 0>::p, NT = ShellTune<T, LEN, 0>::nt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
@@ -272,11 +276,11 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_z_ct(const cplx_t<T>
 }
 
 template <typename T, int LEN>
-__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T> *__restrict__ buf1,
+__global__ __launch_bounds__((ShellTune<T, LEN, 1>::nt)) void k_shell_y_ct(const cplx_t<T> *__restrict__ buf1,
                                                                  const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, cplx_t<T> *buf2) {
   using C = cplx_t<T>;
-  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  constexpr int P = ShellTune<T, LEN, 1>::p, NT = ShellTune<T, LEN, 1>::nt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
@@ -317,11 +321,11 @@ __global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_y_ct(const cplx_t<T>
 }
 
 template <typename T, typename TO, int LEN>
-__global__ __launch_bounds__(ShellTune<T>::nt) void k_shell_x_ct(const cplx_t<T> *__restrict__ buf2,
+__global__ __launch_bounds__((ShellTune<T, LEN, 2>::nt)) void k_shell_x_ct(const cplx_t<T> *__restrict__ buf2,
                                                                  const int2 *__restrict__ bin_m2, ShellArgs a,
                                                                  const cplx_t<T> *tw_g, TO *shells) {
   using C = cplx_t<T>;
-  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
+  constexpr int P = ShellTune<T, LEN, 2>::p, NT = ShellTune<T, LEN, 2>::nt;
   extern __shared__ unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
@@ -367,24 +371,27 @@ static int shell_pipeline_ct(frsd_plan *pl, void *ws, int nfield, const void *tw
   a.M = LEN; a.D = pl->D; a.nc = pl->nc_b; a.nb = pl->p.bk_nbins; a.nfield = nfield;
   a.lut_len = pl->bk_lut_len;
   const int D = a.D;
-  constexpr int P = ShellTune<T>::p, NT = ShellTune<T>::nt;
-  constexpr size_t shmem = fft_pencils_lds<C, LEN, P>();
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z_ct<T, IND, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y_ct<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x_ct<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  constexpr int PZ = ShellTune<T, LEN, 0>::p, NTZ = ShellTune<T, LEN, 0>::nt;
+  constexpr int PY = ShellTune<T, LEN, 1>::p, NTY = ShellTune<T, LEN, 1>::nt;
+  constexpr int PX = ShellTune<T, LEN, 2>::p, NTX = ShellTune<T, LEN, 2>::nt;
+  constexpr size_t shz = fft_pencils_lds<C, LEN, PZ>(), shy = fft_pencils_lds<C, LEN, PY>(),
+                   shx = fft_pencils_lds<C, LEN, PX>();
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_z_ct<T, IND, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shz));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y_ct<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shy));
+  FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x_ct<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shx));
   const int npairs = (nfield + 1) / 2;
   for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
     a.pair0 = p0;
     a.npair = std::min(kPairBatch, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * LEN,
                     nx = (long long)a.npair * LEN * LEN;
-    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z_ct<T, IND, LEN>), dim3((unsigned)((nz + P - 1) / P)), dim3(NT), shmem, s,
+    FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z_ct<T, IND, LEN>), dim3((unsigned)((nz + PZ - 1) / PZ)), dim3(NTZ), shz, s,
                        ws_ptr<const C>(ws, L.lowk), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw,
                        ws_ptr<C>(ws, L.buf1)));
-    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y_ct<T, LEN>), dim3((unsigned)((ny + P - 1) / P)), dim3(NT), shmem, s,
+    FRSD_TIMED("shell_y", s, hipLaunchKernelGGL((k_shell_y_ct<T, LEN>), dim3((unsigned)((ny + PY - 1) / PY)), dim3(NTY), shy, s,
                        ws_ptr<const C>(ws, L.buf1), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw,
                        ws_ptr<C>(ws, L.buf2)));
-    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x_ct<T, TO, LEN>), dim3((unsigned)((nx + P - 1) / P)), dim3(NT), shmem, s,
+    FRSD_TIMED("shell_x", s, hipLaunchKernelGGL((k_shell_x_ct<T, TO, LEN>), dim3((unsigned)((nx + PX - 1) / PX)), dim3(NTX), shx, s,
                        ws_ptr<const C>(ws, L.buf2), ws_ptr<const int2>(ws, L.bk_m2), a, (const C *)tw, shells));
     FRSD_LAUNCH_CHECK();
   }
