@@ -9,8 +9,11 @@ triangles of 37 bins of width 3 k_f up to k = 0.2 h/Mpc.  The served FP32
 measurement is a closed loop of --steps requests cycling a pool of --mocks
 distinct mocks (galaxy catalogues of distinct seeds sharing one random
 catalogue, as in a covariance run); catalogues are resident in HBM before
-the timed region and nothing is cached between requests.  The plain FP64
-leg runs one mock at a time.
+the timed region and nothing is cached between requests.  --streams
+requests are in flight at once, each on its own plan (workspace) and HIP
+stream, so the kernels of consecutive requests overlap; the value is
+requests over the wall time of the whole loop.  The plain FP64 leg runs one
+mock at a time.
 
 Prints one JSON line (see the "metric" key).  --gpus N > 1 is refused: the
 build targets one GPU.
@@ -72,8 +75,8 @@ def algorithmic_cost(name, plan_cfg, n_obj, n_slot, M, n_out, tbytes):
         return "hbm", mesh // 2 + n_obj * 4 * tbytes
     if name.startswith("fft_"):  # read + write every mesh once per pass
         return "hbm", 2 * mesh
-    if name == "shell_x":       # write two real M^3 fields per pair, read the y-pass rows
-        return "hbm", None
+    if name == "shell_x":       # write two real M^3 fields per pair of 8 per launch
+        return "hbm", 16 * M**3 * tbytes
     if name == "triple":        # 3 flops per listed output (triangle x multipole) per cell, on the matrix cores
         return "mfma", 3.0 * n_out * M**3
     return None, None
@@ -105,10 +108,15 @@ def measured_traffic(kernel):
     return e.get("bytes_per_launch")
 
 
-def run_steps(F, torch, plan, mocks, steps, timed: bool):
+def run_steps(F, torch, plans, mocks, steps, timed: bool):
+    """Serve `steps` requests cycling the pool; request i goes to plan i % len(plans)
+    (one stream and workspace per plan, so consecutive requests overlap)."""
+    if not isinstance(plans, (list, tuple)):
+        plans = [plans]
     lat = []
     for i in range(steps):
         g, r, a = mocks[i % len(mocks)]
+        plan = plans[i % len(plans)]
         if timed:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -216,6 +224,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--mocks", type=int, default=16, help="distinct mocks in the pool, cycled")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="requests in flight: one plan (workspace) and HIP stream each, default priority")
+    ap.add_argument("--kernel-steps", type=int, default=8,
+                    help="requests served one at a time after the timed loop, for per-kernel timings and the roofline")
     ap.add_argument("--quick", action="store_true", help="256^3 workload for development runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -254,27 +266,37 @@ def main():
     # ---- served FP32: closed loop over the pool ---------------------------
     cfg = make_config(F, wl, 32, observer, max_obj)
     t0 = time.perf_counter()
-    plan = F.Plan(cfg, device=dev)
+    nstream = max(1, args.streams)
+    plans = [F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev) if nstream > 1 else None)
+             for _ in range(nstream)]
+    plan = plans[0]
     torch.cuda.synchronize()
-    log(f"fp32 plan init (tables + N^T) {time.perf_counter() - t0:.2f} s, workspace {plan.ws_bytes / 1e9:.1f} GB")
-    run_steps(F, torch, plan, dev_mocks, args.warmup, False)
+    log(f"fp32 plan init (tables + N^T) {time.perf_counter() - t0:.2f} s, {nstream} workspace(s) of "
+        f"{plan.ws_bytes / 1e9:.1f} GB")
+    run_steps(F, torch, plans, dev_mocks, max(args.warmup, nstream), False)
     torch.cuda.synchronize()
     log("warmup done")
-    F.frsd_profile(True)
-    F.frsd_profile_report()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat = run_steps(F, torch, plan, dev_mocks, args.steps, True)
+    lat = run_steps(F, torch, plans, dev_mocks, args.steps, True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+    for pl_ in plans:
+        rej = pl_.status()
+        assert rej == 0, f"{rej} objects rejected"
+    last = (args.steps - 1) % len(dev_mocks)
+    last_plan = plans[(args.steps - 1) % nstream]
+    p32 = {k: v.cpu().numpy().copy() for k, v in last_plan.pk_buf.items()}
+    b32 = {k: v.cpu().numpy().copy() for k, v in last_plan.bk_buf.items()}
+    # per-kernel durations with one request in flight (overlapping requests
+    # would fold the other request's kernels into each duration)
+    F.frsd_profile(True)
+    F.frsd_profile_report()
+    run_steps(F, torch, plans[:1], dev_mocks, max(1, args.kernel_steps), False)
+    torch.cuda.synchronize()
     kern = F.frsd_profile_report()
     F.frsd_profile(False)
-    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
-    rej = plan.status()
-    assert rej == 0, f"{rej} objects rejected"
-    last = (args.steps - 1) % len(dev_mocks)
-    p32 = {k: v.cpu().numpy().copy() for k, v in plan.pk_buf.items()}
-    b32 = {k: v.cpu().numpy().copy() for k, v in plan.bk_buf.items()}
     log(f"fp32: {args.steps} requests in {elapsed:.3f} s")
     gold = None if args.quick else oracle_check(
         F, torch, plan, (pool[0][0], ran, pool[0][1], observer, dev_mocks[0][0], r_dev),
@@ -285,12 +307,15 @@ def main():
     M = plan.bk_grid
     assert f"M={M}" in wl["name"], (M, wl["name"])
     n_out = plan.ntri * 3
-    n_obj_last = len(pool[last][0]["w"]) + len(ran["w"])
+    ks = max(1, args.kernel_steps)
+    n_obj_kern = float(np.mean([len(pool[i % len(pool)][0]["w"]) for i in range(ks)])) + len(ran["w"])
     kernels = {k: {"launches": n, "total_ms": round(ms, 3), "avg_ms": round(ms / n, 4)} for k, (n, ms) in kern.items()}
     dom = max(kern, key=lambda k: kern[k][1])
     n_launch, tot_ms = kern[dom]
     avg_s = tot_ms / n_launch / 1e3
-    bound, cost = algorithmic_cost(dom, cfg, n_obj_last, n_slot, M, n_out, tbytes)
+    bound, cost = algorithmic_cost(dom, cfg, n_obj_kern, n_slot, M, n_out, tbytes)
+    if cost is None:
+        bound = None
     if bound == "hbm":
         roof = {"kernel": dom, "bound": "hbm", "achieved": cost / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     elif bound == "mfma":
@@ -302,7 +327,7 @@ def main():
         roof["frac"] = roof["achieved"] / roof["peak"]
         roof["avg_launch_ms"] = avg_s * 1e3
     roof["traffic"] = measured_traffic(dom)
-    del plan
+    del plan, last_plan, plans
     torch.cuda.empty_cache()
 
     # ---- plain FP64: one mock at a time ------------------------------------
@@ -355,6 +380,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["name"], "requests": args.steps, "mocks_in_pool": len(pool),
+                   "in_flight": nstream, "kernel_timing": f"{max(1, args.kernel_steps)} requests, one in flight",
                    "precision": "fp32 served (closed loop), fp64 plain (one mock at a time)"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": roof,
