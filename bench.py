@@ -130,10 +130,10 @@ def run_steps(F, torch, plans, mocks, steps, timed: bool):
     return lat
 
 
-def cpu_baseline(wl, gal, ran, alpha, observer):
+def cpu_baseline(wl, gal, ran, alpha, observer, M):
     """FP64 oracle timed on a bounded sample of the same workload, scaled to one mock."""
     from oracle import estimator as est
-    N, M = wl["n_mesh"], 384
+    N = wl["n_mesh"]
     n_obj = len(gal["w"]) + len(ran["w"])
     t = {}
     sample = 1_000_000
@@ -176,9 +176,9 @@ def cpu_baseline(wl, gal, ran, alpha, observer):
             "seconds_per_mock": per_mock,
             "sample": ("FP64 NumPy oracle stages timed once each on this host and scaled to one mock: TSC "
                        "assignment of 1e6 randoms for one moment plane (x %.0f objects x 46 planes), one "
-                       "512^3 rfftn (x 46), the 60-bin shell sums of 3 multipoles, one 384^3 shell inverse "
-                       "FFT (x 111), one 384^3 triple-product sum (x 5416 triangles x 3 multipoles)"
-                       % (n_obj / sample)),
+                       "512^3 rfftn (x 46), the 60-bin shell sums of 3 multipoles, one %d^3 shell inverse "
+                       "FFT (x 111), one %d^3 triple-product sum (x 5416 triangles x 3 multipoles)"
+                       % (n_obj / sample, M, M)),
             "stage_seconds": {k: round(v, 4) for k, v in t.items()}}
 
 
@@ -364,7 +364,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, pool[0][0], ran, pool[0][1], observer)
+        cpu = cpu_baseline(wl, pool[0][0], ran, pool[0][1], observer, M)
 
     out = {
         "metric": METRIC,
