@@ -57,21 +57,27 @@ struct XArgs {
 };
 
 // Split of FP32 values into bfloat16 pairs, two values at once: one packed
-// rounding gives both hi parts, which are widened back to FP32 by shifting
-// and masking the packed word (no second rounding per value), and the
-// residuals x - hi are packed the same way.  For a product a*b the residual
-// is formed by an FMA, so it is exact.
+// rounding gives both hi parts, which are widened back to FP32 by a byte
+// permute (low half moved up) and a mask of the packed word (no second
+// rounding per value), and the residuals x - hi are packed the same way.
+// For a product a*b the residual is formed by an FMA, so it is exact.
+__device__ __forceinline__ void widen2_bf16(bf16x2_t hi, float &h0, float &h1) {
+  const unsigned u = __builtin_bit_cast(unsigned, hi);
+  // bytes (0, 0, u.b0, u.b1): the low bfloat16 as an FP32 bit pattern
+  h0 = __uint_as_float(__builtin_amdgcn_perm(u, u, 0x01000c0cu));
+  h1 = __uint_as_float(u & 0xffff0000u);
+}
 __device__ __forceinline__ void split2_bf16(float x0, float x1, bf16x2_t &hi, bf16x2_t &lo) {
   hi = bf16x2_t{(__bf16)x0, (__bf16)x1};
-  const unsigned u = __builtin_bit_cast(unsigned, hi);
-  const float h0 = __uint_as_float(u << 16), h1 = __uint_as_float(u & 0xffff0000u);
+  float h0, h1;
+  widen2_bf16(hi, h0, h1);
   lo = bf16x2_t{(__bf16)(x0 - h0), (__bf16)(x1 - h1)};
 }
 __device__ __forceinline__ void split2_prod_bf16(float a0, float b0, float a1, float b1, bf16x2_t &hi,
                                                  bf16x2_t &lo) {
   hi = bf16x2_t{(__bf16)(a0 * b0), (__bf16)(a1 * b1)};
-  const unsigned u = __builtin_bit_cast(unsigned, hi);
-  const float h0 = __uint_as_float(u << 16), h1 = __uint_as_float(u & 0xffff0000u);
+  float h0, h1;
+  widen2_bf16(hi, h0, h1);
   lo = bf16x2_t{(__bf16)__builtin_fmaf(a0, b0, -h0), (__bf16)__builtin_fmaf(a1, b1, -h1)};
 }
 
@@ -84,12 +90,16 @@ __device__ __forceinline__ void split2_prod_bf16(float a0, float b0, float a1, f
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                float *__restrict__ part) {
-  // two stage buffers; row kXMaxB of U stays zero
+  // two stage buffers; row kXMaxB of U stays zero.  B2[buffer][0] holds the
+  // hi parts, B2[buffer][1] the lo parts, at a fixed byte distance so one
+  // address serves both reads.
   __shared__ __attribute__((aligned(16))) float U2[2][kXMaxB + 1][kXUPad];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh2[2][kXCols][kXBPad];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl2[2][kXCols][kXBPad];
-  __shared__ uint16_t prs[kXMaxRows];  // b2 | b3 << 8 of each row
+  __shared__ __attribute__((aligned(16))) __bf16 B2[2][2][kXCols][kXBPad];
+  __shared__ uint32_t prs[kXMaxRows];  // byte offsets in U of rows b2 (low half) and b3 (high half)
   __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
+  constexpr int kURow = kXUPad * 4, kUBuf = (kXMaxB + 1) * kURow;  // bytes
+  constexpr int kBRow = kXBPad * 2, kBHalf = kXCols * kBRow, kBBuf = 2 * kBHalf;
+  static_assert(kXMaxB * kURow < 65536 && kBHalf < 65536, "offsets must fit 16 bits / the DS immediate");
 
   const int lane = threadIdx.x & 63;
   // wave-uniform (scalar) so the job table is read with scalar loads and the
@@ -99,26 +109,31 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   const int lk = lane >> 4;     // 8-wide k group of the 32-wide k-step
   const int nj = jobs.nj[wave];
   // the wave's job tiles, read once into scalar registers
-  int jrt[kXMaxJobs], jct[kXMaxJobs];
+  // (scalar): row offset into prs, B byte offset of the column tile, and one
+  // word whose bit j marks job j present and bit 8 + j marks job j as the
+  // first of its row tile (jobs are sorted by row tile, so each row tile's
+  // pair products are formed once per k-step)
+  int jrt[kXMaxJobs], jcb[kXMaxJobs];
+  int jbits = 0;
 #pragma unroll
   for (int j = 0; j < kXMaxJobs; ++j) {
-    jrt[j] = __builtin_amdgcn_readfirstlane((int)jobs.rt[wave][j]);
-    jct[j] = __builtin_amdgcn_readfirstlane((int)jobs.ct[wave][j]);
+    jrt[j] = __builtin_amdgcn_readfirstlane((int)jobs.rt[wave][j]) * 16;
+    jcb[j] = __builtin_amdgcn_readfirstlane((int)jobs.ct[wave][j]) * 16 * kBRow;
+    if (j < nj) jbits |= 1 << j;
+    if (j < nj && (j == 0 || jrt[j] != jrt[j - 1])) jbits |= 1 << (8 + j);
   }
+  jbits = __builtin_amdgcn_readfirstlane(jbits);
 
-  // hi*hi products in acc, the two cross terms in acc2: two independent
-  // accumulation chains per tile keep consecutive MFMAs independent
-  f32x4_t acc[kXMaxJobs], acc2[kXMaxJobs];
+  // one FP32 accumulator per job takes all three products (an MFMA whose
+  // accumulator input is the previous MFMA's result issues back to back)
+  f32x4_t acc[kXMaxJobs];
 #pragma unroll
-  for (int j = 0; j < kXMaxJobs; ++j) {
-    acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    acc2[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  }
+  for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   // rows past the last pair read the zero row of U
   for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
-    uint16_t v = (uint16_t)(kXMaxB | (kXMaxB << 8));
-    if (i < a.npair) { const int2 p = pairs[i]; v = (uint16_t)(p.x | (p.y << 8)); }
+    uint32_t v = (uint32_t)(kXMaxB * kURow) * 0x10001u;
+    if (i < a.npair) { const int2 p = pairs[i]; v = (uint32_t)(p.x * kURow) | ((uint32_t)(p.y * kURow) << 16); }
     prs[i] = v;
   }
   for (int i = threadIdx.x; i < 2 * kXUPad; i += kXThreads) U2[i / kXUPad][kXMaxB][i % kXUPad] = 0.f;
@@ -130,8 +145,8 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   for (int i = threadIdx.x; i < 2 * (kXCols - a.ncol) * kXBPad; i += kXThreads) {
     const int bsel = i & 1, ii = i >> 1;
     const int c = a.ncol + ii / kXBPad, k = ii % kXBPad;
-    Bh2[bsel][c][k] = (__bf16)0.f;
-    Bl2[bsel][c][k] = (__bf16)0.f;
+    B2[bsel][0][c][k] = (__bf16)0.f;
+    B2[bsel][1][c][k] = (__bf16)0.f;
   }
 
   const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
@@ -161,8 +176,8 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   };
   auto store = [&](int bsel) {
     float(*U)[kXUPad] = U2[bsel];
-    __bf16(*Bh)[kXBPad] = Bh2[bsel];
-    __bf16(*Bl)[kXBPad] = Bl2[bsel];
+    __bf16(*Bh)[kXBPad] = B2[bsel][0];
+    __bf16(*Bl)[kXBPad] = B2[bsel][1];
 #pragma unroll
     for (int q = 0; q < kXPf; ++q) {
       const int e = threadIdx.x + q * kXThreads;
@@ -191,26 +206,28 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   for (long long c0 = c_begin; c0 < c_end; c0 += kXKC, cur ^= 1) {
     const bool more = c0 + kXKC < c_end;
     if (more) load(c0 + kXKC);
-    const float(*U)[kXUPad] = U2[cur];
-    const __bf16(*Bh)[kXBPad] = Bh2[cur];
-    const __bf16(*Bl)[kXBPad] = Bl2[cur];
+    // the job word is re-read as an opaque scalar each stage so the job tests
+    // stay scalar compare-and-branch (not hoisted as per-lane masks)
+    int jb = jbits;
+    asm volatile("" : "+s"(jb));
+    const char *Ub = reinterpret_cast<const char *>(&U2[0][0][0]) + cur * kUBuf;
+    const char *Bb = reinterpret_cast<const char *>(&B2[0][0][0][0]) + cur * kBBuf;
 #pragma unroll
     for (int ks = 0; ks < kXKC / 32; ++ks) {
       const int k0 = ks * 32 + lk * 8;
-      int cur_rt = -1;
+      const char *Ul = Ub + 4 * k0;               // this lane's 8 cells of a U row
+      const char *Bl_ = Bb + li * kBRow + 2 * k0;  // this lane's B row and 8 cells
       bf16x8_t ah, al;
 #pragma unroll
       for (int j = 0; j < kXMaxJobs; ++j) {
-        if (j < nj) {
-          const int rt = jrt[j], ct = jct[j];
-          if (rt != cur_rt) {
-            cur_rt = rt;
-            const unsigned pr = prs[rt * 16 + li];
-            const int b2 = (int)(pr & 0xff), b3 = (int)(pr >> 8);
-            const float4 x0 = *reinterpret_cast<const float4 *>(&U[b2][k0]);
-            const float4 x1 = *reinterpret_cast<const float4 *>(&U[b2][k0 + 4]);
-            const float4 y0 = *reinterpret_cast<const float4 *>(&U[b3][k0]);
-            const float4 y1 = *reinterpret_cast<const float4 *>(&U[b3][k0 + 4]);
+        if ((jb >> j) & 1) {
+          if ((jb >> (8 + j)) & 1) {
+            const unsigned pr = prs[jrt[j] + li];
+            const char *px = Ul + (pr & 0xffffu), *py = Ul + (pr >> 16);
+            const float4 x0 = *reinterpret_cast<const float4 *>(px);
+            const float4 x1 = *reinterpret_cast<const float4 *>(px + 16);
+            const float4 y0 = *reinterpret_cast<const float4 *>(py);
+            const float4 y1 = *reinterpret_cast<const float4 *>(py + 16);
             bf16x2_t h[4], l[4];
             split2_prod_bf16(x0.x, y0.x, x0.y, y0.y, h[0], l[0]);
             split2_prod_bf16(x0.z, y0.z, x0.w, y0.w, h[1], l[1]);
@@ -222,11 +239,12 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
               al[2 * e] = l[e][0]; al[2 * e + 1] = l[e][1];
             }
           }
-          const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(&Bh[ct * 16 + li][k0]);
-          const bf16x8_t bl = *reinterpret_cast<const bf16x8_t *>(&Bl[ct * 16 + li][k0]);
+          const char *pb = Bl_ + jcb[j];
+          const bf16x8_t bh = *reinterpret_cast<const bf16x8_t *>(pb);
+          const bf16x8_t bl = *reinterpret_cast<const bf16x8_t *>(pb + kBHalf);
           acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[j], 0, 0, 0);
-          acc2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc2[j], 0, 0, 0);
-          acc2[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc2[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[j], 0, 0, 0);
         }
       }
     }
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
     if (j < nj) {
       float *t = out + (long long)(jobs.first[wave] + j) * 256;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) t[(4 * lk + v) * 16 + li] = acc[j][v] + acc2[j][v];
+      for (int v = 0; v < 4; ++v) t[(4 * lk + v) * 16 + li] = acc[j][v];
     }
   }
 }
