@@ -36,6 +36,16 @@
 
 namespace frsd {
 
+// streaming store of one complex value (not kept in the caches)
+template <typename C>
+__device__ __forceinline__ void st_nt(C *p, C v) {
+  using T = decltype(v.x);
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<V2 *>(p));
+}
+
+
 struct Keep {
   int ka, kb;    // kept runs [0, ka) and [N - kb, N) (kb = 0: one run [0, ka))
   int nba, nbb;  // workgroups of P columns over each run
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data,
           return live[p] ? cmake<C>(re[p * LEN + e], im[p * LEN + e]) : cmake<C>(T(0), T(0));
         },
         [&](int p, int e, C v) {
-          if (live[p] && kept(e, LEN, keep)) dst[p * LEN + e] = v;
+          if (live[p] && kept(e, LEN, keep)) st_nt(&dst[p * LEN + e], v);
         });
     __syncthreads();  // pencils and live are rewritten by the next group
   }
@@ -234,7 +244,7 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
       },
       [&](int p, int e, C v) {
         const int nz = sfreq(z0 + p, LEN), ne = sfreq(e, LEN);
-        if (kept(e, LEN, keep) && ny2 + nz * nz + ne * ne <= keep.m2max) col[e * es + p] = v;
+        if (kept(e, LEN, keep) && ny2 + nz * nz + ne * ne <= keep.m2max) st_nt(&col[e * es + p], v);
       });
 }
 

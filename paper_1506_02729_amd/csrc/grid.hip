@@ -575,13 +575,15 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       const int n = X0 + sidx - (RING - 1);
       if (colmask[(long long)n * N + Y0 + ly]) {
         const long long g = ((long long)n * N + (Y0 + ly)) * N + (Z0 + lz);
+        // streaming stores: the planes are read again only by the FFT, after
+        // far more data than the caches hold has passed
 #pragma unroll
         for (int id = 0; id < kMaxMom; ++id) {
           const bool present = id < nmom || (id == kMomW && has_w);
           if (!present) continue;
           const int pos = id < nmom ? id : nmom;
-          if (ga.interlace) planar[(2LL * pos + (TWIN ? 1 : 0)) * ps + g] = a[id];
-          else planar[(long long)pos * ps + g] = a[id];
+          if (ga.interlace) __builtin_nontemporal_store(a[id], &planar[(2LL * pos + (TWIN ? 1 : 0)) * ps + g]);
+          else __builtin_nontemporal_store(a[id], &planar[(long long)pos * ps + g]);
         }
         if (!TWIN && !ga.interlace && ((nmom + (has_w ? 1 : 0)) & 1))
           planar[(long long)(nmom + (has_w ? 1 : 0)) * ps + g] = 0.f;

@@ -39,7 +39,7 @@ constexpr int kXCols = 112;       // columns (7 tiles)
 constexpr int kXMaxRows = 768;    // pairs
 constexpr int kXKC = 64;          // cells per LDS stage (2 MFMA k-steps)
 constexpr int kXUPad = kXKC + 4;  // FP32 row stride of the staged F_0 shells (16-byte aligned rows)
-constexpr int kXBPad = kXKC + 8;  // bf16 row stride of the staged B operand (16-byte aligned rows)
+constexpr int kXBPad = kXKC + 16; // bf16 row stride of the staged B operand (16-byte aligned rows; 40 dwords measured fastest)
 constexpr int kXMaxB = 37;        // bins
 constexpr int kXPf = (kXCols * (kXKC / 2) + kXThreads - 1) / kXThreads;  // cell pairs per thread per stage
 
