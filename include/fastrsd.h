@@ -61,7 +61,7 @@ typedef struct frsd_plan frsd_plan;
 /* Estimator parameters (host struct, copied by frsd_plan_create). */
 typedef struct {
   int32_t n_grid;      /* N, FFT mesh side: 2^a 3^b 5^c 7^d, multiple of 16, 32..1024 */
-  int32_t order;       /* mass assignment order p: 1 NGP, 2 CIC, 3 TSC                 */
+  int32_t order;       /* mass assignment order p: 1 NGP, 2 CIC, 3 TSC, 4 PCS          */
   int32_t interlace;   /* 1: interlaced twin grid at half-cell offset (Sec. III.A)    */
   int32_t compensate;  /* 1: divide by prod_d sinc(pi n_d / N)^p                      */
   int32_t ell_max;     /* 0, 2 or 4: multipoles computed (1, 7 or 22 moment meshes)   */

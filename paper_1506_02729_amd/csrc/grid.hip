@@ -12,7 +12,8 @@
 // block grown by the kernel support) in LDS, in cell order, and each thread
 // walks the contiguous runs of objects in the RW^3 cells around its node
 // (RW = 4 for TSC: floor cells i-2..i+1 reach the main node i and i-1..i+1
-// the twin node i+1/2).  The line of sight of an object is rebuilt from its
+// the twin node i+1/2; RW = 5 for PCS: i-2..i+1 and i-2..i+2).  FP32 plans
+// of orders 1-3 use the x-sweep form below instead.  The line of sight of an object is rebuilt from its
 // position and the observer (the true position, not the periodic image,
 // for blocks at the box faces).
 //
@@ -41,7 +42,7 @@ namespace frsd {
 
 constexpr int kBX = 4, kBY = 8, kBZ = 16;
 constexpr int kGThreads = kBX * kBY * kBZ;  // one (main, twin) node pair per thread
-constexpr int kGCellsMax = 1536;            // cells of the grown block (77 columns x 19 for TSC)
+constexpr int kGCellsMax = 1920;            // cells of a grown block (96 columns x 20 for PCS, 77 x 19 for TSC)
 constexpr int kGStageBytes = 65536;         // staged object records (two workgroups per CU)
 
 template <typename T>
@@ -54,6 +55,7 @@ template <int P> struct Win;
 template <> struct Win<1> { static constexpr int LO = -1, HI = 0; };
 template <> struct Win<2> { static constexpr int LO = -1, HI = 1; };
 template <> struct Win<3> { static constexpr int LO = -2, HI = 1; };
+template <> struct Win<4> { static constexpr int LO = -2, HI = 2; };  // main i-2..i+1, twin i-2..i+2
 
 // Assignment kernel of order P at distance d (grid units); NGP is the
 // half-open cell [-1/2, 1/2).
@@ -63,12 +65,19 @@ __device__ __forceinline__ T kernel_w(T d) {
     return (d >= T(-0.5) && d < T(0.5)) ? T(1) : T(0);
   } else if constexpr (P == 2) {
     return fmax(T(1) - fabs(d), T(0));
-  } else {
+  } else if constexpr (P == 3) {
     // both pieces evaluated, then selected: no divergent branch
     const T a = fabs(d);
     const T b = fmax(T(1.5) - a, T(0));
     const T inner = T(0.75) - a * a, outer = T(0.5) * b * b;
     return a < T(0.5) ? inner : outer;
+  } else {
+    // cubic B-spline (PCS): (4 - 6 a^2 + 3 a^3) / 6 for a < 1, (2 - a)^3 / 6 for 1 <= a < 2
+    static_assert(P == 4, "orders 1..4");
+    const T a = fabs(d);
+    const T b = fmax(T(2) - a, T(0));
+    const T inner = (T(4) + a * a * (T(3) * a - T(6))) * T(1.0 / 6.0), outer = b * b * b * T(1.0 / 6.0);
+    return a < T(1) ? inner : outer;
   }
 }
 
@@ -170,8 +179,8 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 
   extern __shared__ unsigned char smem_raw[];
   Rec4<T> *st = reinterpret_cast<Rec4<T> *>(smem_raw);  // staged records, block-relative coordinates
-  __shared__ int cst[kGCellsMax + 1];                    // staged start of each grown-block cell
-  __shared__ int gsrc[kGCellsMax];                       // first sorted record of each cell
+  __shared__ int cst[NCELL + 1];                         // staged start of each grown-block cell
+  __shared__ int gsrc[NCELL];                            // first sorted record of each cell
   __shared__ int scan_tmp[kGThreads];
 
   const int N = ga.N;
@@ -620,7 +629,7 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
                                                ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
-  if constexpr (std::is_same<T, float>::value) {
+  if constexpr (std::is_same<T, float>::value && P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
       const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
       FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<P, false>), dim3(nblk), dim3(kSThreads), 0, s,
@@ -656,7 +665,8 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   switch (pl->p.order) {
     case 1: rc = launch_grid<T, 1>(pl, ws, s); break;
     case 2: rc = launch_grid<T, 2>(pl, ws, s); break;
-    default: rc = launch_grid<T, 3>(pl, ws, s); break;
+    case 3: rc = launch_grid<T, 3>(pl, ws, s); break;
+    default: rc = launch_grid<T, 4>(pl, ws, s); break;
   }
   if (rc) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),

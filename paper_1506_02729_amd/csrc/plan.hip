@@ -116,7 +116,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   const frsd_params &p = *params;
   if (p.n_grid < 32 || p.n_grid > 1024 || p.n_grid % 16 != 0 || !is_smooth(p.n_grid))
     return fail(FRSD_EINVAL, "n_grid must be 2^a 3^b 5^c 7^d, a multiple of 16, in [32, 1024]");
-  if (p.order < 1 || p.order > 3) return fail(FRSD_EINVAL, "order must be 1 (NGP), 2 (CIC) or 3 (TSC)");
+  if (p.order < 1 || p.order > 4) return fail(FRSD_EINVAL, "order must be 1 (NGP), 2 (CIC), 3 (TSC) or 4 (PCS)");
   if (p.ell_max != 0 && p.ell_max != 2 && p.ell_max != 4) return fail(FRSD_EINVAL, "ell_max must be 0, 2 or 4");
   if (p.precision != FRSD_F32 && p.precision != FRSD_F64) return fail(FRSD_EINVAL, "precision must be 32 or 64");
   if (!(p.box > 0) || !std::isfinite(p.box)) return fail(FRSD_EINVAL, "box must be positive");

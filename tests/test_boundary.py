@@ -43,7 +43,7 @@ def test_plan_validation_on_host():
     assert F.frsd_plan_workspace_bytes(h) > 64**3 * 8
     F.frsd_plan_destroy(h)
     bad = [
-        dict(n_grid=100), dict(n_grid=16), dict(order=4), dict(ell_max=3), dict(precision=16),
+        dict(n_grid=100), dict(n_grid=16), dict(order=5), dict(ell_max=3), dict(precision=16),
         dict(pk_nbins=17),                     # beyond Nyquist
         dict(pk_dk=0.0), dict(box=-1.0),
         dict(bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=11),   # bk beyond Nyquist

@@ -130,7 +130,8 @@ def _bk_case(seed, N=48, order=3, interlace=True, ell_max=4, nbk=5, n_gal=3000, 
 
 
 @pytest.mark.parametrize("precision,order,interlace", [(64, 3, True), (32, 3, True), (64, 1, False),
-                                                       (32, 2, True)])
+                                                       (32, 2, True), (64, 4, True), (32, 4, True),
+                                                       (32, 4, False)])
 def test_pk_bk_interlaced(gpu_lib, precision, order, interlace):
     _log(f"case: pk+bk 48^3 order={order} interlace={interlace} precision={precision}")
     gal, ran, alpha, prm = _bk_case(7 + order, order=order, interlace=interlace)
@@ -184,7 +185,8 @@ def test_radix5_triangle_grids(gpu_lib, precision, m_gpu):
     _check_bk(out, refb, prm, precision, plan)
 
 
-@pytest.mark.parametrize("precision,order,interlace", [(64, 3, True), (32, 3, True), (64, 2, False)])
+@pytest.mark.parametrize("precision,order,interlace", [(64, 3, True), (32, 3, True), (64, 2, False),
+                                                       (32, 4, True)])
 def test_sparse_survey_region(gpu_lib, precision, order, interlace):
     """Objects confined to a region that wraps the periodic x boundary and
     covers a band of y, plus one isolated pair of objects: most node columns
@@ -217,10 +219,12 @@ def test_sparse_survey_region(gpu_lib, precision, order, interlace):
     _check_bk(out, refb, prm, precision, plan)
 
 
-@pytest.mark.parametrize("order,interlace", [(1, True), (2, True), (3, True), (1, False), (3, False)])
+@pytest.mark.parametrize("order,interlace", [(1, True), (2, True), (3, True), (1, False), (3, False),
+                                             (4, True), (4, False)])
 def test_fp32_assignment_orders_64(gpu_lib, order, interlace):
-    """FP32 plans on N = 64 (a multiple of 64: the x-sweep assignment) for
-    every order with and without interlacing, against the FP64 oracle."""
+    """FP32 plans on N = 64 (a multiple of 64: the x-sweep assignment for
+    orders 1-3, the gather for PCS) for every order with and without
+    interlacing, against the FP64 oracle."""
     _log(f"case: pk+bk 64^3 FP32 order={order} interlace={interlace}")
     gal, ran, alpha, prm = _bk_case(41 + order, N=64, order=order, interlace=interlace, n_gal=4000, n_ran=20000)
     fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
