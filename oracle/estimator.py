@@ -372,7 +372,9 @@ def shell_sums(fields, prm: Params, kmin, dk, nbins):
     """Full-grid shell sums over |k| bins (eq. shell).
 
     N_b = number of modes, k_eff = mean |k|, S_l0 = sum Re[A_l A_0^*],
-    S_0w = sum Re[A_0 A_0w^*], S_lw = sum Re[A_l A_0w^*].
+    S_22 = sum |A_2|^2 (the autocorrelation of the quadrupole field, used by
+    the split hexadecapole of Sec. II.B eq. P4fast), S_0w = sum Re[A_0 A_0w^*],
+    S_lw = sum Re[A_l A_0w^*].
     """
     N = prm.n_grid
     nx, ny, nz = half_grid(N)
@@ -394,6 +396,8 @@ def shell_sums(fields, prm: Params, kmin, dk, nbins):
             prod_ = fields[ell].ravel()[sel] * np.conj(A0)
             out[f"S{ell}0"] = np.bincount(bb, weights=wsel * prod_.real, minlength=nbins)
             out[f"C{ell}0"] = np.bincount(bb, weights=wsel * np.abs(prod_), minlength=nbins)
+    if 2 in fields:
+        out["S22"] = np.bincount(bb, weights=wsel * np.abs(fields[2].ravel()[sel]) ** 2, minlength=nbins)
     if "w" in fields:
         Aw = np.conj(fields["w"].ravel()[sel])
         for ell in (0, 2, 4):
@@ -404,7 +408,16 @@ def shell_sums(fields, prm: Params, kmin, dk, nbins):
 
 
 def pk_multipoles(gal, ran, alpha, prm: Params, fields=None):
-    """P_0, P_2, P_4 of the survey estimator (Sec. III.A eqs. P0_impl-P4_impl)."""
+    """P_0, P_2, P_4 of the survey estimator (Sec. III.A eqs. P0_impl-P4_impl),
+    and the split hexadecapole P_4b (Sec. II.B eqs. factorizeL4, split, P4fast).
+
+    P_4b: L_4 = 35/18 L_2^2 - 5/9 L_2 - 7/18 with L_2^2 split over the two
+    objects of a pair turns 9 F_4 F_0^* into 35/2 |F_2|^2 - 5 F_2 F_0^* -
+    7/2 |F_0|^2, so P_4b = (35/2 S_22 - 5 S_20 - 7/2 S_00) / (N_b I22) with the
+    raw S_00: the self pairs (an object with itself, where the split is exact)
+    then carry the same zero-mean term as in P_4, and no N_0 is subtracted.
+    Needs only the monopole and quadrupole fields (7 FFTs).
+    """
     if fields is None:
         fields = multipole_fields(gal, ran, alpha, prm)
     sc = scalars(gal, ran, alpha)
@@ -416,6 +429,8 @@ def pk_multipoles(gal, ran, alpha, prm: Params, fields=None):
             res["P2"] = 5.0 * res["S20"] / (nb * sc["I22"])
         if "S40" in res:
             res["P4"] = 9.0 * res["S40"] / (nb * sc["I22"])
+        if "S22" in res:
+            res["P4b"] = (17.5 * res["S22"] - 5.0 * res["S20"] - 3.5 * res["S00"]) / (nb * sc["I22"])
     res.update(sc)
     return res
 

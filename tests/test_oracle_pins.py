@@ -246,6 +246,55 @@ def test_plane_parallel_limit_multipoles_follow_legendre_of_kz():
         assert np.max(np.abs(f[ell] - est.legendre(ell, mu) * f[0])) <= 1e-10 * scale
 
 
+def _split_identity_gap(res):
+    """|35/2 S22 - 5 S20 - 7/2 S00 - 9 S40| per bin and the scale it is measured against."""
+    lhs = 17.5 * res["S22"] - 5.0 * res["S20"] - 3.5 * res["S00"]
+    return np.abs(lhs - 9.0 * res["S40"]), 17.5 * res["S22"] + 3.5 * res["S00"]
+
+
+def test_split_hexadecapole_exact_for_self_pairs():
+    """Sec. II.B eqs. factorizeL4, split, P4fast: splitting L_2^2 over the two
+    objects of a pair is exact when they are the same object, so with a single
+    object (every pair a self pair) 35/2 S22 - 5 S20 - 7/2 S00 = 9 S40 bin by
+    bin for any observer, and P_4b = P_4."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    one = synth.uniform_box(1, 500.0, rng, nbar=1e-4, w=0.9)
+    kf = 2 * math.pi / 500.0
+    prm = est.Params(n_grid=32, box=500.0, observer=(-310.0, 120.0, 640.0), order=3, ell_max=4,
+                     pk_kmin=0.0, pk_dk=2 * kf, pk_nbins=8)
+    res = est.pk_multipoles(one, None, 0.0, prm)
+    gap, scale = _split_identity_gap(res)
+    assert np.max(gap / scale) < 1e-12
+    # two objects seen along different lines of sight: the cross pairs are
+    # not split exactly, so the identity is not vacuous
+    two = synth.uniform_box(2, 500.0, rng, nbar=1e-4, w=0.9)
+    gap2, scale2 = _split_identity_gap(est.pk_multipoles(two, None, 0.0, prm))
+    assert np.max(gap2 / scale2) > 1e-5
+
+
+def test_split_hexadecapole_plane_parallel_and_seven_fields():
+    """Plane-parallel limit (every line of sight along z): L_2 of each object
+    is L_2(khat_z), the split is exact and P_4b = P_4 per bin; P_4b needs only
+    the monopole and quadrupole fields, so an ell_max = 2 plan gives the same
+    P_4b."""
+    gal, ran, alpha = _tiny(33)
+    kf = 2 * math.pi / 500.0
+    D = 1e12 * 500.0
+    kw = dict(n_grid=32, box=500.0, observer=(250.0, 250.0, -D), order=3, pk_kmin=0.0, pk_dk=2 * kf,
+              pk_nbins=8)
+    r4 = est.pk_multipoles(gal, ran, alpha, est.Params(ell_max=4, **kw))
+    gap, scale = _split_identity_gap(r4)
+    assert np.max(gap / scale) < 1e-9
+    floor = (17.5 * r4["S22"] + 3.5 * r4["S00"]) / (r4["n_modes"] * r4["I22"])
+    assert np.max(np.abs(r4["P4b"] - r4["P4"]) / floor) < 1e-9
+    # a general observer: P_4b differs from P_4
+    r4g = est.pk_multipoles(gal, ran, alpha, est.Params(ell_max=4, **dict(kw, observer=(-300.0, -300.0, -300.0))))
+    assert np.max(np.abs(r4g["P4b"] - r4g["P4"]) / floor) > 1e-4
+    r2 = est.pk_multipoles(gal, ran, alpha, est.Params(ell_max=2, **kw))
+    assert "P4" not in r2
+    np.testing.assert_allclose(r2["P4b"], r4["P4b"], rtol=1e-12)
+
+
 def test_kaiser_deterministic_ratio_and_continuum_limit():
     N, box, fgrowth = 48, 1000.0, 0.7
     rng = np.random.Generator(np.random.PCG64(77))
