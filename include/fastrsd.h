@@ -101,6 +101,11 @@ typedef struct {
   double *scalars;   /* [I22, N_0, I33, W3]: I22 = alpha sum_r nbar w^2 (eq. I22def),
                         N_0 = (sum_g + alpha^2 sum_r) w^2 (eq. N0true),
                         I33 = alpha sum_r nbar^2 w^3, W3 = (sum_g - alpha^3 sum_r) w^3 */
+  double *p4b;       /* optional (NULL: not written).  Split hexadecapole of Sec. II.B
+                        eqs. (factorizeL4), (split), (P4fast): (35/2 S22 - 5 S20 -
+                        7/2 S00) / (N_b I22) with the raw S00; needs ell_max >= 2 only
+                        (7 FFTs), NaN for ell_max 0                                  */
+  double *s22;       /* optional (NULL: not written).  Raw sum_b |F_2|^2              */
 } frsd_pk_out;
 
 /* Bispectrum outputs: caller-owned DEVICE arrays of ntri entries, one per

@@ -85,7 +85,7 @@ struct Layout {
 template <typename T> struct alignas(4 * sizeof(T)) Rec4 { T x, y, z, w; };
 inline size_t sorted_bytes(size_t nobj, size_t tbytes) { return ((nobj * 4 * tbytes) + 255) & ~(size_t)255; }
 
-constexpr int kBinSums = 8;     // per bin: count, sum|k|, S00, S20, S40, S0w, S2w, S4w
+constexpr int kBinSums = 8;     // per bin: count, sum|k|, then S00 S20 S40 S22 (P bins) or -, -, -, S0w S2w S4w (B bins)
 constexpr int kScalars = 4;     // I22, N0, I33, W3
 constexpr int kIngestBlocks = 1024;
 constexpr int kBinBlocks = 2048;

@@ -67,8 +67,10 @@ __device__ __forceinline__ void wave_run_add(int key, double *v, double *lds_bin
 
 // Per-mode sums reduced by the binning kernel: GEOM (once per plan) the
 // mode count and sum |k| of every bin; otherwise the data sums, (S00, S20,
-// S40) for the P_ell bins and (S0w, S2w, S4w) for the bispectrum bins.
-template <bool GEOM> struct BinValues { static constexpr int n = GEOM ? 2 : 3; };
+// S40, S22) for the P_ell bins and (S0w, S2w, S4w, unused) for the
+// bispectrum bins.  S22 = sum |F_2|^2 feeds the split hexadecapole P_4b
+// (Sec. II.B eq. P4fast).
+template <bool GEOM> struct BinValues { static constexpr int n = GEOM ? 2 : 4; };
 
 // Rank-2 and rank-4 monomials of k-hat times their multiplicities in the
 // full contraction, in moment-table order (xx yy zz xy yz zx; xxxx yyyy zzzz
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
                                                       double *part) {
   using C = cplx_t<T>;
   constexpr int NV = BinValues<GEOM>::n;
-  __shared__ double bins[kMaxBinsAll * 3];
+  __shared__ double bins[kMaxBinsAll * NV];
   // per-axis factors for |n| <= nmax: interlacing phase exp(-i pi n / N)
   // (cos, sin) and the inverse window 1 / sinc(pi n / N)^p
   __shared__ double tcos[kBinTab], tsin[kBinTab], tiw[kBinTab];
@@ -256,9 +258,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
       const double S0w = A[0][0] * A[3][0] + A[0][1] * A[3][1];
       const double S2w = A[1][0] * A[3][0] + A[1][1] * A[3][1];
       const double S4w = A[2][0] * A[3][0] + A[2][1] * A[3][1];
+      const double S22 = A[1][0] * A[1][0] + A[1][1] * A[1][1];
       // each half-space mode stands for n and -n
-      vp[0] = 2.0 * S00; vp[NV > 1 ? 1 : 0] = 2.0 * S20; vp[NV - 1] = 2.0 * S40;
-      vb[0] = 2.0 * S0w; vb[NV > 1 ? 1 : 0] = 2.0 * S2w; vb[NV - 1] = 2.0 * S4w;
+      if constexpr (NV == 4) {
+        vp[0] = 2.0 * S00; vp[1] = 2.0 * S20; vp[2] = 2.0 * S40; vp[3] = 2.0 * S22;
+        vb[0] = 2.0 * S0w; vb[1] = 2.0 * S2w; vb[2] = 2.0 * S4w; vb[3] = 0.0;
+      }
       if (kb >= 0 && lowk) {
         // A_0, A_2, A_4 at n and -n on the low-k cube [-nc, nc]^3
         const int D = a.D, nc = a.nc_b;
@@ -281,7 +286,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
 
 // Sum of the per-block partials, one wavefront per (bin, quantity) reading
 // its nblk contiguous partials, into the kBinSums slots of the bin: geometry
-// into slots 0-1, data sums into 2-4 (P_ell bins) or 5-7 (bispectrum bins).
+// into slots 0-1, data sums into 2-5 (P_ell bins: S00 S20 S40 S22) or 5-7
+// (bispectrum bins: S0w S2w S4w; their fourth quantity is not kept).
 __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb,
                                                     int geom, double *sum) {
   const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -289,8 +295,9 @@ __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk
   double s = 0;
   for (int b = lane; b < nblk; b += 64) s += part[(long long)i * nblk + b];
   s = wave_sum(s);
-  if (lane == 0) {
-    const int bin = i / nv, q = i - bin * nv;
+  const int bin = i / nv, q = i - bin * nv;
+  const bool keep = geom || bin < pk_nb || q < 3;
+  if (lane == 0 && keep) {
     const int slot = geom ? q : (bin < pk_nb ? 2 + q : 5 + q);
     sum[bin * kBinSums + slot] = s;
   }
@@ -298,7 +305,7 @@ __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk
 
 __global__ void k_pk_final(const double *sum, const double *scal, int nb, int ell_max, int64_t *n_modes, double *k_eff,
                            double *p0, double *p2, double *p4, double *s00, double *s20, double *s40,
-                           double *scal_out) {
+                           double *scal_out, double *p4b, double *s22) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const double I22 = scal[0], N0 = scal[1];
   if (b == 0 && scal_out)
@@ -312,6 +319,11 @@ __global__ void k_pk_final(const double *sum, const double *scal, int nb, int el
   p0[b] = (v[2] / cnt - N0) / I22;
   p2[b] = ell_max >= 2 ? 5.0 * v[3] / (cnt * I22) : __builtin_nan("");
   p4[b] = ell_max >= 4 ? 9.0 * v[4] / (cnt * I22) : __builtin_nan("");
+  // split hexadecapole (Sec. II.B eqs. factorizeL4, split, P4fast):
+  // L_4 = 35/18 L_2^2 - 5/9 L_2 - 7/18 with L_2^2 split over the pair, times
+  // 9, over N_b I22; the raw S00 keeps the self pairs' term the same as in P_4
+  if (s22) s22[b] = v[5];
+  if (p4b) p4b[b] = ell_max >= 2 ? (17.5 * v[5] - 5.0 * v[3] - 3.5 * v[2]) / (cnt * I22) : __builtin_nan("");
 }
 
 static BinArgs bin_args(const frsd_plan *pl) {
@@ -387,7 +399,7 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
                      ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
-                     out->p4, out->s00, out->s20, out->s40, out->scalars));
+                     out->p4, out->s00, out->s20, out->s40, out->scalars, out->p4b, out->s22));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

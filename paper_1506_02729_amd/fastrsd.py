@@ -57,7 +57,7 @@ class frsd_catalog(ctypes.Structure):
 
 class frsd_pk_out(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
-                ("n_modes", "k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "scalars")]
+                ("n_modes", "k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "scalars", "p4b", "s22")]
 
 
 class frsd_bk_out(ctypes.Structure):
@@ -257,7 +257,7 @@ class Plan:
         nb = cfg.pk_nbins
         f64 = dict(dtype=torch.float64, device=self.device)
         self.pk_buf = {"n_modes": torch.zeros(nb, dtype=torch.int64, device=self.device)}
-        for key in ("k_eff", "p0", "p2", "p4", "s00", "s20", "s40"):
+        for key in ("k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "p4b", "s22"):
             self.pk_buf[key] = torch.zeros(nb, **f64)
         self.pk_buf["scalars"] = torch.zeros(4, **f64)
         self.ntri = frsd_bk_ntriangles(self.handle) if cfg.bk_nbins > 0 else 0

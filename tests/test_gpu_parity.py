@@ -70,6 +70,14 @@ def _check_pk(out, ref, prm, precision):
         assert np.max(e) < tol, (f"P{ell}", e)
     e = _rel(out["s00"], ref["S00"], 0)
     assert np.max(e) < tol
+    if prm.ell_max >= 2:
+        # split hexadecapole: floor from the magnitudes of its three terms
+        floor4b = (17.5 * ref["S22"] + 5.0 * ref["C20"] + 3.5 * ref["S00"]) / (nb * I22)
+        e = _rel(out["p4b"], ref["P4b"], floor4b)
+        assert np.max(e) < tol, ("P4b", e)
+        assert np.max(_rel(out["s22"], ref["S22"], 0)) < tol
+    else:
+        assert np.all(np.isnan(out["p4b"]))
 
 
 def _check_bk(out, ref, prm, precision, plan):
