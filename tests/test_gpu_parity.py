@@ -277,6 +277,36 @@ def test_empty_randoms_and_repeat_calls(gpu_lib):
     np.testing.assert_allclose(again["s20"], out["s20"], rtol=1e-12)
 
 
+def test_no_caching_by_input_identity(gpu_lib):
+    """Served requests recompute everything: the same device buffers refilled
+    with another catalogue of the same size give that catalogue's spectra
+    (each checked against the oracle), and the first catalogue again gives
+    its own spectra, on one plan and workspace."""
+    _log("case: no caching by buffer identity (FP32, 48^3, pk + bk)")
+    import torch
+    dev = torch.device("cuda:0")
+    gal_a, ran_a, alpha, prm = _bk_case(51)
+    gal_b, ran_b, _, _ = _bk_case(52)
+    plan = gpu_lib.Plan(_cfg(gpu_lib, prm, 32, len(gal_a["w"]) + len(ran_a["w"])), device=dev)
+    g = gpu_lib.device_catalog(gal_a, dev, torch.float64)
+    r = gpu_lib.device_catalog(ran_a, dev, torch.float64)
+
+    def refill(dst, src):
+        for key in ("pos", "w", "nbar"):
+            dst[key].copy_(torch.as_tensor(np.ascontiguousarray(src[key]), dtype=torch.float64))
+
+    results = []
+    for gal, ran in ((gal_a, ran_a), (gal_b, ran_b), (gal_a, ran_a)):
+        refill(g, gal)
+        refill(r, ran)
+        out = plan.run(g, r, alpha)
+        fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+        _check_pk(out, est.pk_multipoles(gal, ran, alpha, prm, fields=fields), prm, 32)
+        _check_bk(out, est.bk_multipoles(gal, ran, alpha, prm, fields=fields), prm, 32, plan)
+        results.append(out)
+    assert np.max(np.abs(results[0]["p0"] - results[1]["p0"])) > 1e-3 * np.max(np.abs(results[0]["p0"]))
+
+
 def test_out_of_box_objects_are_rejected(gpu_lib):
     _log("case: out-of-box rejection")
     gal, ran, alpha, prm = _bk_case(13, nbk=0)
