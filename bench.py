@@ -224,7 +224,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--mocks", type=int, default=16, help="distinct mocks in the pool, cycled")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="requests in flight: one plan (workspace) and HIP stream each, default priority")
     ap.add_argument("--kernel-steps", type=int, default=8,
                     help="requests served one at a time after the timed loop, for per-kernel timings and the roofline")
