@@ -225,11 +225,24 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     const size_t npair_batch = kPairBatch;
     L.lowk = take(2 * T * 3 * D * D * D);
     // intermediates sized for FP64 (the N^T indicator fields are FP64 for every plan)
-    L.buf1 = take(16 * npair_batch * D * D * M);
-    L.buf2 = take(16 * npair_batch * D * M * M);
+    const size_t buf1_bytes = 16 * npair_batch * D * D * M, buf2_bytes = 16 * npair_batch * D * M * M;
     const size_t nfield = (size_t)pl->n_ell * p.bk_nbins;
     const size_t shell_bytes = std::max(T * nfield, (size_t)8 * p.bk_nbins) * M * M * M;
-    L.shells = take(shell_bytes);
+    // The planar assignment arrays are dead outside the assignment and the
+    // first FFT pass, and the shell intermediates and fields live only inside
+    // one bispectrum call (and plan init); calls on a workspace are ordered
+    // on one stream, so the shell buffers share the planar region when they
+    // fit in it.
+    const size_t planar_bytes = 2 * T * NNN * sd.n_slot;
+    if (align256(buf1_bytes) + align256(buf2_bytes) + align256(shell_bytes) <= planar_bytes) {
+      L.buf1 = L.planar;
+      L.buf2 = L.buf1 + align256(buf1_bytes);
+      L.shells = L.buf2 + align256(buf2_bytes);
+    } else {
+      L.buf1 = take(buf1_bytes);
+      L.buf2 = take(buf2_bytes);
+      L.shells = take(shell_bytes);
+    }
     L.tri_tab = take(16 * (size_t)pl->n_out + 16 * (size_t)pl->ntri + 12 * (size_t)pl->ntri);
     L.tri_part = take(std::max(8 * (size_t)std::max(pl->n_out, (int)pl->ntri) * kTriBlocks,
                                triple_mfma_part_bytes(kTriMfmaBlocks)));
