@@ -578,7 +578,8 @@ int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s) {
     if (triple_mfma_supported(pl)) rc = triple_mfma(pl, ws, reinterpret_cast<const float *>(shells), s);
     else rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
   } else {
-    rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+    if (triple_mfma_supported(pl)) rc = triple_mfma64(pl, ws, reinterpret_cast<const double *>(shells), s);
+    else rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
   }
   if (rc) return rc;
   BkFinalArgs a{};
@@ -690,7 +691,7 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
     for (int b2 = 0; b2 < nb; ++b2)
       for (int b3 = 0; b3 <= b2; ++b3) pairs.push_back(make_int2(b2, b3));
     FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.pair_tab), pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
-    if (!f64 && triple_mfma_supported(pl)) {
+    if (triple_mfma_supported(pl)) {
       const int rc = triple_mfma_upload(pl, ws);
       if (rc) return rc;
     }

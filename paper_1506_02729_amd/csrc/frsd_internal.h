@@ -189,6 +189,7 @@ bool triple_mfma_supported(const frsd_plan *pl);
 size_t triple_mfma_part_bytes(int nwg);
 size_t triple_mfma_dense_bytes();
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
+int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);
 int triple_mfma_upload(frsd_plan *pl, void *ws);
 
 // Shell-filtered inverse FFTs on the M^3 grid (bk.hip).

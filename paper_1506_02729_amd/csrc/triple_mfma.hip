@@ -264,8 +264,143 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   }
 }
 
+// FP64 plans: the same block-sparse product on v_mfma_f64_16x16x4_f64, with
+// no operand splitting.  Lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16 x 4 by 4 x 16 step and C[l / 16 + 4 v][l % 16] in accumulator
+// register v.  A = F_0,b2 F_0,b3 is formed per lane from the staged
+// monopole shells (one product per lane and k-step); partials stay FP64.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int kZKC = 32;         // cells per LDS stage (8 MFMA k-steps of 4)
+constexpr int kZPad = kZKC + 2;  // doubles per staged row: rows 68 dwords apart keep 8-byte reads conflict-free
+constexpr int kZPf = (kXCols * (kZKC / 2) + kXThreads - 1) / kXThreads;  // cell pairs per thread per stage
+
+__global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__restrict__ f, XArgs a, XJobs jobs,
+                                                               const int2 *__restrict__ pairs,
+                                                               double *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) double U2[2][kXMaxB + 1][kZPad];  // row kXMaxB stays zero
+  __shared__ __attribute__((aligned(16))) double B2[2][kXCols][kZPad];
+  __shared__ uint32_t prs[kXMaxRows];  // U row offsets (doubles) of b2 (low half) and b3 (high half)
+  __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
+  static_assert(kXMaxB * kZPad < 65536, "row offsets must fit 16 bits");
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15;  // row of A, column of B and C
+  const int lk = lane >> 4;  // k of A and B
+  const int nj = jobs.nj[wave];
+  int jrt[kXMaxJobs], jcb[kXMaxJobs];
+  int jbits = 0;  // bit j: job j present; bit 8 + j: job j starts a row tile
+#pragma unroll
+  for (int j = 0; j < kXMaxJobs; ++j) {
+    jrt[j] = __builtin_amdgcn_readfirstlane((int)jobs.rt[wave][j]) * 16;
+    jcb[j] = __builtin_amdgcn_readfirstlane((int)jobs.ct[wave][j]) * 16 * kZPad;
+    if (j < nj) jbits |= 1 << j;
+    if (j < nj && (j == 0 || jrt[j] != jrt[j - 1])) jbits |= 1 << (8 + j);
+  }
+  jbits = __builtin_amdgcn_readfirstlane(jbits);
+  f64x4_t acc[kXMaxJobs];
+#pragma unroll
+  for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+
+  for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
+    uint32_t v = (uint32_t)(kXMaxB * kZPad) * 0x10001u;
+    if (i < a.npair) { const int2 p = pairs[i]; v = (uint32_t)(p.x * kZPad) | ((uint32_t)(p.y * kZPad) << 16); }
+    prs[i] = v;
+  }
+  for (int i = threadIdx.x; i < 2 * kZPad; i += kXThreads) U2[i / kZPad][kXMaxB][i % kZPad] = 0.0;
+  for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
+    const int l = i / a.nb, b1 = i - l * a.nb;
+    cmap[i] = (uint8_t)(b1 * a.n_ell + l);
+  }
+  for (int i = threadIdx.x; i < 2 * (kXCols - a.ncol) * kZPad; i += kXThreads) {
+    const int bsel = i & 1, ii = i >> 1;
+    B2[bsel][a.ncol + ii / kZPad][ii % kZPad] = 0.0;
+  }
+
+  const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
+  const long long c_end = min(a.ncell, c_begin + a.cells_per_wg);
+  const int npe = a.ncol * (kZKC / 2);  // cell pairs per stage
+  const bool even = (a.ncell & 1) == 0;
+  double2 pf[kZPf];
+  auto load = [&](long long c0) {
+    const int len = (int)min((long long)kZKC, c_end - c0);
+#pragma unroll
+    for (int q = 0; q < kZPf; ++q) {
+      const int e = threadIdx.x + q * kXThreads;
+      const int fl = e >> 4, k = 2 * (e & 15);
+      double2 v = make_double2(0.0, 0.0);
+      if (e < npe) {
+        const double *src = f + (long long)fl * a.ncell + c0 + k;
+        if (k + 1 < len) {
+          if (even) v = *reinterpret_cast<const double2 *>(src);
+          else v = make_double2(src[0], src[1]);
+        } else if (k < len) {
+          v.x = src[0];
+        }
+      }
+      pf[q] = v;
+    }
+  };
+  auto store = [&](int bsel) {
+#pragma unroll
+    for (int q = 0; q < kZPf; ++q) {
+      const int e = threadIdx.x + q * kXThreads;
+      if (e < npe) {
+        const int fl = e >> 4, k = 2 * (e & 15);
+        *reinterpret_cast<double2 *>(&B2[bsel][cmap[fl]][k]) = pf[q];
+        if (fl < a.nb) *reinterpret_cast<double2 *>(&U2[bsel][fl][k]) = pf[q];
+      }
+    }
+  };
+
+  if (c_begin < c_end) {
+    load(c_begin);
+    __syncthreads();  // tables above written
+    store(0);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (long long c0 = c_begin; c0 < c_end; c0 += kZKC, cur ^= 1) {
+    const bool more = c0 + kZKC < c_end;
+    if (more) load(c0 + kZKC);
+    int jb = jbits;
+    asm volatile("" : "+s"(jb));  // job tests stay scalar branches
+    const double *Ub = &U2[cur][0][0];
+    const double *Bb = &B2[cur][0][0] + li * kZPad;
+#pragma unroll
+    for (int ks = 0; ks < kZKC / 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      double av = 0.0;
+#pragma unroll
+      for (int j = 0; j < kXMaxJobs; ++j) {
+        if ((jb >> j) & 1) {
+          if ((jb >> (8 + j)) & 1) {
+            const unsigned pr = prs[jrt[j] + li];
+            av = Ub[(pr & 0xffffu) + kk] * Ub[(pr >> 16) + kk];
+          }
+          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bb[jcb[j] + kk], acc[j], 0, 0, 0);
+        }
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  double *out = part + (long long)blockIdx.x * a.njobs * 256;
+#pragma unroll
+  for (int j = 0; j < kXMaxJobs; ++j) {
+    if (j < nj) {
+      double *t = out + (long long)(jobs.first[wave] + j) * 256;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t[(lk + 4 * v) * 16 + li] = acc[j][v];
+    }
+  }
+}
+
+
 // Sum over workgroups (FP64) of the partial tiles, one thread per entry.
-__global__ void k_triple_mfma_reduce(const float *__restrict__ part, int nwg, int nvals, double *__restrict__ sum) {
+template <typename TP>
+__global__ void k_triple_mfma_reduce(const TP *__restrict__ part, int nwg, int nvals, double *__restrict__ sum) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvals) return;
   // four interleaved sums keep several loads in flight
@@ -384,7 +519,7 @@ bool triple_mfma_supported(const frsd_plan *pl) {
   return make_jobs(pl, &j, &tj, &n);
 }
 
-size_t triple_mfma_part_bytes(int nwg) { return sizeof(float) * (size_t)nwg * kXWaves * kXMaxJobs * 256; }
+size_t triple_mfma_part_bytes(int nwg) { return sizeof(double) * (size_t)nwg * kXWaves * kXMaxJobs * 256; }
 size_t triple_mfma_dense_bytes() {
   return sizeof(double) * (size_t)kXWaves * kXMaxJobs * 256 + sizeof(int16_t) * (kXMaxRows / 16) * 7 + 256;
 }
@@ -412,8 +547,42 @@ int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
                                              ws_ptr<const int2>(ws, L.pair_tab), ws_ptr<float>(ws, L.tri_part)));
   const int nvals = njobs * 256;
   FRSD_TIMED("tri_reduce", s,
-             hipLaunchKernelGGL(k_triple_mfma_reduce, dim3((nvals + 255) / 256), dim3(256), 0, s,
+             hipLaunchKernelGGL(k_triple_mfma_reduce<float>, dim3((nvals + 255) / 256), dim3(256), 0, s,
                                 ws_ptr<const float>(ws, L.tri_part), nwg, nvals, dense));
+  FRSD_TIMED("tri_gather", s,
+             hipLaunchKernelGGL(k_triple_mfma_gather, dim3((pl->n_out + 255) / 256), dim3(256), 0, s, dense,
+                                ws_ptr<const int4>(ws, L.tri_tab), tj, a.nb, a.n_ell, pl->n_out,
+                                ws_ptr<double>(ws, L.tri_sum)));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+// FP64 plans: the same job tiles on the FP64 matrix cores.
+int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) {
+  const Layout &L = pl->L;
+  XArgs a{};
+  a.ncell = (long long)pl->M * pl->M * pl->M;
+  a.nb = pl->p.bk_nbins;
+  a.n_ell = pl->n_ell;
+  a.ncol = pl->n_ell * a.nb;
+  a.npair = a.nb * (a.nb + 1) / 2;
+  XJobs jobs;
+  std::vector<int16_t> tile_job;
+  int njobs = 0;
+  if (!make_jobs(pl, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
+  a.njobs = njobs;
+  const int nwg = kTriMfmaBlocks;
+  long long per = (a.ncell + nwg - 1) / nwg;
+  per = (per + kZKC - 1) / kZKC * kZKC;
+  a.cells_per_wg = per;
+  double *dense = ws_ptr<double>(ws, L.tri_dense);
+  const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
+  FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple_mfma64, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
+                                             ws_ptr<const int2>(ws, L.pair_tab), ws_ptr<double>(ws, L.tri_part)));
+  const int nvals = njobs * 256;
+  FRSD_TIMED("tri_reduce", s,
+             hipLaunchKernelGGL(k_triple_mfma_reduce<double>, dim3((nvals + 255) / 256), dim3(256), 0, s,
+                                ws_ptr<const double>(ws, L.tri_part), nwg, nvals, dense));
   FRSD_TIMED("tri_gather", s,
              hipLaunchKernelGGL(k_triple_mfma_gather, dim3((pl->n_out + 255) / 256), dim3(256), 0, s, dense,
                                 ws_ptr<const int4>(ws, L.tri_tab), tj, a.nb, a.n_ell, pl->n_out,
