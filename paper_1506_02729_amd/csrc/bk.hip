@@ -686,11 +686,7 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
     FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tri_tab), tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice));
     FRSD_HIP(hipMemcpy(ws_ptr<int4>(ws, L.tri_tab) + tab.size(), pl->tri.data(), pl->tri.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice));
-    // rows of the dense contraction: pair r = b2 (b2 + 1) / 2 + b3, b2 >= b3
-    std::vector<int2> pairs;
-    for (int b2 = 0; b2 < nb; ++b2)
-      for (int b3 = 0; b3 <= b2; ++b3) pairs.push_back(make_int2(b2, b3));
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.pair_tab), pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
+    // the matrix-core contraction's tables (job tiles, pair rows)
     if (triple_mfma_supported(pl)) {
       const int rc = triple_mfma_upload(pl, ws);
       if (rc) return rc;

@@ -3,7 +3,7 @@
 // The bispectrum triangle sums T_ell(b1,b2,b3) = sum_x F_{ell,b1}(x)
 // F_{0,b2}(x) F_{0,b3}(x) (Sec. III.B eq. Factorize) are entries of one
 // product C = A B summed over the M^3 cells x, with
-//   rows  r = (b2, b3), b2 >= b3, r = b2 (b2 + 1) / 2 + b3:  A[r][x] = F_{0,b2}(x) F_{0,b3}(x)
+//   rows  r = the pairs (b2, b3), b2 >= b3, in the order of pair_rows below:  A[r][x] = F_{0,b2}(x) F_{0,b3}(x)
 //   cols  c = n_ell b1 + l (b1-major):                       B[x][c] = F_{ell_l,b1}(x)
 // A is formed on the fly from the staged F_0 shells, so only the shell
 // fields themselves are read from HBM.  Only the 16 x 16 tiles of C that
@@ -415,6 +415,8 @@ __global__ void k_triple_mfma_reduce(const TP *__restrict__ part, int nwg, int n
 }
 
 // Gather the listed outputs (triangle t, multipole l) from the job tiles.
+// tile_job holds the (row tile, column tile) -> job table followed by the
+// row of each pair b2 (b2 + 1) / 2 + b3.
 __global__ void k_triple_mfma_gather(const double *__restrict__ dense, const int4 *__restrict__ otab,
                                      const int16_t *__restrict__ tile_job, int nb, int n_ell, int nout,
                                      double *__restrict__ tsum) {
@@ -422,20 +424,45 @@ __global__ void k_triple_mfma_gather(const double *__restrict__ dense, const int
   if (o >= nout) return;
   const int4 e = otab[o];  // (field l * nb + b1, b2, b3)
   const int l = e.x / nb, b1 = e.x - l * nb;
-  const int r = e.y * (e.y + 1) / 2 + e.z;
+  const int r = tile_job[(kXMaxRows / 16) * 7 + e.y * (e.y + 1) / 2 + e.z];
   const int c = b1 * n_ell + l;
   const int job = tile_job[(r / 16) * 7 + c / 16];
   tsum[o] = dense[(long long)job * 256 + (r % 16) * 16 + (c % 16)];
+}
+
+// Row of each pair p = b2 (b2 + 1) / 2 + b3 in the product: pairs sorted by
+// the last 16-column tile they need, then by their first needed column, so
+// that the 16 pairs of a row tile need similar column ranges (103 instead
+// of 114 output tiles for 37 bins).  Pairs in no listed triangle go last.
+static std::vector<int> pair_rows(const frsd_plan *pl) {
+  const int nb = pl->p.bk_nbins, ne = pl->n_ell, np = nb * (nb + 1) / 2;
+  std::vector<int> lo(np, 1 << 30), hi(np, 1 << 30);
+  for (int64_t t = 0; t < pl->ntri; ++t) {
+    const int b1 = pl->tri[3 * t], b2 = pl->tri[3 * t + 1], b3 = pl->tri[3 * t + 2];
+    const int p = b2 * (b2 + 1) / 2 + b3;
+    lo[p] = std::min(lo[p], b1 * ne);
+    hi[p] = hi[p] == (1 << 30) ? b1 * ne + ne - 1 : std::max(hi[p], b1 * ne + ne - 1);
+  }
+  std::vector<int> order(np);
+  for (int p = 0; p < np; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ha = hi[a] / 16, hb = hi[b] / 16;
+    return ha != hb ? ha < hb : lo[a] < lo[b];
+  });
+  std::vector<int> row(np);
+  for (int r = 0; r < np; ++r) row[order[r]] = r;
+  return row;
 }
 
 // Host-side job list: every (row tile, column tile) holding a listed output.
 static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *tile_job, int *njobs) {
   const int nb = pl->p.bk_nbins, ne = pl->n_ell;
   const int nrt = (nb * (nb + 1) / 2 + 15) / 16;
+  const std::vector<int> row = pair_rows(pl);
   std::vector<char> need((size_t)nrt * 7, 0);
   for (int64_t t = 0; t < pl->ntri; ++t) {
     const int b1 = pl->tri[3 * t], b2 = pl->tri[3 * t + 1], b3 = pl->tri[3 * t + 2];
-    const int r = b2 * (b2 + 1) / 2 + b3;
+    const int r = row[b2 * (b2 + 1) / 2 + b3];
     for (int l = 0; l < ne; ++l) need[(r / 16) * 7 + (b1 * ne + l) / 16] = 1;
   }
   std::vector<std::pair<int, int>> list;
@@ -445,7 +472,8 @@ static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *ti
   const int n = (int)list.size();
   if (n > kXWaves * kXMaxJobs) return false;
   *jobs = XJobs{};
-  tile_job->assign((size_t)kXMaxRows / 16 * 7, (int16_t)-1);
+  tile_job->assign((size_t)kXMaxRows / 16 * 7 + kXMaxRows, (int16_t)-1);
+  for (size_t p = 0; p < row.size(); ++p) (*tile_job)[(size_t)kXMaxRows / 16 * 7 + p] = (int16_t)row[p];
 
   // Preferred: whole row tiles per wavefront (each row tile's pair products
   // formed by one wavefront only), balanced over the four SIMDs (wavefront w
@@ -521,7 +549,8 @@ bool triple_mfma_supported(const frsd_plan *pl) {
 
 size_t triple_mfma_part_bytes(int nwg) { return sizeof(double) * (size_t)nwg * kXWaves * kXMaxJobs * 256; }
 size_t triple_mfma_dense_bytes() {
-  return sizeof(double) * (size_t)kXWaves * kXMaxJobs * 256 + sizeof(int16_t) * (kXMaxRows / 16) * 7 + 256;
+  return sizeof(double) * (size_t)kXWaves * kXMaxJobs * 256 + sizeof(int16_t) * ((kXMaxRows / 16) * 7 + kXMaxRows) +
+         256;
 }
 
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
@@ -591,7 +620,8 @@ int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) 
   return FRSD_OK;
 }
 
-// Uploads the (row tile, column tile) -> job table (synchronous; plan init).
+// Uploads the (row tile, column tile) -> job table, the row of each pair and
+// the pair (b2, b3) of each row (synchronous; plan init).
 int triple_mfma_upload(frsd_plan *pl, void *ws) {
   XJobs jobs;
   std::vector<int16_t> tile_job;
@@ -600,6 +630,13 @@ int triple_mfma_upload(frsd_plan *pl, void *ws) {
   double *dense = ws_ptr<double>(ws, pl->L.tri_dense);
   int16_t *tj = reinterpret_cast<int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
   FRSD_HIP(hipMemcpy(tj, tile_job.data(), tile_job.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  const int nb = pl->p.bk_nbins;
+  const std::vector<int> row = pair_rows(pl);
+  std::vector<int2> pairs(row.size());
+  for (int b2 = 0; b2 < nb; ++b2)
+    for (int b3 = 0; b3 <= b2; ++b3) pairs[row[b2 * (b2 + 1) / 2 + b3]] = make_int2(b2, b3);
+  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, pl->L.pair_tab), pairs.data(), pairs.size() * sizeof(int2),
+                     hipMemcpyHostToDevice));
   return FRSD_OK;
 }
 
