@@ -558,7 +558,8 @@ int run_nt(frsd_plan *pl, void *ws, hipStream_t s) {
   int rc = shell_pipeline<double, double, true>(pl, ws, pl->p.bk_nbins, ws_ptr<void>(ws, L.tw_inv64), shells, s);
   if (rc) return rc;
   const int4 *otab = ws_ptr<const int4>(ws, L.tri_tab) + pl->n_out;
-  rc = contract<double>(pl, ws, shells, pl->p.bk_nbins, otab, (int)pl->ntri, s);
+  if (triple_mfma_supported(pl, 1)) rc = triple_mfma64_nt(pl, ws, shells, s);
+  else rc = contract<double>(pl, ws, shells, pl->p.bk_nbins, otab, (int)pl->ntri, s);
   if (rc) return rc;
   const double inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
   FRSD_TIMED("nt_final", s, hipLaunchKernelGGL(k_nt_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s,

@@ -72,6 +72,7 @@ struct Layout {
   size_t shells = 0;                             // shell fields on M^3
   size_t tri_tab = 0, tri_part = 0, tri_sum = 0; // contraction tables and partials
   size_t pair_tab = 0, tri_dense = 0;             // (b2, b3) of each row; dense sums of the MFMA path
+  size_t pair_tab_nt = 0, tri_dense_nt = 0;       // the same for the N^T indicator sums
   size_t nt = 0;                                 // N^T per triangle
   size_t pk_lut = 0, bk_lut = 0;                 // |n|^2 -> bin index (int16, -1 outside)
   size_t bk_m2 = 0;                              // |n|^2 range of every bispectrum bin (int2)
@@ -186,10 +187,12 @@ int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mes
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);
+bool triple_mfma_supported(const frsd_plan *pl, int ne);
 size_t triple_mfma_part_bytes(int nwg);
 size_t triple_mfma_dense_bytes();
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
 int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);
+int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStream_t s);
 int triple_mfma_upload(frsd_plan *pl, void *ws);
 
 // Shell-filtered inverse FFTs on the M^3 grid (bk.hip).

@@ -248,6 +248,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
                                triple_mfma_part_bytes(kTriMfmaBlocks)));
     L.pair_tab = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
     L.tri_dense = take(triple_mfma_dense_bytes());
+    L.pair_tab_nt = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
+    L.tri_dense_nt = take(triple_mfma_dense_bytes());
     L.tri_sum = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri));
     L.nt = take(8 * (size_t)pl->ntri);
   }

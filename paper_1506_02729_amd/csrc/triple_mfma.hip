@@ -434,8 +434,8 @@ __global__ void k_triple_mfma_gather(const double *__restrict__ dense, const int
 // the last 16-column tile they need, then by their first needed column, so
 // that the 16 pairs of a row tile need similar column ranges (103 instead
 // of 114 output tiles for 37 bins).  Pairs in no listed triangle go last.
-static std::vector<int> pair_rows(const frsd_plan *pl) {
-  const int nb = pl->p.bk_nbins, ne = pl->n_ell, np = nb * (nb + 1) / 2;
+static std::vector<int> pair_rows(const frsd_plan *pl, int ne) {
+  const int nb = pl->p.bk_nbins, np = nb * (nb + 1) / 2;
   std::vector<int> lo(np, 1 << 30), hi(np, 1 << 30);
   for (int64_t t = 0; t < pl->ntri; ++t) {
     const int b1 = pl->tri[3 * t], b2 = pl->tri[3 * t + 1], b3 = pl->tri[3 * t + 2];
@@ -454,11 +454,13 @@ static std::vector<int> pair_rows(const frsd_plan *pl) {
   return row;
 }
 
-// Host-side job list: every (row tile, column tile) holding a listed output.
-static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *tile_job, int *njobs) {
-  const int nb = pl->p.bk_nbins, ne = pl->n_ell;
+// Host-side job list: every (row tile, column tile) holding a listed output,
+// for ne column groups (the multipoles of T_ell, or 1 for the N^T indicator
+// sums).
+static bool make_jobs(const frsd_plan *pl, int ne, XJobs *jobs, std::vector<int16_t> *tile_job, int *njobs) {
+  const int nb = pl->p.bk_nbins;
   const int nrt = (nb * (nb + 1) / 2 + 15) / 16;
-  const std::vector<int> row = pair_rows(pl);
+  const std::vector<int> row = pair_rows(pl, ne);
   std::vector<char> need((size_t)nrt * 7, 0);
   for (int64_t t = 0; t < pl->ntri; ++t) {
     const int b1 = pl->tri[3 * t], b2 = pl->tri[3 * t + 1], b3 = pl->tri[3 * t + 2];
@@ -538,14 +540,15 @@ static bool make_jobs(const frsd_plan *pl, XJobs *jobs, std::vector<int16_t> *ti
   return true;
 }
 
-bool triple_mfma_supported(const frsd_plan *pl) {
+bool triple_mfma_supported(const frsd_plan *pl, int ne) {
   const int nb = pl->p.bk_nbins;
-  if (nb > kXMaxB || nb * (nb + 1) / 2 > kXMaxRows || pl->n_ell * nb > kXCols) return false;
+  if (nb > kXMaxB || nb * (nb + 1) / 2 > kXMaxRows || ne * nb > kXCols) return false;
   XJobs j;
   std::vector<int16_t> tj;
   int n;
-  return make_jobs(pl, &j, &tj, &n);
+  return make_jobs(pl, ne, &j, &tj, &n);
 }
+bool triple_mfma_supported(const frsd_plan *pl) { return triple_mfma_supported(pl, pl->n_ell); }
 
 size_t triple_mfma_part_bytes(int nwg) { return sizeof(double) * (size_t)nwg * kXWaves * kXMaxJobs * 256; }
 size_t triple_mfma_dense_bytes() {
@@ -564,7 +567,7 @@ int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
   XJobs jobs;
   std::vector<int16_t> tile_job;
   int njobs = 0;
-  if (!make_jobs(pl, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
+  if (!make_jobs(pl, pl->n_ell, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
   a.njobs = njobs;
   const int nwg = kTriMfmaBlocks;
   long long per = (a.ncell + nwg - 1) / nwg;
@@ -586,58 +589,80 @@ int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
   return FRSD_OK;
 }
 
-// FP64 plans: the same job tiles on the FP64 matrix cores.
-int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) {
+// FP64 on the matrix cores: ne column groups of fields (n_ell for T_ell,
+// 1 for the N^T indicator sums), with the job tables at `dense_off` and the
+// pair table at `pair_off`; writes tsum[o] for the nout outputs of otab.
+static int triple_mfma64_run(frsd_plan *pl, void *ws, const double *fields, int ne, size_t dense_off,
+                             size_t pair_off, const int4 *otab, int nout, hipStream_t s) {
   const Layout &L = pl->L;
   XArgs a{};
   a.ncell = (long long)pl->M * pl->M * pl->M;
   a.nb = pl->p.bk_nbins;
-  a.n_ell = pl->n_ell;
-  a.ncol = pl->n_ell * a.nb;
+  a.n_ell = ne;
+  a.ncol = ne * a.nb;
   a.npair = a.nb * (a.nb + 1) / 2;
   XJobs jobs;
   std::vector<int16_t> tile_job;
   int njobs = 0;
-  if (!make_jobs(pl, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
+  if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
   a.njobs = njobs;
   const int nwg = kTriMfmaBlocks;
   long long per = (a.ncell + nwg - 1) / nwg;
   per = (per + kZKC - 1) / kZKC * kZKC;
   a.cells_per_wg = per;
-  double *dense = ws_ptr<double>(ws, L.tri_dense);
+  double *dense = ws_ptr<double>(ws, dense_off);
   const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
   FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple_mfma64, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
-                                             ws_ptr<const int2>(ws, L.pair_tab), ws_ptr<double>(ws, L.tri_part)));
+                                             ws_ptr<const int2>(ws, pair_off), ws_ptr<double>(ws, L.tri_part)));
   const int nvals = njobs * 256;
   FRSD_TIMED("tri_reduce", s,
              hipLaunchKernelGGL(k_triple_mfma_reduce<double>, dim3((nvals + 255) / 256), dim3(256), 0, s,
                                 ws_ptr<const double>(ws, L.tri_part), nwg, nvals, dense));
   FRSD_TIMED("tri_gather", s,
-             hipLaunchKernelGGL(k_triple_mfma_gather, dim3((pl->n_out + 255) / 256), dim3(256), 0, s, dense,
-                                ws_ptr<const int4>(ws, L.tri_tab), tj, a.nb, a.n_ell, pl->n_out,
-                                ws_ptr<double>(ws, L.tri_sum)));
+             hipLaunchKernelGGL(k_triple_mfma_gather, dim3((nout + 255) / 256), dim3(256), 0, s, dense, otab, tj,
+                                a.nb, ne, nout, ws_ptr<double>(ws, L.tri_sum)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
+// FP64 plans: T_ell on the same job tiles as the FP32 path.
+int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) {
+  return triple_mfma64_run(pl, ws, fields, pl->n_ell, pl->L.tri_dense, pl->L.pair_tab,
+                           ws_ptr<const int4>(ws, pl->L.tri_tab), pl->n_out, s);
+}
+
+// N^T indicator sums (plan init): one column group, the triangle list as outputs.
+int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStream_t s) {
+  return triple_mfma64_run(pl, ws, indicators, 1, pl->L.tri_dense_nt, pl->L.pair_tab_nt,
+                           ws_ptr<const int4>(ws, pl->L.tri_tab) + pl->n_out, (int)pl->ntri, s);
+}
+
 // Uploads the (row tile, column tile) -> job table, the row of each pair and
-// the pair (b2, b3) of each row (synchronous; plan init).
-int triple_mfma_upload(frsd_plan *pl, void *ws) {
+// the pair (b2, b3) of each row for ne column groups (synchronous; plan init).
+static int upload_tables_for(frsd_plan *pl, void *ws, int ne, size_t dense_off, size_t pair_off) {
   XJobs jobs;
   std::vector<int16_t> tile_job;
   int njobs = 0;
-  if (!make_jobs(pl, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
-  double *dense = ws_ptr<double>(ws, pl->L.tri_dense);
+  if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
+  double *dense = ws_ptr<double>(ws, dense_off);
   int16_t *tj = reinterpret_cast<int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
   FRSD_HIP(hipMemcpy(tj, tile_job.data(), tile_job.size() * sizeof(int16_t), hipMemcpyHostToDevice));
   const int nb = pl->p.bk_nbins;
-  const std::vector<int> row = pair_rows(pl);
+  const std::vector<int> row = pair_rows(pl, ne);
   std::vector<int2> pairs(row.size());
   for (int b2 = 0; b2 < nb; ++b2)
     for (int b3 = 0; b3 <= b2; ++b3) pairs[row[b2 * (b2 + 1) / 2 + b3]] = make_int2(b2, b3);
-  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, pl->L.pair_tab), pairs.data(), pairs.size() * sizeof(int2),
-                     hipMemcpyHostToDevice));
+  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, pair_off), pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
   return FRSD_OK;
+}
+
+// Tables of the T_ell contraction and, when it fits the tiles, of the N^T
+// indicator sums.
+int triple_mfma_upload(frsd_plan *pl, void *ws) {
+  int rc = upload_tables_for(pl, ws, pl->n_ell, pl->L.tri_dense, pl->L.pair_tab);
+  if (rc) return rc;
+  if (triple_mfma_supported(pl, 1)) rc = upload_tables_for(pl, ws, 1, pl->L.tri_dense_nt, pl->L.pair_tab_nt);
+  return rc;
 }
 
 }  // namespace frsd
