@@ -1,4 +1,5 @@
-// Triple-product contraction on the matrix cores (FP32 plans).
+// Triple-product contraction on the matrix cores: BF16 hi/lo for FP32 plans,
+// FP64 MFMA for FP64 plans and for the N^T indicator sums of plan init.
 //
 // The bispectrum triangle sums T_ell(b1,b2,b3) = sum_x F_{ell,b1}(x)
 // F_{0,b2}(x) F_{0,b3}(x) (Sec. III.B eq. Factorize) are entries of one
