@@ -98,3 +98,27 @@ def test_triangle_grid_choice():
     h = F.frsd_plan_create(F.Config(**{**base, "bk_nbins": 0}).to_c())
     assert F.frsd_bk_grid(h) == 0
     F.frsd_plan_destroy(h)
+
+
+def test_workspace_shares_the_planar_region():
+    """The shell intermediates and fields (live only inside one bispectrum
+    call) share the planar assignment arrays (live only during the
+    assignment and the first FFT pass): at H512 the FP32 workspace is the
+    rest plus the larger of the two, and order 4 (PCS) plans build too."""
+    from paper_1506_02729_amd import fastrsd as F
+    kf = 2 * math.pi / 3500.0
+    base = dict(n_grid=512, box=3500.0, observer=(-400.0, 1750.0, 1750.0), precision=32, pk_dk=0.005,
+                pk_nbins=60, bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, max_objects=41_000_000)
+    h = F.frsd_plan_create(F.Config(**base).to_c())
+    with_bk = F.frsd_plan_workspace_bytes(h)
+    F.frsd_plan_destroy(h)
+    h = F.frsd_plan_create(F.Config(**{**base, "bk_nbins": 0}).to_c())
+    without_bk = F.frsd_plan_workspace_bytes(h)
+    F.frsd_plan_destroy(h)
+    planar = 2 * 4 * 512**3 * 23            # 23 complex slots of real/imaginary planes
+    shells = 4 * 111 * 343**3                # 111 FP32 shell fields on M = 343
+    assert shells < planar
+    assert with_bk - without_bk < 3e9        # tables, low-k cube and contraction partials only
+    assert with_bk < 52e9
+    h = F.frsd_plan_create(F.Config(**{**base, "order": 4}).to_c())
+    F.frsd_plan_destroy(h)
