@@ -222,10 +222,12 @@ def open_loop(args, F, torch, synth, dev, log):
     (exponential gaps of mean --mean-gap s), N uniform in {256, 384, 512},
     N_g uniform in [3e5, the pool size] and N_r = 50 N_g taken as prefixes of
     shuffled pool catalogues resident in HBM, P_ell to min(0.3, k_Ny) in bins
-    of 0.005 and B_ell on 18 bins of 3 k_f (k <= 0.1).  Each mesh size has
-    --open-loop-slots plans (workspace + stream), allocated up front; a queued
-    request is admitted as soon as a plan of its size is free.  Latency runs
-    from arrival to the P_ell and B_ell arrays on the host."""
+    of 0.005 and B_ell on 18 bins of 3 k_f (k <= 0.1).  Admission by HBM
+    footprint: every mesh size starts with one plan (workspace + stream); a
+    queued request takes a free plan of its size, or a new one when the
+    workspaces (exact sizes from the plan) stay within --hbm-budget-gb, or
+    waits.  Latency runs from arrival to the P_ell and B_ell arrays on the
+    host."""
     from collections import deque
     box = 3500.0
     kf = 2 * math.pi / box
@@ -243,14 +245,22 @@ def open_loop(args, F, torch, synth, dev, log):
     nr_all = len(ran["w"])
     log(f"open loop: pool of {len(gals)} mocks, {ng_max}+ galaxies, {nr_all} randoms in {time.perf_counter() - t0:.1f} s")
     sizes = (256, 384, 512)
-    plans, nbins = {}, {}
+    plans, nbins, cfgs, ws_bytes = {}, {}, {}, {}
+    budget = args.hbm_budget_gb * 1e9
     for N in sizes:
         kny = math.pi * N / box
         nbins[N] = min(60, int(math.floor(kny / 0.005 - 1e-9)))  # bins of 0.005 to min(0.3, k_Ny)
         cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
                        precision=32, pk_kmin=0.0, pk_dk=0.005, pk_nbins=nbins[N], bk_kmin=1.5 * kf, bk_dk=3 * kf,
                        bk_nbins=18, max_objects=ng_max + nr_all)
-        plans[N] = [F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev)) for _ in range(args.open_loop_slots)]
+        cfgs[N] = cfg
+        h = F.frsd_plan_create(cfg.to_c())
+        ws_bytes[N] = F.frsd_plan_workspace_bytes(h)
+        F.frsd_plan_destroy(h)
+        plans[N] = [F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev))]
+    used = sum(ws_bytes[N] for N in sizes)
+    if used > budget:
+        raise SystemExit(f"--hbm-budget-gb {args.hbm_budget_gb} is below one workspace per size ({used / 1e9:.1f} GB)")
     n = args.open_loop
     arrive = np.cumsum(rng.exponential(args.mean_gap, n))
     n_of = rng.choice(np.array(sizes), n)
@@ -288,8 +298,14 @@ def open_loop(args, F, torch, synth, dev, log):
                 sizes_done.append(int(n_of[k]))
                 inflight.remove(rec)
                 free[id(pl)] = True
-        for k in list(queue):  # admit every queued request that has a free plan of its size
-            pl = next((p for p in plans[int(n_of[k])] if free[id(p)]), None)
+        for k in list(queue):  # admit every queued request that has (or may allocate) a plan of its size
+            N = int(n_of[k])
+            pl = next((p for p in plans[N] if free[id(p)]), None)
+            if pl is None and used + ws_bytes[N] <= budget:
+                pl = F.Plan(cfgs[N], device=dev, stream=torch.cuda.Stream(dev))
+                plans[N].append(pl)
+                used += ws_bytes[N]
+                free[id(pl)] = True
             if pl is None:
                 continue
             queue.remove(k)
@@ -310,7 +326,8 @@ def open_loop(args, F, torch, synth, dev, log):
     out = {"metric": "open-loop request latency p99 (arrival to host result), mixed N in {256, 384, 512}",
            "value": float(np.percentile(lat_ms, 99)), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
            "requests": n, "p50_ms": float(np.percentile(lat_ms, 50)), "mocks_per_s": n / elapsed,
-           "mean_gap_s": args.mean_gap, "slots_per_size": args.open_loop_slots, "per_size": per_size,
+           "mean_gap_s": args.mean_gap, "hbm_budget_gb": args.hbm_budget_gb,
+           "plans_per_size": {str(N): len(plans[N]) for N in sizes}, "workspace_gb": used / 1e9, "per_size": per_size,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "open loop: lognormal pool (4 mocks, 8e5 galaxies, 4e7 randoms, 3500 Mpc/h box), "
                                   "prefixes N_g in [3e5, pool], N_r = 50 N_g, P_ell l=0,2,4 to min(0.3, k_Ny), "
@@ -337,7 +354,8 @@ def main():
     ap.add_argument("--open-loop", type=int, default=0,
                     help="instead of the closed loop: this many open-loop requests of mixed mesh sizes")
     ap.add_argument("--mean-gap", type=float, default=0.5, help="open loop: mean inter-arrival time (s)")
-    ap.add_argument("--open-loop-slots", type=int, default=2, help="open loop: plans per mesh size")
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0,
+                    help="open loop: device memory for plan workspaces (admission by footprint)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
