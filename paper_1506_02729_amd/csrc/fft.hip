@@ -142,7 +142,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
 // of P_COL complex values.
 template <typename T> struct FwdTune {
   static constexpr int nt_row = 256, nt_col = sizeof(T) == 4 ? 512 : 256;
-  static constexpr int row_elems = sizeof(T) == 4 ? 4096 : 2048;  // rows per workgroup x length
+  static constexpr int row_elems = sizeof(T) == 4 ? 8192 : 2048;  // rows per workgroup x length (16 rows of 512 measured 6% faster than 8)
   static constexpr int p_col = sizeof(T) == 4 ? 16 : 8;
 };
 template <typename T, int LEN> constexpr int p_row() {
