@@ -13,12 +13,16 @@ float64, of what the estimator computes:
   shell binning, P_ell, the FFT triangle search, N^T and B_ell
   (Sec. III.A eqs. F0-Nelltrue and mapFFT, Sec. III.B eqs. BispMono-F_k).
 * ``brute``      -- brute-force twins used to pin the estimator: per-mode
-  direct sums over objects, direct triangle enumeration, lattice-point
-  counts.
+  direct sums over objects, direct triangle enumeration (with any function
+  per side), lattice-point counts.
 
-Parity unpinned: the l > 0 thin-shell shot-noise q1 term (SN2, SN4) has no
-pin beyond its formula, and I33 (not defined in the paper; read as
-alpha sum_r nbar^2 w^3) is pinned only through its definition.
+Every function is pinned by a test in ``tests/test_oracle_pins.py`` or
+``tests/test_oracle_pins_bk.py`` against something other than itself: brute
+force over objects or lattice triangles, closed forms (I22, I33, N_0, W3 for
+constant nbar and w), exact expectations (P_ell of a Poisson-sampled fixed
+field), the plane-parallel limit (B_ell prefactors, the w^2-weighted shell
+sums), and lattice configurations in which the thin-shell shot noise equals
+its exact triangle sum.
 
 It shares no code with the GPU path.  Every function cites the passage of
 the paper it follows.

@@ -188,3 +188,44 @@ def triangle_enumeration(value_fn, e2_edges, triangles, ells=(0, 2, 4)):
         for ell in ells:
             sums[ell][t] = np.sum(value_fn(ell, n1[i1]) * v2 * v3)
     return cnt, sums
+
+
+def triangle_enumeration_slots(f1, f2, f3, e2_edges, triangles):
+    """Direct sums over closed lattice triangles with a function per side.
+
+    For each (b1, b2, b3): sum of f1(n1) f2(n2) f3(n3) over n1 in b1, n2 in
+    b2 and n3 = -(n1 + n2) in b3 (the delta function of eq. NT), and the
+    count of such triangles.  f_i(nvec[k, 3]) -> complex values.
+    """
+    cnt, sums = triangle_enumeration_many([(f1, f2, f3)], e2_edges, triangles)
+    return cnt, sums[0]
+
+
+def triangle_enumeration_many(products, e2_edges, triangles):
+    """``triangle_enumeration_slots`` for several products (f1, f2, f3) over
+    one enumeration of the closed triangles; returns the count and a list of
+    sums, one per product."""
+    e2 = np.asarray(e2_edges, dtype=np.float64)
+    nc = int(math.ceil(math.sqrt(e2[-1])) - 1)
+    r = np.arange(-nc, nc + 1)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    m2 = np.sum(g * g, axis=1)
+    b = np.searchsorted(e2, m2, side="right") - 1
+    b = np.where((m2 > 0) & (b >= 0) & (b < len(e2) - 1), b, -1)
+    shells = {i: g[b == i] for i in range(len(e2) - 1)}
+    cnt = np.zeros(len(triangles))
+    sums = [np.zeros(len(triangles), dtype=np.complex128) for _ in products]
+    for t, (b1, b2, b3) in enumerate(triangles):
+        n1 = shells[b1]
+        n2 = shells[b2]
+        n3 = -(n1[:, None, :] + n2[None, :, :])
+        m3 = np.sum(n3 * n3, axis=-1)
+        ok = (m3 >= e2[b3]) & (m3 < e2[b3 + 1]) & (m3 > 0)
+        cnt[t] = ok.sum()
+        if cnt[t] == 0:
+            continue
+        i1, i2 = np.nonzero(ok)
+        q1, q2, q3 = n1[i1], n2[i2], n3[i1, i2]
+        for k, (f1, f2, f3) in enumerate(products):
+            sums[k][t] = np.sum(f1(q1) * f2(q2) * f3(q3))
+    return cnt, sums

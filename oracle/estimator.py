@@ -283,15 +283,18 @@ def fourier_of_weights(u, weight, prm: Params, nx, ny, nz, u_twin=None):
 
 
 def multipole_fields(gal, ran, alpha, prm: Params, with_w: bool = False,
-                     sign: int = -1):
-    """A_0, A_2, A_4 (and A_0^w) on the rfftn half grid.
+                     sign: int = -1, with_w_ell: bool = False):
+    """A_0, A_2, A_4 (and A_0^w, A_2^w, A_4^w) on the rfftn half grid.
 
     A_0 = F_0 (eq. F0); A_2 = 3/2 khat_a khat_b Q^{ab} - 1/2 A_0 (eq. F2 with
     Q^{ab} of eq. Qab); A_4 = 35/8 khat^4 Q^{abcd} - 5/2 A_2 - 7/8 A_0
     (eq. delta4 in the survey form).  A_0^w is the w^2-weighted monopole
     F_0^w with weights w^2 for galaxies and alpha^2 w^2 for randoms
-    (the definition after eq. SNbisp2).  ``sign=+1`` conjugates every field,
-    i.e. uses exp(+ik.x) as written in eq. F0.
+    (the definition after eq. SNbisp2).  With ``with_w_ell`` also
+    F^w_2(q) = F^w_2(qhat, q) and F^w_4 (the same definition with
+    L_ell(qhat . xhat_j), i.e. the same combination as A_2 and A_4 of the
+    w^2-weighted moment meshes), keys "w2" and "w4".  ``sign=+1`` conjugates
+    every field, i.e. uses exp(+ik.x) as written in eq. F0.
     """
     N = prm.n_grid
     pos, w, w2 = combined_catalog(gal, ran, alpha)
@@ -325,8 +328,20 @@ def multipole_fields(gal, ran, alpha, prm: Params, with_w: bool = False,
             s += multiplicity(idx) * khat_mono(idx) * fourier_of_weights(
                 u, w * monomial(xhat, idx), prm, nx, ny, nz, ut)
         fields[4] = 35.0 / 8.0 * s - 2.5 * fields[2] - 7.0 / 8.0 * A0
-    if with_w:
+    if with_w or with_w_ell:
         fields["w"] = fourier_of_weights(u, w2, prm, nx, ny, nz, ut)
+    if with_w_ell and prm.ell_max >= 2:
+        s = np.zeros_like(A0)
+        for idx in MOMENTS_2:
+            s += multiplicity(idx) * khat_mono(idx) * fourier_of_weights(
+                u, w2 * monomial(xhat, idx), prm, nx, ny, nz, ut)
+        fields["w2"] = 1.5 * s - 0.5 * fields["w"]
+        if prm.ell_max >= 4:
+            s = np.zeros_like(A0)
+            for idx in MOMENTS_4:
+                s += multiplicity(idx) * khat_mono(idx) * fourier_of_weights(
+                    u, w2 * monomial(xhat, idx), prm, nx, ny, nz, ut)
+            fields["w4"] = 35.0 / 8.0 * s - 2.5 * fields["w2"] - 7.0 / 8.0 * fields["w"]
     if sign > 0:
         fields = {k: np.conj(v) for k, v in fields.items()}
     return fields
@@ -374,7 +389,8 @@ def shell_sums(fields, prm: Params, kmin, dk, nbins):
     N_b = number of modes, k_eff = mean |k|, S_l0 = sum Re[A_l A_0^*],
     S_22 = sum |A_2|^2 (the autocorrelation of the quadrupole field, used by
     the split hexadecapole of Sec. II.B eq. P4fast), S_0w = sum Re[A_0 A_0w^*],
-    S_lw = sum Re[A_l A_0w^*].
+    S_lw = sum Re[A_l A_0w^*], and with the w^2-weighted multipoles
+    Q_lw = sum Re[A_0 (A_l^w)^*] (the q_2, q_3 terms of eq. SNbisp2thin).
     """
     N = prm.n_grid
     nx, ny, nz = half_grid(N)
@@ -404,6 +420,10 @@ def shell_sums(fields, prm: Params, kmin, dk, nbins):
             if ell in fields:
                 out[f"S{ell}w"] = np.bincount(bb, weights=wsel * (fields[ell].ravel()[sel] * Aw).real,
                                               minlength=nbins)
+    for ell in (2, 4):
+        if f"w{ell}" in fields:
+            out[f"Q{ell}w"] = np.bincount(bb, weights=wsel * (A0 * np.conj(fields[f"w{ell}"].ravel()[sel])).real,
+                                          minlength=nbins)
     return out
 
 
@@ -493,13 +513,15 @@ def shell_field(values, nx, ny, nz, M: int) -> np.ndarray:
     return f.real
 
 
-def bk_triangle_sums(fields, prm: Params, triangles=None, indicators_only=False):
+def bk_triangle_sums(fields, prm: Params, triangles=None, indicators_only=False, t220=False):
     """T_ell(b1,b2,b3) = M^-3 sum_x F_{ell,b1}(x) F_{0,b2}(x) F_{0,b3}(x) and N^T.
 
     The grid sum over real space equals the sum over closed triangles
     q1 + q2 + q3 = 0 with q_i in shell b_i (eq. Factorize), exact when
     M > 3 n_c.  N^T is the same sum with unit fields (eq. NT, exact
-    discrete count), rounded to the nearest integer.
+    discrete count), rounded to the nearest integer.  With ``t220`` also
+    T_220 = M^-3 sum_x F_{2,b1} F_{2,b2} F_{0,b3}, the triangle sum of the
+    zero-area hexadecapole (Sec. II.C eq. Bhexa2: delta_2 on q1 and q2).
     """
     M = bk_grid(prm)
     N = prm.n_grid
@@ -522,9 +544,13 @@ def bk_triangle_sums(fields, prm: Params, triangles=None, indicators_only=False)
 
     out = {"NT": np.zeros(len(triangles))}
     ells = [] if indicators_only else [e for e in (0, 2, 4) if e in fields]
+    t220 = t220 and 2 in ells
     for ell in ells:
         out[f"T{ell}"] = np.zeros(len(triangles))
         out[f"C{ell}"] = np.zeros(len(triangles))
+    if t220:
+        out["T220"] = np.zeros(len(triangles))
+        out["C220"] = np.zeros(len(triangles))
     for t, (b1, b2, b3) in enumerate(np.asarray(triangles)):
         out["NT"][t] = np.rint(np.sum(get("I", b1) * get("I", b2) * get("I", b3)) / M**3)
         if ells:
@@ -533,6 +559,10 @@ def bk_triangle_sums(fields, prm: Params, triangles=None, indicators_only=False)
                 f1 = get(ell, b1)
                 out[f"T{ell}"][t] = np.sum(f1 * pair) / M**3
                 out[f"C{ell}"][t] = np.sum(np.abs(f1 * pair)) / M**3
+        if t220:
+            prod = get(2, b1) * get(2, b2) * get(0, b3)
+            out["T220"][t] = np.sum(prod) / M**3
+            out["C220"][t] = np.sum(np.abs(prod)) / M**3
         # drop fields no longer needed by later triangles in lexicographic order
         if len(cache) > 64:
             cache.clear()
@@ -540,14 +570,41 @@ def bk_triangle_sums(fields, prm: Params, triangles=None, indicators_only=False)
     return out
 
 
-def bk_multipoles(gal, ran, alpha, prm: Params, triangles=None, fields=None):
+def bin_centres(prm: Params) -> np.ndarray:
+    """Centres of the bispectrum bins in k_f units (mid-points of the edges)."""
+    e = np.sqrt(squared_edges(prm.bk_kmin, prm.bk_dk, prm.bk_nbins, prm.kf))
+    return 0.5 * (e[:-1] + e[1:])
+
+
+def triangle_cosines(prm: Params, triangles) -> tuple:
+    """cos(q1, q2) and cos(q1, q3) of a closed triangle with sides at the bin
+    centres (law of cosines: q3^2 = q1^2 + q2^2 + 2 q1.q2), clamped to
+    [-1, 1] for bin triples that do not close at their centres."""
+    c = bin_centres(prm)
+    t = np.asarray(triangles, dtype=np.int64).reshape(-1, 3)
+    k1, k2, k3 = c[t[:, 0]], c[t[:, 1]], c[t[:, 2]]
+    c12 = np.clip((k3 * k3 - k1 * k1 - k2 * k2) / (2.0 * k1 * k2), -1.0, 1.0)
+    c13 = np.clip((k2 * k2 - k1 * k1 - k3 * k3) / (2.0 * k1 * k3), -1.0, 1.0)
+    return c12, c13
+
+
+def bk_multipoles(gal, ran, alpha, prm: Params, triangles=None, fields=None, zero_area=False, tsums=None):
     """B_0, B_2, B_4 of the survey estimator with thin-shell shot noise.
 
     B_ell^raw = (2 ell + 1) T_ell / (N^T I33) (eqs. BispMono, BispQuad).
-    Shot noise (eq. SNbisp2thin): for ell = 0 the full thin-shell form
-    N^(0) = sum_i S_0w(b_i)/(N_{b_i} I33) - 2 W3 / I33; for ell > 0 only its
-    first term (2 ell + 1) S_lw(b1)/(N_{b1} I33) (the F_ell^w terms are not
-    computed).  Triangles with N^T = 0 give NaN.
+    Shot noise in the thin-shell form (eq. SNbisp2thin):
+      N^(0) = sum_i S_0w(b_i)/(N_{b_i} I33) - 2 W3 / I33,
+      N^(l) = (2l+1)/I33 [S_lw(b1)/N_{b1} + sum_{i=2,3} L_l(qhat_1 . qhat_i) Q_lw(b_i)/N_{b_i}]
+    with S_lw = sum Re F_l F_0w^*, Q_lw = sum Re F_0 (F^w_l)^* and the cosines
+    at the bin centres (``triangle_cosines``).  "SN{l}_q1" is the first term
+    alone; "SN{l}" needs the w^2-weighted multipoles (fields "w2", "w4",
+    ``multipole_fields(with_w_ell=True)``) and is the q1 term otherwise.
+    With ``zero_area`` also the zero-area hexadecapole of Sec. II.C
+    eq. Bhexa2 in the survey normalisation,
+      B4za = [35/2 T_220 - 5 T_2 - 7/2 T_0] / (N^T I33)
+    (no shot noise subtracted).  Triangles with N^T = 0 give NaN.  ``tsums``
+    takes triangle sums already computed for these triangles (e.g. by
+    ``bk_triangle_sums_streamed``).
     """
     if triangles is None:
         triangles = triangle_list(prm)
@@ -555,7 +612,7 @@ def bk_multipoles(gal, ran, alpha, prm: Params, triangles=None, fields=None):
     if fields is None:
         fields = multipole_fields(gal, ran, alpha, prm, with_w=True)
     sc = scalars(gal, ran, alpha)
-    ts = bk_triangle_sums(fields, prm, triangles)
+    ts = tsums if tsums is not None else bk_triangle_sums(fields, prm, triangles, t220=zero_area)
     sh = shell_sums(fields, prm, prm.bk_kmin, prm.bk_dk, prm.bk_nbins)
     nt = ts["NT"]
     res = {"triangles": triangles, "NT": nt, "M": ts["M"], "bins": sh}
@@ -566,13 +623,98 @@ def bk_multipoles(gal, ran, alpha, prm: Params, triangles=None, fields=None):
             res[f"T{ell}"] = ts[f"T{ell}"]
             res[f"C{ell}"] = ts[f"C{ell}"]
             res[f"B{ell}"] = np.where(nt > 0, (2 * ell + 1) * ts[f"T{ell}"] / (nt * sc["I33"]), np.nan)
+        if "T220" in ts:
+            res["T220"] = ts["T220"]
+            res["C220"] = ts["C220"]
+            res["B4za"] = np.where(nt > 0, (17.5 * ts["T220"] - 5.0 * ts["T2"] - 3.5 * ts["T0"]) / (nt * sc["I33"]),
+                                   np.nan)
         nb = sh["n_modes"].astype(np.float64)
         if "S0w" in sh:
             per_bin = sh["S0w"] / nb
             b1, b2, b3 = triangles.T
             res["SN0"] = (per_bin[b1] + per_bin[b2] + per_bin[b3]) / sc["I33"] - 2.0 * sc["W3"] / sc["I33"]
+            c12, c13 = triangle_cosines(prm, triangles)
             for ell in (2, 4):
                 if f"S{ell}w" in sh:
-                    res[f"SN{ell}"] = (2 * ell + 1) * (sh[f"S{ell}w"] / nb)[b1] / sc["I33"]
+                    q1 = (2 * ell + 1) * (sh[f"S{ell}w"] / nb)[b1] / sc["I33"]
+                    res[f"SN{ell}_q1"] = q1
+                    res[f"SN{ell}"] = q1
+                    if f"Q{ell}w" in sh:
+                        per = sh[f"Q{ell}w"] / nb
+                        res[f"SN{ell}"] = q1 + (2 * ell + 1) * (legendre(ell, c12) * per[b2]
+                                                                + legendre(ell, c13) * per[b3]) / sc["I33"]
     res.update(sc)
     return res
+
+
+def bk_triangle_sums_streamed(fields, prm: Params, triangles, scratch_path: str, chunk: int = 1 << 17,
+                              t220: bool = False):
+    """The sums of ``bk_triangle_sums`` for grids whose shell fields do not all
+    fit in memory (the same definition, Sec. III.B eqs. Factorize, F_k, NT).
+
+    Every shell field needed (the unit indicator and F_0, F_2, F_4 of each
+    bin, eq. F_k) is computed once by ``shell_field`` and written to a
+    memory-mapped file at ``scratch_path``.  The grid sum over x is then taken
+    over chunks of cells: for each chunk the (pair x cell) array of products
+    F_{0,b2}(x) F_{0,b3}(x) times the (cell x field) array of F_{l,b1}(x)
+    gives the chunk's contribution to every sum_x F_{0,b2} F_{0,b3} F_{l,b1}
+    at once (a matrix product as a step), accumulated in float64; the
+    absolute values give the conditioning sums C_l, the indicators N^T, and
+    with ``t220`` the pair F_{2,b2} F_{0,b3} against F_{2,b1} gives T_220.
+    """
+    M = bk_grid(prm)
+    N = prm.n_grid
+    triangles = np.asarray(triangles, dtype=np.int64).reshape(-1, 3)
+    nb = prm.bk_nbins
+    nx, ny, nz, b = lowk_modes(prm)
+    ells = [e for e in (0, 2, 4) if e in fields]
+    kinds = ["I"] + ells
+    t220 = t220 and 2 in ells
+    ncell = M**3
+    store = np.lib.format.open_memmap(scratch_path, mode="w+", dtype=np.float64, shape=(len(kinds) * nb, ncell))
+    for ki, kind in enumerate(kinds):
+        for bin_ in range(nb):
+            sel = b == bin_
+            if kind == "I":
+                vals = np.ones(int(sel.sum()), dtype=np.complex128)
+            else:
+                vals = gather_full(fields[kind], N, nx[sel], ny[sel], nz[sel])
+            store[ki * nb + bin_] = shell_field(vals, nx[sel], ny[sel], nz[sel], M).ravel()
+    store.flush()
+    pairs = sorted({(int(t[1]), int(t[2])) for t in triangles})
+    pidx = {p: i for i, p in enumerate(pairs)}
+    p2 = np.array([p[0] for p in pairs])
+    p3 = np.array([p[1] for p in pairs])
+    row = {k: ki * nb for ki, k in enumerate(kinds)}
+    nd = len(ells) * nb
+    acc_nt = np.zeros((len(pairs), nb))
+    acc_t = np.zeros((len(pairs), nd))
+    acc_c = np.zeros((len(pairs), nd))
+    acc_220 = np.zeros((len(pairs), nb))
+    acc_c220 = np.zeros((len(pairs), nb))
+    for c0 in range(0, ncell, chunk):
+        blk = np.array(store[:, c0:c0 + chunk])
+        ind = blk[row["I"]:row["I"] + nb]
+        acc_nt += (ind[p2] * ind[p3]) @ ind.T
+        f0 = blk[row[0]:row[0] + nb]
+        data = np.concatenate([blk[row[e]:row[e] + nb] for e in ells])
+        pr = f0[p2] * f0[p3]
+        acc_t += pr @ data.T
+        acc_c += np.abs(pr) @ np.abs(data).T
+        if t220:
+            f2 = blk[row[2]:row[2] + nb]
+            pr2 = f2[p2] * f0[p3]
+            acc_220 += pr2 @ f2.T
+            acc_c220 += np.abs(pr2) @ np.abs(f2).T
+    del store
+    os.remove(scratch_path)
+    pi = np.array([pidx[(int(t[1]), int(t[2]))] for t in triangles])
+    b1 = triangles[:, 0]
+    out = {"NT": np.rint(acc_nt[pi, b1] / M**3), "M": M}
+    for li, ell in enumerate(ells):
+        out[f"T{ell}"] = acc_t[pi, li * nb + b1] / M**3
+        out[f"C{ell}"] = acc_c[pi, li * nb + b1] / M**3
+    if t220:
+        out["T220"] = acc_220[pi, b1] / M**3
+        out["C220"] = acc_c220[pi, b1] / M**3
+    return out
