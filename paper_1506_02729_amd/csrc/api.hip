@@ -29,7 +29,7 @@ extern "C" int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *
   if (rc) return rc;
   if (ws_bytes < plan->L.total) return fail(FRSD_ENOMEM, "workspace smaller than frsd_plan_workspace_bytes");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  rc = upload_tables(plan, ws, s);
+  rc = upload_tables(plan, ws, s, false);
   if (rc) return rc;
   rc = run_bin_geometry(plan, ws, s);
   if (rc) return rc;

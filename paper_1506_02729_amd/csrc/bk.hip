@@ -13,7 +13,9 @@
 // The triangle sums T_ell(b1,b2,b3) = M^-3 sum_x F_{ell,b1} F_{0,b2} F_{0,b3}
 // equal the sums over closed triangles when M > 3 n_c.  N^T is the same sum
 // of indicator fields, done once per plan in FP64 and rounded.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "device.h"
@@ -638,31 +640,46 @@ static std::vector<int16_t> bin_lut(const std::vector<double> &e2, int len) {
   return lut;
 }
 
-int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
+void tab_add(frsd_plan *pl, size_t ws_off, const void *src, size_t bytes) {
+  const size_t off = (pl->tab_host.size() + 255) & ~(size_t)255;
+  pl->tab_host.resize(off + bytes);
+  std::memcpy(pl->tab_host.data() + off, src, bytes);
+  pl->tab_seg.push_back(TabSeg{off, ws_off, bytes});
+}
+
+// Every constant table of the plan, in one host image: stage twiddles of
+// the forward and inverse transforms, the |n|^2 -> bin lookups, the |n|^2
+// range of each bispectrum bin, the contraction output tables and triangle
+// list, and the matrix-core job tables of the T_ell and N^T contractions
+// (each only when that contraction runs on the matrix cores: run_bk and
+// run_nt take the same predicates).
+int build_tables(frsd_plan *pl) {
+  if (pl->tab_built) return FRSD_OK;
+  pl->tab_host.clear();
+  pl->tab_seg.clear();
   const Layout &L = pl->L;
-  FRSD_HIP(hipStreamSynchronize(s));
   const bool f64 = pl->p.precision == FRSD_F64;
   if (f64) {
     auto t = twiddles<double>(pl->N);
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_fwd), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    tab_add(pl, L.tw_fwd, t.data(), t.size() * sizeof(double));
   } else {
     auto t = twiddles<float>(pl->N);
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_fwd), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    tab_add(pl, L.tw_fwd, t.data(), t.size() * sizeof(float));
   }
   auto lp = bin_lut(pl->pk_e2, pl->pk_lut_len);
-  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.pk_lut), lp.data(), lp.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  tab_add(pl, L.pk_lut, lp.data(), lp.size() * sizeof(int16_t));
   if (pl->p.bk_nbins > 0) {
     if (f64) {
       auto t = twiddles<double>(pl->M);
-      FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv), t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+      tab_add(pl, L.tw_inv, t.data(), t.size() * sizeof(double));
     } else {
       auto t = twiddles<float>(pl->M);
-      FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv), t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+      tab_add(pl, L.tw_inv, t.data(), t.size() * sizeof(float));
     }
     auto t64 = twiddles<double>(pl->M);
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tw_inv64), t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice));
+    tab_add(pl, L.tw_inv64, t64.data(), t64.size() * sizeof(double));
     auto lb = bin_lut(pl->bk_e2, pl->bk_lut_len);
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.bk_lut), lb.data(), lb.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    tab_add(pl, L.bk_lut, lb.data(), lb.size() * sizeof(int16_t));
     // |n|^2 range [lo, hi] of every bispectrum bin (bins hold consecutive
     // integers; an empty bin gets lo > hi)
     std::vector<int2> m2r(pl->p.bk_nbins, make_int2(1, 0));
@@ -674,7 +691,7 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
     }
     for (int m = 1; m < pl->bk_lut_len; ++m)
       if (lb[m] >= 0 && (m < m2r[lb[m]].x || m > m2r[lb[m]].y)) return fail(FRSD_EINVAL, "bin lookup not monotone");
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.bk_m2), m2r.data(), m2r.size() * sizeof(int2), hipMemcpyHostToDevice));
+    tab_add(pl, L.bk_m2, m2r.data(), m2r.size() * sizeof(int2));
     // contraction tables: data outputs (field of b1 for each ell, b2, b3), then
     // indicator outputs (b1, b2, b3), then the raw int32 triangle list
     const int nb = pl->p.bk_nbins;
@@ -684,15 +701,36 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s) {
       for (int li = 0; li < pl->n_ell; ++li) tab[t * pl->n_ell + li] = make_int4(li * nb + b1, b2, b3, 0);
       tab[pl->n_out + t] = make_int4(b1, b2, b3, 0);
     }
-    FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, L.tri_tab), tab.data(), tab.size() * sizeof(int4), hipMemcpyHostToDevice));
-    FRSD_HIP(hipMemcpy(ws_ptr<int4>(ws, L.tri_tab) + tab.size(), pl->tri.data(), pl->tri.size() * sizeof(int32_t),
-                       hipMemcpyHostToDevice));
-    // the matrix-core contraction's tables (job tiles, pair rows)
+    tab_add(pl, L.tri_tab, tab.data(), tab.size() * sizeof(int4));
+    tab_add(pl, L.tri_tab + tab.size() * sizeof(int4), pl->tri.data(), pl->tri.size() * sizeof(int32_t));
     if (triple_mfma_supported(pl)) {
-      const int rc = triple_mfma_upload(pl, ws);
+      const int rc = triple_mfma_tables(pl, pl->n_ell, false);
+      if (rc) return rc;
+    }
+    if (triple_mfma_supported(pl, 1)) {
+      const int rc = triple_mfma_tables(pl, 1, true);
       if (rc) return rc;
     }
   }
+  pl->tab_built = true;
+  return FRSD_OK;
+}
+
+int upload_tables(frsd_plan *pl, void *ws, hipStream_t s, bool pageable) {
+  int rc = build_tables(pl);
+  if (rc) return rc;
+  const unsigned char *src = pl->tab_host.data();
+  if (!pageable) {
+    if (!pl->tab_pinned) {
+      FRSD_HIP(hipHostMalloc(&pl->tab_pinned, std::max<size_t>(pl->tab_host.size(), 1), hipHostMallocDefault));
+      std::memcpy(pl->tab_pinned, pl->tab_host.data(), pl->tab_host.size());
+      FRSD_HIP(hipEventCreateWithFlags(&pl->tab_done, hipEventDisableTiming));
+    }
+    src = static_cast<const unsigned char *>(pl->tab_pinned);
+  }
+  for (const TabSeg &g : pl->tab_seg)
+    FRSD_HIP(hipMemcpyAsync(ws_ptr<void>(ws, g.ws_off), src + g.host_off, g.bytes, hipMemcpyHostToDevice, s));
+  if (!pageable) FRSD_HIP(hipEventRecord(pl->tab_done, s));
   return FRSD_OK;
 }
 

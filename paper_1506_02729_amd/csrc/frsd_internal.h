@@ -94,6 +94,12 @@ constexpr int kTriBlocks = 1024;
 constexpr int kTriMfmaBlocks = 1024;
 constexpr int kPairBatch = 8;   // shell-field pairs per inverse-FFT batch
 
+// One constant table of a plan: bytes at host_off of the plan's host table
+// image go to workspace offset ws_off.
+struct TabSeg {
+  size_t host_off, ws_off, bytes;
+};
+
 }  // namespace frsd
 
 struct frsd_plan {
@@ -115,6 +121,14 @@ struct frsd_plan {
   frsd::Layout L;
   int state = 0;                      // 0 created, 1 initialised, 2 assigned, 3 pk done
   void *init_ws = nullptr;
+  // Constant tables (twiddles, bin lookups, triangle and contraction tables),
+  // built on the host once per plan and copied into a workspace at init.
+  std::vector<unsigned char> tab_host;
+  std::vector<frsd::TabSeg> tab_seg;
+  bool tab_built = false;
+  void *tab_pinned = nullptr;          // page-locked copy of tab_host: the uploads are asynchronous
+  hipEvent_t tab_done = nullptr;       // recorded on the stream after the last upload from tab_pinned
+  ~frsd_plan();
 };
 
 namespace frsd {
@@ -173,7 +187,12 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s);
 template <typename T>
 int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s);
 int run_nt(frsd_plan *pl, void *ws, hipStream_t s);
-int upload_tables(frsd_plan *pl, void *ws, hipStream_t s);
+// Host table image of the plan (once per plan), then its upload into ws on
+// stream s: from page-locked memory (asynchronous; allocates it on the first
+// call) or, with `pageable`, straight from the host image (no allocation).
+int build_tables(frsd_plan *pl);
+void tab_add(frsd_plan *pl, size_t ws_off, const void *src, size_t bytes);
+int upload_tables(frsd_plan *pl, void *ws, hipStream_t s, bool pageable);
 
 // FFT passes (fft.hip) --------------------------------------------------------
 // Forward c2c FFT of n_batch N^3 complex meshes given as planar real arrays
@@ -193,7 +212,10 @@ size_t triple_mfma_dense_bytes();
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
 int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);
 int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStream_t s);
-int triple_mfma_upload(frsd_plan *pl, void *ws);
+// Job and pair tables of the contraction for ne column groups (n_ell for
+// T_ell; 1 and for_nt for the N^T indicator sums), added to the plan's
+// table image.
+int triple_mfma_tables(frsd_plan *pl, int ne, bool for_nt);
 
 // Shell-filtered inverse FFTs on the M^3 grid (bk.hip).
 template <typename T>

@@ -266,6 +266,16 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   return FRSD_OK;
 }
 
+// The page-locked table image may still be the source of uploads queued by
+// frsd_plan_init: wait for them before it is freed.
+frsd_plan::~frsd_plan() {
+  if (tab_done) {
+    (void)hipEventSynchronize(tab_done);
+    (void)hipEventDestroy(tab_done);
+  }
+  if (tab_pinned) (void)hipHostFree(tab_pinned);
+}
+
 extern "C" void frsd_plan_destroy(frsd_plan *plan) { delete plan; }
 
 extern "C" int frsd_plan_workspace_bytes(const frsd_plan *plan, size_t *bytes) {

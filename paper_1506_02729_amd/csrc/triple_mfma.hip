@@ -638,32 +638,26 @@ int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStrea
                            ws_ptr<const int4>(ws, pl->L.tri_tab) + pl->n_out, (int)pl->ntri, s);
 }
 
-// Uploads the (row tile, column tile) -> job table, the row of each pair and
-// the pair (b2, b3) of each row for ne column groups (synchronous; plan init).
-static int upload_tables_for(frsd_plan *pl, void *ws, int ne, size_t dense_off, size_t pair_off) {
+// The (row tile, column tile) -> job table, the row of each pair and the
+// pair (b2, b3) of each row for ne column groups, added to the plan's table
+// image: those of T_ell (ne = n_ell) at tri_dense / pair_tab, those of the
+// N^T indicator sums (for_nt, ne = 1) at tri_dense_nt / pair_tab_nt.
+int triple_mfma_tables(frsd_plan *pl, int ne, bool for_nt) {
   XJobs jobs;
   std::vector<int16_t> tile_job;
   int njobs = 0;
   if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
-  double *dense = ws_ptr<double>(ws, dense_off);
-  int16_t *tj = reinterpret_cast<int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
-  FRSD_HIP(hipMemcpy(tj, tile_job.data(), tile_job.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+  const size_t dense_off = for_nt ? pl->L.tri_dense_nt : pl->L.tri_dense;
+  const size_t pair_off = for_nt ? pl->L.pair_tab_nt : pl->L.pair_tab;
+  tab_add(pl, dense_off + sizeof(double) * (size_t)kXWaves * kXMaxJobs * 256, tile_job.data(),
+          tile_job.size() * sizeof(int16_t));
   const int nb = pl->p.bk_nbins;
   const std::vector<int> row = pair_rows(pl, ne);
   std::vector<int2> pairs(row.size());
   for (int b2 = 0; b2 < nb; ++b2)
     for (int b3 = 0; b3 <= b2; ++b3) pairs[row[b2 * (b2 + 1) / 2 + b3]] = make_int2(b2, b3);
-  FRSD_HIP(hipMemcpy(ws_ptr<void>(ws, pair_off), pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
+  tab_add(pl, pair_off, pairs.data(), pairs.size() * sizeof(int2));
   return FRSD_OK;
-}
-
-// Tables of the T_ell contraction and, when it fits the tiles, of the N^T
-// indicator sums.
-int triple_mfma_upload(frsd_plan *pl, void *ws) {
-  int rc = upload_tables_for(pl, ws, pl->n_ell, pl->L.tri_dense, pl->L.pair_tab);
-  if (rc) return rc;
-  if (triple_mfma_supported(pl, 1)) rc = upload_tables_for(pl, ws, 1, pl->L.tri_dense_nt, pl->L.pair_tab_nt);
-  return rc;
 }
 
 }  // namespace frsd
