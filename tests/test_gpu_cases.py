@@ -1,0 +1,149 @@
+"""GPU parity on paths and inputs the other parity tests do not reach:
+a forward mesh side without a compiled FFT kernel, triangle lists beyond the
+matrix-core tile tables (the vector contraction for T_ell with the N^T sums
+still on the matrix cores, and more than 37 bins), an observer inside the
+box (lines of sight in every direction), negative weights and an empty galaxy
+catalogue.  Same tolerances as ``test_gpu_parity``: 1e-10 (FP64 plans) and
+2e-4 (FP32 plans) per bin or triangle against max(|ref|, c_b); counts exact.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from paper_1506_02729_amd import synth
+from test_gpu_parity import TOL, _bk_case, _cfg, _check_bk, _check_pk, _rel, _run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle(gal, ran, alpha, prm, triangles=None):
+    fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+    refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+    refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields, triangles=triangles) if prm.bk_nbins else None
+    return refp, refb
+
+
+def _check_bk_sample(out, refb, idx, prm, precision, plan):
+    """_check_bk on the triangles plan.triangles[idx]."""
+    tol = TOL[precision]
+    np.testing.assert_array_equal(plan.triangles[idx], refb["triangles"])
+    np.testing.assert_array_equal(out["bk_nt"][idx], refb["NT"])
+    ok = refb["NT"] > 0
+    assert ok.sum() > len(idx) // 2
+    for ell in (0, 2, 4):
+        e = _rel(out[f"bk_t{ell}"][idx][ok], refb[f"T{ell}"][ok], refb[f"C{ell}"][ok])
+        assert np.max(e) < tol, (f"T{ell}", np.max(e))
+        floor = (2 * ell + 1) * refb[f"C{ell}"][ok] / (refb["NT"][ok] * refb["I33"])
+        e = _rel(out[f"bk_b{ell}"][idx][ok], refb[f"B{ell}"][ok], floor)
+        assert np.max(e) < tol, (f"B{ell}", np.max(e))
+    e = _rel(out["bk_sn0"][idx], refb["SN0"], np.abs(refb["SN0"]))
+    assert np.max(e) < tol
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_runtime_forward_length(gpu_lib, precision):
+    """N = 80 (2^4 5) has no compiled forward kernel: the run-time pencil
+    kernels transform every pass; M = 80 is a run-time shell length too."""
+    _log(f"case: N=80 run-time forward FFT precision={precision}")
+    gal, ran, alpha, prm = _bk_case(71, N=80, nbk=8, n_gal=5000, n_ran=25000)
+    prm.pk_dk = 2.0 * prm.kf
+    prm.pk_nbins = 19
+    refp, refb = _oracle(gal, ran, alpha, prm)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    assert plan.bk_grid == 80
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
+def _dense_case(seed, N, nb, kmin, dk, n_gal=6000, n_ran=30000):
+    gal, ran, alpha, prm = _bk_case(seed, N=N, nbk=nb, n_gal=n_gal, n_ran=n_ran)
+    prm.bk_kmin, prm.bk_dk = kmin * prm.kf, dk * prm.kf
+    prm.pk_kmin, prm.pk_dk, prm.pk_nbins = 0.0, 2.0 * prm.kf, N // 4 - 1
+    return gal, ran, alpha, prm
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_triangle_list_beyond_the_tile_tables(gpu_lib, precision):
+    """37 bins of 1 k_f from 14.5 k_f (N = 112, run-time forward and shell
+    lengths, M = 160): every bin triple closes, 8314 triangles; the T_ell
+    product needs 129 output tiles (more than the 128 of the matrix-core
+    tables, so the vector contraction runs) while the N^T indicator sums need
+    82 and stay on the FP64 matrix cores.  Checked on 160 sampled triangles
+    and every power-spectrum bin."""
+    _log(f"case: 37 dense bins N=112 precision={precision}")
+    gal, ran, alpha, prm = _dense_case(81, 112, 37, 14.5, 1.0)
+    tri = est.triangle_list(prm)
+    assert len(tri) == 8314
+    idx = np.sort(np.random.Generator(np.random.PCG64(5)).choice(len(tri), 160, replace=False))
+    refp, refb = _oracle(gal, ran, alpha, prm, triangles=tri[idx])
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    assert plan.bk_grid == 160
+    _check_pk(out, refp, prm, precision)
+    _check_bk_sample(out, refb, idx, prm, precision, plan)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_more_bins_than_the_matrix_core_tables(gpu_lib, precision):
+    """40 bins of 1 k_f from 1.5 k_f (N = 96, M = 125): more bins than the
+    matrix-core tables hold, so both the T_ell and the N^T sums take the
+    vector contraction.  Checked on 120 sampled triangles."""
+    _log(f"case: 40 bins N=96 precision={precision}")
+    gal, ran, alpha, prm = _dense_case(83, 96, 40, 1.5, 1.0)
+    tri = est.triangle_list(prm)
+    idx = np.sort(np.random.Generator(np.random.PCG64(6)).choice(len(tri), 120, replace=False))
+    refp, refb = _oracle(gal, ran, alpha, prm, triangles=tri[idx])
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    assert plan.bk_grid == 125
+    _check_pk(out, refp, prm, precision)
+    _check_bk_sample(out, refb, idx, prm, precision, plan)
+
+
+@pytest.mark.parametrize("precision,N,order", [(64, 48, 3), (32, 48, 3), (32, 64, 3), (32, 64, 2), (64, 48, 4)])
+def test_observer_inside_the_box(gpu_lib, precision, N, order):
+    """Observer at the centre of the box: lines of sight in every direction
+    (both signs of every component), on the gather (N = 48) and x-sweep
+    (N = 64, FP32) assignment kernels."""
+    _log(f"case: observer inside the box N={N} order={order} precision={precision}")
+    gal, ran, alpha, prm = _bk_case(91 + order, N=N, order=order, n_gal=4000, n_ran=20000)
+    prm.observer = (301.3, 288.7, 305.1)
+    refp, refb = _oracle(gal, ran, alpha, prm)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
+@pytest.mark.parametrize("precision,N", [(64, 48), (32, 64)])
+def test_negative_weights(gpu_lib, precision, N):
+    """Weights of both signs (the boundary allows them): a third of the
+    galaxies and randoms carry negative w."""
+    _log(f"case: negative weights N={N} precision={precision}")
+    gal, ran, alpha, prm = _bk_case(97, N=N, n_gal=4000, n_ran=20000)
+    rng = np.random.Generator(np.random.PCG64(98))
+    for c in (gal, ran):
+        c["w"] = np.where(rng.random(len(c["w"])) < 0.33, -c["w"], c["w"])
+    refp, refb = _oracle(gal, ran, alpha, prm)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+
+
+def test_empty_galaxy_catalogue(gpu_lib):
+    """No galaxies: the field is -alpha times the randoms' (raw sums valid)."""
+    _log("case: empty galaxy catalogue")
+    gal, ran, alpha, prm = _bk_case(99, nbk=3)
+    empty = {"pos": np.zeros((0, 3)), "w": np.zeros(0), "nbar": np.zeros(0)}
+    refp, refb = _oracle(empty, ran, alpha, prm)
+    out, plan = _run_gpu(gpu_lib, prm, 64, empty, ran, alpha)
+    np.testing.assert_array_equal(out["n_modes"], refp["n_modes"])
+    assert np.max(_rel(out["s00"], refp["S00"], 0)) < 1e-10
+    _check_pk(out, refp, prm, 64)
+    _check_bk(out, refb, prm, 64, plan)

@@ -53,3 +53,41 @@ def test_results_same_alone_and_in_the_mix(gpu_lib):
         for key in ("p0", "p2", "p4", "p4b", "bk_t0", "bk_t2", "bk_t4"):
             scale = np.max(np.abs(alone[i][key]))
             assert np.max(np.abs(mix[key] - alone[i][key])) <= 1e-5 * scale, (i, key)
+
+
+def test_mixed_sizes_in_flight(gpu_lib):
+    """Requests of different mesh sizes and bin sets in flight together: a
+    48^3 (gather assignment), a 64^3 (x-sweep assignment) and a 96^3 FP32
+    plan, each on its own stream, enqueued before any result is read; each
+    result equals the same request run alone (1e-5 of the largest value) and
+    the FP64 oracle (2e-4 per bin)."""
+    import torch
+    _log("case: 48^3, 64^3 and 96^3 FP32 requests in flight together")
+    dev = torch.device("cuda:0")
+    cases = [_bk_case(111, N=48, nbk=5), _bk_case(112, N=64, nbk=6, n_gal=4000, n_ran=20000),
+             _bk_case(113, N=96, nbk=8, n_gal=8000, n_ran=40000)]
+    cases[2][3].pk_nbins = 20
+    cfgs = [_cfg(gpu_lib, prm, 32, len(g["w"]) + len(r["w"])) for g, r, _, prm in cases]
+    cats = [(gpu_lib.device_catalog(g, dev), gpu_lib.device_catalog(r, dev), a) for g, r, a, _ in cases]
+    torch.cuda.synchronize()
+    alone = [gpu_lib.Plan(cfg, device=dev).run(g, r, a) for cfg, (g, r, a) in zip(cfgs, cats)]
+    plans = [gpu_lib.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev)) for cfg in cfgs]
+    torch.cuda.synchronize()
+    for plan, (g, r, a) in zip(plans, cats):
+        plan.mesh_assign(g, r, a)
+        plan.pk()
+        plan.bk()
+    torch.cuda.synchronize()
+    for i, plan in enumerate(plans):
+        assert plan.status() == 0
+        mix = {k: v.cpu().numpy() for k, v in plan.pk_buf.items()}
+        mix.update({"bk_" + k: v.cpu().numpy() for k, v in plan.bk_buf.items()})
+        gal, ran, alpha, prm = cases[i]
+        fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
+        _check_pk(mix, est.pk_multipoles(gal, ran, alpha, prm, fields=fields), prm, 32)
+        _check_bk(mix, est.bk_multipoles(gal, ran, alpha, prm, fields=fields), prm, 32, plan)
+        np.testing.assert_array_equal(mix["n_modes"], alone[i]["n_modes"])
+        np.testing.assert_array_equal(mix["bk_nt"], alone[i]["bk_nt"])
+        for key in ("p0", "p2", "p4", "p4b", "bk_t0", "bk_t2", "bk_t4"):
+            scale = np.max(np.abs(alone[i][key]))
+            assert np.max(np.abs(mix[key] - alone[i][key])) <= 1e-5 * scale, (i, key)
