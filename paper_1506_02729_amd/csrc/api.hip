@@ -13,7 +13,7 @@ static int check_ws(const frsd_plan *pl, const void *ws) {
   return FRSD_OK;
 }
 
-static int check_catalog(const frsd_catalog *c, bool need_nbar, const char *what) {
+int frsd::check_catalog(const frsd_catalog *c, bool need_nbar, const char *what) {
   if (!c) return fail(FRSD_EINVAL, std::string("null catalogue: ") + what);
   if (c->n < 0) return fail(FRSD_EINVAL, std::string("negative size: ") + what);
   if (c->n == 0) return FRSD_OK;

@@ -136,6 +136,8 @@ namespace frsd {
 // error handling ------------------------------------------------------------
 int fail(int code, const std::string &msg);
 void clear_error();
+// FRSD_EINVAL unless c is a valid catalogue (randoms need nbar)
+int check_catalog(const frsd_catalog *c, bool need_nbar, const char *what);
 
 #define FRSD_HIP(call)                                                       \
   do {                                                                       \
@@ -207,7 +209,7 @@ int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mes
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);
 bool triple_mfma_supported(const frsd_plan *pl, int ne);
-size_t triple_mfma_part_bytes(int nwg);
+size_t triple_mfma_part_bytes(const frsd_plan *pl, int nwg);
 size_t triple_mfma_dense_bytes();
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
 int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);

@@ -244,8 +244,12 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
       L.shells = take(shell_bytes);
     }
     L.tri_tab = take(16 * (size_t)pl->n_out + 16 * (size_t)pl->ntri + 12 * (size_t)pl->ntri);
-    L.tri_part = take(std::max(8 * (size_t)std::max(pl->n_out, (int)pl->ntri) * kTriBlocks,
-                               triple_mfma_part_bytes(kTriMfmaBlocks)));
+    // contraction partials: the vector contraction's (per output and
+    // workgroup) only for the sums that do not fit the matrix-core tables
+    size_t vec_part = 0;
+    if (!triple_mfma_supported(pl)) vec_part = std::max(vec_part, 8 * (size_t)pl->n_out * kTriBlocks);
+    if (!triple_mfma_supported(pl, 1)) vec_part = std::max(vec_part, 8 * (size_t)pl->ntri * kTriBlocks);
+    L.tri_part = take(std::max(vec_part, triple_mfma_part_bytes(pl, kTriMfmaBlocks)));
     L.pair_tab = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
     L.tri_dense = take(triple_mfma_dense_bytes());
     L.pair_tab_nt = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);

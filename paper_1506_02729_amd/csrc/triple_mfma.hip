@@ -551,7 +551,21 @@ bool triple_mfma_supported(const frsd_plan *pl, int ne) {
 }
 bool triple_mfma_supported(const frsd_plan *pl) { return triple_mfma_supported(pl, pl->n_ell); }
 
-size_t triple_mfma_part_bytes(int nwg) { return sizeof(double) * (size_t)nwg * kXWaves * kXMaxJobs * 256; }
+// Workgroup partials of the contractions that run on the matrix cores: nwg
+// workgroups x the larger job count of T_ell and N^T x one 16 x 16 tile,
+// FP64 (FP32 plans store FP32 partials in the same region).
+size_t triple_mfma_part_bytes(const frsd_plan *pl, int nwg) {
+  int most = 0;
+  for (const int ne : {pl->n_ell, 1}) {
+    XJobs j;
+    std::vector<int16_t> tj;
+    int n = 0;
+    const int nb = pl->p.bk_nbins;
+    if (nb > kXMaxB || nb * (nb + 1) / 2 > kXMaxRows || ne * nb > kXCols) continue;
+    if (make_jobs(pl, ne, &j, &tj, &n)) most = std::max(most, n);
+  }
+  return sizeof(double) * (size_t)nwg * (size_t)most * 256;
+}
 size_t triple_mfma_dense_bytes() {
   return sizeof(double) * (size_t)kXWaves * kXMaxJobs * 256 + sizeof(int16_t) * ((kXMaxRows / 16) * 7 + kXMaxRows) +
          256;
