@@ -161,6 +161,28 @@ int frsd_bk_grid(const frsd_plan *plan, int32_t *m);
  * (Sec. III.B).  Requires a preceding frsd_pk_multipoles on ws. */
 int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid allocation): one whole
+ * request -- the plan's tables and N^T, then the steps of frsd_mesh_assign,
+ * frsd_pk_multipoles and, when bk is non-NULL and the plan has bispectrum
+ * bins, frsd_bk_multipoles -- with the library's static device scratch as
+ * the workspace instead of a caller-provided one.  Same arguments, outputs
+ * and results as that sequence; the caller passes the catalogues and the
+ * output arrays only.  Allocates nothing: no hipMalloc, hipFree or
+ * page-locked allocation (tables are copied from the plan's host image, or
+ * from its page-locked copy if frsd_plan_init made one).
+ * Limit: the plan's workspace (frsd_plan_workspace_bytes) must fit the
+ * scratch of 128 MiB (e.g. FP32 plans up to N = 64 with a few bispectrum
+ * bins); larger plans get FRSD_ENOMEM before any device work.  The scratch
+ * (one per device, held until the process ends) keeps the last call's
+ * contents; every region a call reads is written by that call first.  All
+ * calls on one device share it: calls that overlap in time on one device
+ * (other streams or threads) race and give undefined results.  The count
+ * of rejected objects is not reported (frsd_status needs a workspace).
+ * Asynchronous on `stream`. */
+int frsd_run_static(frsd_plan *plan, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
+                    const frsd_pk_out *pk, const frsd_bk_out *bk, void *stream);
+
 /* Synchronises `stream` and reports the number of objects rejected by the
  * last frsd_mesh_assign (outside [0, L)^3 or at the observer).  Returns
  * FRSD_EDOM when that number is non-zero. */

@@ -78,6 +78,8 @@ _proto = {
     "frsd_bk_grid": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "frsd_bk_triangles": (ctypes.c_int, [_P, _P]),
     "frsd_bk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_bk_out), _P]),
+    "frsd_run_static": (ctypes.c_int, [_P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
+                                       ctypes.c_double, ctypes.POINTER(frsd_pk_out), ctypes.POINTER(frsd_bk_out), _P]),
     "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "frsd_profile": (ctypes.c_int, [ctypes.c_int]),
     "frsd_profile_report": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -151,6 +153,12 @@ def frsd_bk_triangles(plan) -> np.ndarray:
 
 def frsd_bk_multipoles(plan, ws_ptr, out: frsd_bk_out, stream) -> None:
     _check(_lib.frsd_bk_multipoles(plan, ws_ptr, ctypes.byref(out), stream))
+
+
+def frsd_run_static(plan, gal: frsd_catalog, ran: frsd_catalog, alpha: float, pk: frsd_pk_out,
+                    bk: frsd_bk_out | None, stream) -> None:
+    _check(_lib.frsd_run_static(plan, ctypes.byref(gal), ctypes.byref(ran), float(alpha), ctypes.byref(pk),
+                                ctypes.byref(bk) if bk is not None else None, stream))
 
 
 def frsd_status(plan, ws_ptr, stream) -> int:
