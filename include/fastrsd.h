@@ -77,6 +77,13 @@ typedef struct {
                             top bispectrum edge in k_f units), which makes the grid
                             sum equal to the exact closed-triangle sum              */
   int64_t max_objects;   /* capacity: galaxies + randoms per frsd_mesh_assign call    */
+  int32_t bk_ell_max;    /* bispectrum multipoles: 0, 2 or 4 (<= ell_max); -1: ell_max */
+  int32_t bk_shot_noise; /* l > 0 shot noise of eq. (SNbisp2thin): 0 its q1 term only;
+                            1 complete, with the w^2-weighted multipoles F^w_2, F^w_4
+                            (the moment meshes gridded again with weight w^2 inside
+                            frsd_bk_multipoles, transformed to the bispectrum sphere) */
+  int32_t bk_zero_area;  /* 1: also T_220 and the zero-area hexadecapole B4za of
+                            Sec. II.C eq. (Bhexa2) (needs bk_ell_max >= 2)          */
 } frsd_params;
 
 /* A catalogue in device memory.  pos is n x 3 interleaved (x, y, z);
@@ -114,8 +121,15 @@ typedef struct {
   double *nt;             /* N^T, exact count of closed lattice triangles (eq. NT)  */
   double *t0, *t2, *t4;   /* raw triangle sums sum_T Re F_ell(q1) F_0(q2) F_0(q3)   */
   double *b0, *b2, *b4;   /* (2 ell + 1) T_ell / (N^T I33); NaN when N^T == 0        */
-  double *sn0, *sn2, *sn4;/* thin-shell shot noise (eq. SNbisp2thin): sn0 complete,
-                             sn2/sn4 the q1 term only.  B_ell = b_ell - sn_ell      */
+  double *sn0, *sn2, *sn4;/* thin-shell shot noise (eq. SNbisp2thin), N^(ell): sn0
+                             complete; sn2/sn4 complete with bk_shot_noise = 1, else
+                             the q1 term (2l+1) S_lw(b1)/(N_b1 I33).  The cosines
+                             qhat1.qhat_i come from the law of cosines at the bin
+                             centres (clamped to [-1, 1]).  B_ell = b_ell - sn_ell;
+                             NaN for ell > bk_ell_max                               */
+  double *t220;           /* optional (bk_zero_area): sum_T Re F_2(q1) F_2(q2) F_0(q3) */
+  double *b4za;           /* optional (bk_zero_area): (35/2 T_220 - 5 T_2 - 7/2 T_0) /
+                             (N^T I33), eq. (Bhexa2), no shot noise subtracted      */
 } frsd_bk_out;
 
 /* Validates parameters and builds the host-side plan: bins, triangle list,

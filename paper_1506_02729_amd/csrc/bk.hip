@@ -503,11 +503,24 @@ __global__ void k_nt_final(const double *sum, int ntri, double inv_m3, double *n
 
 struct BkFinalArgs {
   int ntri, n_ell, pk_nb;
+  int full_sn;   // complete l > 0 shot noise (Q_lw sums present)
   double inv_m3;
 };
 
+__device__ __forceinline__ double legendre_even(int ell, double mu) {
+  const double m2 = mu * mu;
+  return ell == 2 ? 1.5 * m2 - 0.5 : (35.0 * m2 * m2 - 30.0 * m2 + 3.0) * 0.125;
+}
+
+// B_ell^raw = (2 ell + 1) T_ell / (N^T I33) (eqs. BispMono, BispQuad), the
+// thin-shell shot noise of eq. SNbisp2thin and, with t220, the zero-area
+// hexadecapole of eq. Bhexa2.  Shot noise for l > 0: the q1 term
+// (2l+1) S_lw(b1) / (N_b1 I33) and, with full_sn, the q2 and q3 terms
+// (2l+1) L_l(qhat1 . qhat_i) Q_lw(b_i) / (N_bi I33), the cosines from the
+// law of cosines at the bin centres ctr (k_f units), clamped to [-1, 1].
 __global__ void k_bk_final(const int *tri, const double *tsum, const double *nt, const double *bin_sum,
-                           const double *scal, BkFinalArgs a, frsd_bk_out out) {
+                           const double *scal, const double *ctr, const double *t220, BkFinalArgs a,
+                           frsd_bk_out out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ntri) return;
   const double I33 = scal[2], W3 = scal[3];
@@ -517,29 +530,46 @@ __global__ void k_bk_final(const int *tri, const double *tsum, const double *nt,
   double *tp[3] = {out.t0, out.t2, out.t4};
   double *bp[3] = {out.b0, out.b2, out.b4};
   double *sp[3] = {out.sn0, out.sn2, out.sn4};
+  double Tl[3] = {nan, nan, nan};
   out.nt[t] = NT;
   for (int li = 0; li < 3; ++li) {
     const double ell = 2.0 * li;
     if (li < a.n_ell) {
       const double T = tsum[t * a.n_ell + li] * a.inv_m3;
+      Tl[li] = T;
       tp[li][t] = T;
       bp[li][t] = NT > 0 ? (2 * ell + 1) * T / (NT * I33) : nan;
     } else {
       tp[li][t] = nan; bp[li][t] = nan;
     }
   }
-  // bin sums of the bispectrum bins: [count, sum|k|, S00, S20, S40, S0w, S2w, S4w]
+  // bin sums of the bispectrum bins: [count, sum|k|, Q2w, Q4w, -, S0w, S2w, S4w]
   auto bs = [&](int bin, int q) { return bin_sum[(a.pk_nb + bin) * kBinSums + q]; };
   double sn0 = 0;
   for (int i = 0; i < 3; ++i) sn0 += bs(b[i], 5) / bs(b[i], 0);
   sp[0][t] = sn0 / I33 - 2.0 * W3 / I33;
-  sp[1][t] = a.n_ell > 1 ? 5.0 * bs(b[0], 6) / (bs(b[0], 0) * I33) : nan;
-  sp[2][t] = a.n_ell > 2 ? 9.0 * bs(b[0], 7) / (bs(b[0], 0) * I33) : nan;
+  const double k1 = ctr[b[0]], k2 = ctr[b[1]], k3 = ctr[b[2]];
+  const double c12 = fmin(1.0, fmax(-1.0, (k3 * k3 - k1 * k1 - k2 * k2) / (2.0 * k1 * k2)));
+  const double c13 = fmin(1.0, fmax(-1.0, (k2 * k2 - k1 * k1 - k3 * k3) / (2.0 * k1 * k3)));
+  for (int li = 1; li < 3; ++li) {
+    const int ell = 2 * li;
+    if (li >= a.n_ell) { sp[li][t] = nan; continue; }
+    double v = bs(b[0], 5 + li) / bs(b[0], 0);
+    if (a.full_sn)
+      v += legendre_even(ell, c12) * bs(b[1], 1 + li) / bs(b[1], 0) +
+           legendre_even(ell, c13) * bs(b[2], 1 + li) / bs(b[2], 0);
+    sp[li][t] = (2 * ell + 1) * v / I33;
+  }
+  if (t220) {
+    const double T = t220[t] * a.inv_m3;
+    if (out.t220) out.t220[t] = T;
+    if (out.b4za) out.b4za[t] = NT > 0 ? (17.5 * T - 5.0 * Tl[1] - 3.5 * Tl[0]) / (NT * I33) : nan;
+  }
 }
 
 template <typename T>
 static int contract(frsd_plan *pl, void *ws, const T *fields, int nfield, const int4 *otab, int nout,
-                    hipStream_t s) {
+                    hipStream_t s, size_t sum_off = (size_t)-1) {
   const Layout &L = pl->L;
   const long long M3 = (long long)pl->M * pl->M * pl->M;
   const size_t shmem = sizeof(T) * (size_t)nfield * kTriChunk;
@@ -548,7 +578,7 @@ static int contract(frsd_plan *pl, void *ws, const T *fields, int nfield, const 
   FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple<T>, dim3(kTriBlocks, ny), dim3(kTriThreads), shmem, s, fields, M3, nfield, otab, nout,
                      ws_ptr<double>(ws, L.tri_part)));
   FRSD_TIMED("tri_reduce", s, hipLaunchKernelGGL(k_sum_part, dim3((nout + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.tri_part),
-                     kTriBlocks, nout, ws_ptr<double>(ws, L.tri_sum)));
+                     kTriBlocks, nout, ws_ptr<double>(ws, sum_off == (size_t)-1 ? L.tri_sum : sum_off)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -574,25 +604,45 @@ template <typename T>
 int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s) {
   const Layout &L = pl->L;
   const int nfield = pl->n_ell * pl->p.bk_nbins;
+  int rc;
+  // complete l > 0 shot noise: the w^2-weighted moments and their Q_lw sums
+  // (they use the planar and mesh regions before the shell fields take them)
+  if (pl->n_wmom > 0) {
+    if ((rc = run_w_moments<T>(pl, ws, s))) return rc;
+    if ((rc = run_bin_w<T>(pl, ws, s))) return rc;
+  }
   T *shells = ws_ptr<T>(ws, L.shells);
-  int rc = shell_pipeline<T, T, false>(pl, ws, nfield, ws_ptr<void>(ws, L.tw_inv), shells, s);
+  rc = shell_pipeline<T, T, false>(pl, ws, nfield, ws_ptr<void>(ws, L.tw_inv), shells, s);
   if (rc) return rc;
+  const bool z220 = pl->p.bk_zero_area != 0;
+  const int4 *otab220 = ws_ptr<const int4>(ws, L.tri_tab220);
   if constexpr (sizeof(T) == 4) {
     if (triple_mfma_supported(pl)) rc = triple_mfma(pl, ws, reinterpret_cast<const float *>(shells), s);
     else rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+    if (!rc && z220) {
+      if (triple_mfma_supported(pl, 1)) rc = triple_mfma_220(pl, ws, reinterpret_cast<const float *>(shells), s);
+      else rc = contract<T>(pl, ws, shells, nfield, otab220, (int)pl->ntri, s, L.tri_sum220);
+    }
   } else {
     if (triple_mfma_supported(pl)) rc = triple_mfma64(pl, ws, reinterpret_cast<const double *>(shells), s);
     else rc = contract<T>(pl, ws, shells, nfield, ws_ptr<const int4>(ws, L.tri_tab), pl->n_out, s);
+    if (!rc && z220) {
+      if (triple_mfma_supported(pl, 1)) rc = triple_mfma64_220(pl, ws, reinterpret_cast<const double *>(shells), s);
+      else rc = contract<T>(pl, ws, shells, nfield, otab220, (int)pl->ntri, s, L.tri_sum220);
+    }
   }
   if (rc) return rc;
   BkFinalArgs a{};
   a.ntri = (int)pl->ntri; a.n_ell = pl->n_ell; a.pk_nb = pl->p.pk_nbins;
+  a.full_sn = pl->n_wmom > 0 ? 1 : 0;
   a.inv_m3 = 1.0 / ((double)pl->M * pl->M * pl->M);
   // the triangle list is kept in the tail of the table region as int32 triples
   const int *tri = reinterpret_cast<const int *>(ws_ptr<const int4>(ws, L.tri_tab) + pl->n_out + pl->ntri);
   FRSD_TIMED("bk_final", s, hipLaunchKernelGGL(k_bk_final, dim3((unsigned)((pl->ntri + 255) / 256)), dim3(256), 0, s, tri,
                      ws_ptr<const double>(ws, L.tri_sum), ws_ptr<const double>(ws, L.nt),
-                     ws_ptr<const double>(ws, L.bin_sum), ws_ptr<const double>(ws, L.scal), a, *out));
+                     ws_ptr<const double>(ws, L.bin_sum), ws_ptr<const double>(ws, L.scal),
+                     ws_ptr<const double>(ws, L.bk_ctr), z220 ? ws_ptr<const double>(ws, L.tri_sum220) : nullptr,
+                     a, *out));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -703,6 +753,18 @@ int build_tables(frsd_plan *pl) {
     }
     tab_add(pl, L.tri_tab, tab.data(), tab.size() * sizeof(int4));
     tab_add(pl, L.tri_tab + tab.size() * sizeof(int4), pl->tri.data(), pl->tri.size() * sizeof(int32_t));
+    // bin centres in k_f units (the thin-shell cosines of the shot noise)
+    std::vector<double> ctr(nb);
+    for (int b = 0; b < nb; ++b) ctr[b] = 0.5 * (std::sqrt(pl->bk_e2[b]) + std::sqrt(pl->bk_e2[b + 1]));
+    tab_add(pl, L.bk_ctr, ctr.data(), ctr.size() * sizeof(double));
+    if (pl->p.bk_zero_area) {
+      // vector-contraction outputs of T_220: (F_2 of b1, F_2 of b2, F_0 of b3)
+      std::vector<int4> t220((size_t)pl->ntri);
+      for (int64_t t = 0; t < pl->ntri; ++t)
+        t220[t] = make_int4(nb + pl->tri[3 * t], nb + pl->tri[3 * t + 1], pl->tri[3 * t + 2], 0);
+      tab_add(pl, L.tri_tab220, t220.data(), t220.size() * sizeof(int4));
+      if (triple_mfma_supported(pl, 1)) triple_mfma_tables_220(pl);
+    }
     if (triple_mfma_supported(pl)) {
       const int rc = triple_mfma_tables(pl, pl->n_ell, false);
       if (rc) return rc;

@@ -76,6 +76,9 @@ struct Layout {
   size_t nt = 0;                                 // N^T per triangle
   size_t pk_lut = 0, bk_lut = 0;                 // |n|^2 -> bin index (int16, -1 outside)
   size_t bk_m2 = 0;                              // |n|^2 range of every bispectrum bin (int2)
+  size_t bk_ctr = 0;                             // centre of every bispectrum bin, k_f units (double)
+  size_t pair_tab_220 = 0, tri_sum220 = 0;       // pairs (F_2 b2, F_0 b3) and sums of T_220
+  size_t tri_tab220 = 0;                         // vector-contraction outputs of T_220 (F_2 b1, F_2 b2, F_0 b3)
   size_t total = 0;
 };
 
@@ -116,7 +119,9 @@ struct frsd_plan {
   std::vector<int32_t> tri;           // 3 * ntri
   int64_t ntri = 0;
   int n_out = 0;                      // contraction outputs (ntri * n_ell)
-  int n_ell = 0;                      // multipoles in the bispectrum (1 or 3)
+  int n_ell = 0;                      // multipoles in the bispectrum (1, 2 or 3)
+  int bk_ell = 0;                     // highest bispectrum multipole (0, 2 or 4)
+  int n_wmom = 0;                     // w^2-weighted moments of the complete l > 0 shot noise (0, 7 or 22)
   frsd::FftLen fft_n, fft_m;
   frsd::Layout L;
   int state = 0;                      // 0 created, 1 initialised, 2 assigned, 3 pk done
@@ -186,6 +191,11 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
 int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s);
+// complete l > 0 shot noise: w^2-weighted moments (grid.hip), their sums (pk.hip)
+template <typename T>
+int run_w_moments(frsd_plan *pl, void *ws, hipStream_t s);
+template <typename T>
+int run_bin_w(frsd_plan *pl, void *ws, hipStream_t s);
 template <typename T>
 int run_bk(frsd_plan *pl, void *ws, const frsd_bk_out *out, hipStream_t s);
 int run_nt(frsd_plan *pl, void *ws, hipStream_t s);
@@ -214,6 +224,10 @@ size_t triple_mfma_dense_bytes();
 int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
 int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);
 int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStream_t s);
+// T_220 = sum_x F_{2,b1} F_{2,b2} F_{0,b3} on the N^T job tiles (when those fit)
+int triple_mfma_220(frsd_plan *pl, void *ws, const float *fields, hipStream_t s);
+int triple_mfma64_220(frsd_plan *pl, void *ws, const double *fields, hipStream_t s);
+void triple_mfma_tables_220(frsd_plan *pl);
 // Job and pair tables of the contraction for ne column groups (n_ell for
 // T_ell; 1 and for_nt for the N^T indicator sums), added to the plan's
 // table image.

@@ -91,6 +91,7 @@ struct GridArgs {
   int n_ell_mom;       // moments of the multipoles: 1, 7 or 22 (ell_max 0, 2, 4)
   int has_w;           // w^2 plane present (position n_ell_mom)
   int interlace;
+  int wsq;             // 1: every object weighs t0^2 (the w^2-weighted moments of F^w_l)
   double ou[3];        // observer in grid units
   long long plane_stride;
 };
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
       r.x = (T)(LO + col / CY) + g.x;
       r.y = (T)(LO + col % CY) + g.y;
       r.z = (T)(LO + k) + g.z;
-      r.w = g.w;
+      r.w = ga.wsq ? g.w * g.w : g.w;
       st[i - s0] = r;
     }
     __syncthreads();
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const Rec4<float> g = recs[gsrc[lo] + (i - cst[lo])];
         const int iy = lo / CZ, iz = lo - iy * CZ;
         SweepRec r;
-        r.a = make_float4(g.x, (float)(LO + iy) + g.y, (float)(LO + iz) + g.z, g.w);
+        r.a = make_float4(g.x, (float)(LO + iy) + g.y, (float)(LO + iz) + g.z, ga.wsq ? g.w * g.w : g.w);
         st[i - s0] = r;
       }
       __syncthreads();
@@ -612,23 +613,25 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   }
 }
 
+// Assignment of n_ell_mom moment planes (and the w^2 plane when has_w);
+// wsq: weights t0^2 instead of t0 (a second pass after the first, whose
+// occupancy masks it reuses).
 template <typename T, int P>
-static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
+static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq) {
   const Layout &L = pl->L;
   const int N = pl->N;
-  const SlotDesc &sd = pl->slots;
   GridArgs ga{};
   ga.N = N;
-  for (int m = 0; m < sd.n_mom; ++m) {
-    if (sd.mom_id[m] == kMomW) ga.has_w = 1;
-    else ++ga.n_ell_mom;
-  }
+  ga.n_ell_mom = n_ell_mom;
+  ga.has_w = has_w;
+  ga.wsq = wsq;
   ga.interlace = pl->p.interlace;
   for (int d = 0; d < 3; ++d) ga.ou[d] = pl->p.observer[d] / pl->h;
   ga.plane_stride = (long long)N * N * N;
-  FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
-                                               ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
-                                               ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
+  if (!wsq)
+    FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
+                                                 ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
+                                                 ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
   if constexpr (std::is_same<T, float>::value && P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
       const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
@@ -658,22 +661,51 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s) {
 }
 
 template <typename T>
+static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq) {
+  switch (pl->p.order) {
+    case 1: return launch_grid<T, 1>(pl, ws, s, n_ell_mom, has_w, wsq);
+    case 2: return launch_grid<T, 2>(pl, ws, s, n_ell_mom, has_w, wsq);
+    case 3: return launch_grid<T, 3>(pl, ws, s, n_ell_mom, has_w, wsq);
+    default: return launch_grid<T, 4>(pl, ws, s, n_ell_mom, has_w, wsq);
+  }
+}
+
+template <typename T>
 int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
                     hipStream_t s) {
   int rc = ingest_and_sort<T>(pl, ws, gal, ran, alpha, s);
   if (rc) return rc;
-  switch (pl->p.order) {
-    case 1: rc = launch_grid<T, 1>(pl, ws, s); break;
-    case 2: rc = launch_grid<T, 2>(pl, ws, s); break;
-    case 3: rc = launch_grid<T, 3>(pl, ws, s); break;
-    default: rc = launch_grid<T, 4>(pl, ws, s); break;
+  const SlotDesc &sd = pl->slots;
+  int n_ell_mom = 0, has_w = 0;
+  for (int m = 0; m < sd.n_mom; ++m) {
+    if (sd.mom_id[m] == kMomW) has_w = 1;
+    else ++n_ell_mom;
   }
-  if (rc) return rc;
+  if ((rc = grid_order<T>(pl, ws, s, n_ell_mom, has_w, 0))) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
                           ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax,
                           std::max(pl->pk_lut_len, pl->p.bk_nbins > 0 ? pl->bk_lut_len : 0) - 1,
                           ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
 }
+
+// The w^2-weighted moment meshes of F^w_2, F^w_4 (Sec. III.B, the definition
+// of F^w_l below eq. SNbisp2): the first n_wmom moments gridded again from
+// the sorted records with weight t0^2 (w^2 for galaxies, alpha^2 w^2 for
+// randoms), then transformed with the forward passes pruned to the
+// bispectrum sphere.  Overwrites the planar and mesh regions (the
+// multipole fields of the bispectrum already sit in the low-k cube).
+template <typename T>
+int run_w_moments(frsd_plan *pl, void *ws, hipStream_t s) {
+  int rc = grid_order<T>(pl, ws, s, pl->n_wmom, 0, 1);
+  if (rc) return rc;
+  const int n_slot = pl->p.interlace ? pl->n_wmom : (pl->n_wmom + 1) / 2;
+  return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
+                          ws_ptr<void>(ws, pl->L.mesh), n_slot, pl->nc_b, pl->bk_lut_len - 1,
+                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
+}
+
+template int run_w_moments<float>(frsd_plan *, void *, hipStream_t);
+template int run_w_moments<double>(frsd_plan *, void *, hipStream_t);
 
 template int run_mesh_assign<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
                                     hipStream_t);

@@ -119,7 +119,11 @@ __device__ __forceinline__ void add_slots(std::integer_sequence<int, S...>, int 
 
 // IL: slot s holds moment position s on the main grid (real part) and on
 // the twin grid (imaginary part); otherwise positions 2s and 2s+1.
-template <typename T, bool GEOM, bool IL>
+// WP: the slots hold the w^2-weighted moments (a second assignment pass),
+// whose combinations are F^w_0, F^w_2, F^w_4; only bispectrum bins are
+// summed, Q_lw = sum Re[F_0 (F^w_l)^*] for l = 2, 4, with F_0 read from the
+// low-k cube written by the first pass.
+template <typename T, bool GEOM, bool IL, bool WP = false>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict__ mesh, long long slot_stride,
                                                       BinArgs a, const int16_t *__restrict__ pk_lut,
                                                       const int16_t *__restrict__ bk_lut, cplx_t<T> *lowk,
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
       const bool half = (iz > 0) || (iy > 0) || (iy == 0 && ix > 0);
       m2 = (long long)ix * ix + (long long)iy * iy + (long long)iz * iz;
       if (half) {
-        kp = (m2 < a.pk_lut_len) ? pk_lut[m2] : -1;
+        kp = (!WP && m2 < a.pk_lut_len) ? pk_lut[m2] : -1;
         kb = (a.bk_nb > 0 && m2 < a.bk_lut_len) ? bk_lut[m2] : -1;
       }
     }
@@ -260,11 +264,18 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
       const double S4w = A[2][0] * A[3][0] + A[2][1] * A[3][1];
       const double S22 = A[1][0] * A[1][0] + A[1][1] * A[1][1];
       // each half-space mode stands for n and -n
-      if constexpr (NV == 4) {
+      if constexpr (WP) {
+        if (kb >= 0) {
+          const int D = a.D, nc = a.nc_b;
+          const C f0 = lowk[((long long)(ix + nc) * D + (iy + nc)) * D + (iz + nc)];
+          vb[0] = 2.0 * ((double)f0.x * A[1][0] + (double)f0.y * A[1][1]);
+          vb[1] = 2.0 * ((double)f0.x * A[2][0] + (double)f0.y * A[2][1]);
+        }
+      } else if constexpr (NV == 4) {
         vp[0] = 2.0 * S00; vp[1] = 2.0 * S20; vp[2] = 2.0 * S40; vp[3] = 2.0 * S22;
         vb[0] = 2.0 * S0w; vb[1] = 2.0 * S2w; vb[2] = 2.0 * S4w; vb[3] = 0.0;
       }
-      if (kb >= 0 && lowk) {
+      if (!WP && kb >= 0 && lowk) {
         // A_0, A_2, A_4 at n and -n on the low-k cube [-nc, nc]^3
         const int D = a.D, nc = a.nc_b;
         const long long DDD = (long long)D * D * D;
@@ -285,20 +296,22 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
 }
 
 // Sum of the per-block partials, one wavefront per (bin, quantity) reading
-// its nblk contiguous partials, into the kBinSums slots of the bin: geometry
-// into slots 0-1, data sums into 2-5 (P_ell bins: S00 S20 S40 S22) or 5-7
-// (bispectrum bins: S0w S2w S4w; their fourth quantity is not kept).
+// its nblk contiguous partials, into the kBinSums slots of the bin.  mode 1
+// (geometry): slots 0-1; mode 0 (data): slots 2-5 (P_ell bins: S00 S20 S40
+// S22) or 5-7 (bispectrum bins: S0w S2w S4w; their fourth quantity is not
+// kept); mode 2 (w^2-weighted pass): slots 2-3 of the bispectrum bins (Q2w,
+// Q4w).
 __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb,
-                                                    int geom, double *sum) {
+                                                    int mode, double *sum) {
   const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= nall * nv) return;  // whole wavefronts
   double s = 0;
   for (int b = lane; b < nblk; b += 64) s += part[(long long)i * nblk + b];
   s = wave_sum(s);
   const int bin = i / nv, q = i - bin * nv;
-  const bool keep = geom || bin < pk_nb || q < 3;
+  const bool keep = mode == 1 || (mode == 0 && (bin < pk_nb || q < 3)) || (mode == 2 && bin >= pk_nb && q < 2);
   if (lane == 0 && keep) {
-    const int slot = geom ? q : (bin < pk_nb ? 2 + q : 5 + q);
+    const int slot = mode == 1 ? q : (mode == 2 ? 2 + q : (bin < pk_nb ? 2 + q : 5 + q));
     sum[bin * kBinSums + slot] = s;
   }
 }
@@ -371,7 +384,7 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
                                                (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part)));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
-                                                 p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));
+                                                 p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));  // geometry
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -406,5 +419,36 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
 
 template int run_pk<float>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t);
 template int run_pk<double>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t);
+
+// Q_lw = sum_b Re[F_0 (F^w_l)^*] (l = 2, 4) of every bispectrum bin from the
+// w^2-weighted moment meshes of run_w_moments (the q_2, q_3 terms of Sec. III.B
+// eq. SNbisp2thin), into slots 2-3 of the bispectrum bins' sums.
+template <typename T>
+int run_bin_w(frsd_plan *pl, void *ws, hipStream_t s) {
+  const Layout &L = pl->L;
+  const frsd_params &p = pl->p;
+  const int nall = p.pk_nbins + p.bk_nbins;
+  BinArgs a = bin_args(pl);
+  a.nmax = pl->nc_b;
+  a.n_ell = pl->n_wmom;
+  a.has_w = 0;
+  a.n_slot = p.interlace ? pl->n_wmom : (pl->n_wmom + 1) / 2;
+  using C = cplx_t<T>;
+  const long long NNN = (long long)pl->N * pl->N * pl->N;
+  constexpr int NV = BinValues<false>::n;
+  auto kern = p.interlace ? k_bin<T, false, true, true> : k_bin<T, false, false, true>;
+  FRSD_TIMED("bin_w", s, hipLaunchKernelGGL(kern, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
+                                            NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
+                                            ws_ptr<const int16_t>(ws, L.bk_lut), ws_ptr<C>(ws, L.lowk),
+                                            ws_ptr<double>(ws, L.bin_part)));
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
+                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 p.pk_nbins, 2, ws_ptr<double>(ws, L.bin_sum)));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+template int run_bin_w<float>(frsd_plan *, void *, hipStream_t);
+template int run_bin_w<double>(frsd_plan *, void *, hipStream_t);
 
 }  // namespace frsd

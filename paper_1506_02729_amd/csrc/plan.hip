@@ -126,6 +126,12 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (p.bk_nbins < 0 || (p.bk_nbins > 0 && (!(p.bk_dk > 0) || p.bk_kmin < 0)))
     return fail(FRSD_EINVAL, "invalid bispectrum bins");
   if (p.max_objects < 0) return fail(FRSD_EINVAL, "max_objects must be >= 0");
+  const int bk_ell = p.bk_ell_max < 0 ? p.ell_max : p.bk_ell_max;
+  if (p.bk_ell_max < -1 || (bk_ell != 0 && bk_ell != 2 && bk_ell != 4) || bk_ell > p.ell_max)
+    return fail(FRSD_EINVAL, "bk_ell_max must be -1, 0, 2 or 4 and at most ell_max");
+  if (p.bk_shot_noise != 0 && p.bk_shot_noise != 1) return fail(FRSD_EINVAL, "bk_shot_noise must be 0 or 1");
+  if (p.bk_zero_area != 0 && p.bk_zero_area != 1) return fail(FRSD_EINVAL, "bk_zero_area must be 0 or 1");
+  if (p.bk_zero_area && bk_ell < 2) return fail(FRSD_EINVAL, "bk_zero_area needs the quadrupole (bk_ell_max >= 2)");
 
   frsd_plan *pl = new frsd_plan();
   pl->p = p;
@@ -168,8 +174,10 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
             pl->tri.push_back(b1); pl->tri.push_back(b2); pl->tri.push_back(b3);
           }
     pl->ntri = (int64_t)pl->tri.size() / 3;
-    pl->n_ell = p.ell_max == 0 ? 1 : (p.ell_max == 2 ? 2 : 3);
+    pl->bk_ell = bk_ell;
+    pl->n_ell = bk_ell / 2 + 1;
     pl->n_out = (int)(pl->ntri * pl->n_ell);
+    pl->n_wmom = (p.bk_shot_noise && bk_ell >= 2) ? (bk_ell == 2 ? 7 : 22) : 0;
   }
 
   // moments in slot order, and their packing into complex meshes
@@ -256,6 +264,12 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     L.tri_dense_nt = take(triple_mfma_dense_bytes());
     L.tri_sum = take(8 * (size_t)std::max(pl->n_out, (int)pl->ntri));
     L.nt = take(8 * (size_t)pl->ntri);
+    L.bk_ctr = take(8 * (size_t)p.bk_nbins);
+    if (p.bk_zero_area) {
+      L.pair_tab_220 = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
+      L.tri_sum220 = take(8 * (size_t)pl->ntri);
+      L.tri_tab220 = take(16 * (size_t)pl->ntri);
+    }
   }
   // bin lookup tables |n|^2 -> bin (int16)
   pl->pk_lut_len = (int)std::ceil(pl->pk_e2.back());

@@ -42,6 +42,7 @@ constexpr int kXKC = 64;          // cells per LDS stage (2 MFMA k-steps)
 constexpr int kXUPad = kXKC + 4;  // FP32 row stride of the staged F_0 shells (16-byte aligned rows)
 constexpr int kXBPad = kXKC + 16; // bf16 row stride of the staged B operand (16-byte aligned rows; 40 dwords measured fastest)
 constexpr int kXMaxB = 37;        // bins
+constexpr int kXMaxU = 2 * kXMaxB + 1;  // staged pair-product rows: F_0 and F_2 shells of every bin, then a zero row
 constexpr int kXPf = (kXCols * (kXKC / 2) + kXThreads - 1) / kXThreads;  // cell pairs per thread per stage
 
 struct XJobs {
@@ -51,10 +52,16 @@ struct XJobs {
   int nj[kXWaves];
 };
 
+// ncol: columns of the product (B fields); nload: fields read per stage
+// (fields 0..nload-1 of the shell array); nu: fields staged for the pair
+// products (0..nu-1).  t220: the columns are the F_2 fields (nb..2nb-1)
+// and the pair rows hold F_{2,b2} F_{0,b3} (Sec. II.C eq. Bhexa2);
+// otherwise field l nb + b1 is column b1 n_ell + l.
 struct XArgs {
   long long ncell;
   long long cells_per_wg;
   int nb, n_ell, ncol, npair, njobs;
+  int nload, nu, t220;
 };
 
 // Split of FP32 values into bfloat16 pairs, two values at once: one packed
@@ -94,13 +101,14 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
   // two stage buffers; row kXMaxB of U stays zero.  B2[buffer][0] holds the
   // hi parts, B2[buffer][1] the lo parts, at a fixed byte distance so one
   // address serves both reads.
-  __shared__ __attribute__((aligned(16))) float U2[2][kXMaxB + 1][kXUPad];
+  __shared__ __attribute__((aligned(16))) float U2[2][kXMaxU][kXUPad];
   __shared__ __attribute__((aligned(16))) __bf16 B2[2][2][kXCols][kXBPad];
   __shared__ uint32_t prs[kXMaxRows];  // byte offsets in U of rows b2 (low half) and b3 (high half)
-  __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
-  constexpr int kURow = kXUPad * 4, kUBuf = (kXMaxB + 1) * kURow;  // bytes
+  __shared__ uint8_t cmap[kXCols];     // staged field -> column (0xff: not a column)
+  constexpr int kURow = kXUPad * 4, kUBuf = kXMaxU * kURow;  // bytes
   constexpr int kBRow = kXBPad * 2, kBHalf = kXCols * kBRow, kBBuf = 2 * kBHalf;
-  static_assert(kXMaxB * kURow < 65536 && kBHalf < 65536, "offsets must fit 16 bits / the DS immediate");
+  constexpr int kZeroRow = kXMaxU - 1;
+  static_assert(kZeroRow * kURow < 65536 && kBHalf < 65536, "offsets must fit 16 bits / the DS immediate");
 
   const int lane = threadIdx.x & 63;
   // wave-uniform (scalar) so the job table is read with scalar loads and the
@@ -133,14 +141,14 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 
   // rows past the last pair read the zero row of U
   for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
-    uint32_t v = (uint32_t)(kXMaxB * kURow) * 0x10001u;
+    uint32_t v = (uint32_t)(kZeroRow * kURow) * 0x10001u;
     if (i < a.npair) { const int2 p = pairs[i]; v = (uint32_t)(p.x * kURow) | ((uint32_t)(p.y * kURow) << 16); }
     prs[i] = v;
   }
-  for (int i = threadIdx.x; i < 2 * kXUPad; i += kXThreads) U2[i / kXUPad][kXMaxB][i % kXUPad] = 0.f;
-  for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
+  for (int i = threadIdx.x; i < 2 * kXUPad; i += kXThreads) U2[i / kXUPad][kZeroRow][i % kXUPad] = 0.f;
+  for (int i = threadIdx.x; i < a.nload; i += kXThreads) {
     const int l = i / a.nb, b1 = i - l * a.nb;
-    cmap[i] = (uint8_t)(b1 * a.n_ell + l);
+    cmap[i] = a.t220 ? (uint8_t)(l == 1 ? b1 : 0xff) : (uint8_t)(b1 * a.n_ell + l);
   }
   // padding columns stay zero
   for (int i = threadIdx.x; i < 2 * (kXCols - a.ncol) * kXBPad; i += kXThreads) {
@@ -152,7 +160,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 
   const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
   const long long c_end = min(a.ncell, c_begin + a.cells_per_wg);
-  const int npe = a.ncol * (kXKC / 2);  // cell pairs per stage
+  const int npe = a.nload * (kXKC / 2);  // cell pairs per stage
   const bool even = (a.ncell & 1) == 0;
   float2 pf[kXPf];
 
@@ -185,11 +193,13 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
       if (e < npe) {
         const int fl = e >> 5, k = 2 * (e & 31);
         const int col = cmap[fl];
-        bf16x2_t h, l;
-        split2_bf16(pf[q].x, pf[q].y, h, l);
-        *reinterpret_cast<bf16x2_t *>(&Bh[col][k]) = h;
-        *reinterpret_cast<bf16x2_t *>(&Bl[col][k]) = l;
-        if (fl < a.nb) *reinterpret_cast<float2 *>(&U[fl][k]) = pf[q];
+        if (col != 0xff) {
+          bf16x2_t h, l;
+          split2_bf16(pf[q].x, pf[q].y, h, l);
+          *reinterpret_cast<bf16x2_t *>(&Bh[col][k]) = h;
+          *reinterpret_cast<bf16x2_t *>(&Bl[col][k]) = l;
+        }
+        if (fl < a.nu) *reinterpret_cast<float2 *>(&U[fl][k]) = pf[q];
       }
     }
   };
@@ -278,11 +288,12 @@ constexpr int kZPf = (kXCols * (kZKC / 2) + kXThreads - 1) / kXThreads;  // cell
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                double *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) double U2[2][kXMaxB + 1][kZPad];  // row kXMaxB stays zero
+  __shared__ __attribute__((aligned(16))) double U2[2][kXMaxU][kZPad];  // the last row stays zero
   __shared__ __attribute__((aligned(16))) double B2[2][kXCols][kZPad];
   __shared__ uint32_t prs[kXMaxRows];  // U row offsets (doubles) of b2 (low half) and b3 (high half)
-  __shared__ uint8_t cmap[kXCols];     // field l * nb + b1 -> column b1 * n_ell + l
-  static_assert(kXMaxB * kZPad < 65536, "row offsets must fit 16 bits");
+  __shared__ uint8_t cmap[kXCols];     // staged field -> column (0xff: not a column)
+  constexpr int kZeroRow = kXMaxU - 1;
+  static_assert(kZeroRow * kZPad < 65536, "row offsets must fit 16 bits");
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -304,14 +315,14 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__res
   for (int j = 0; j < kXMaxJobs; ++j) acc[j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 
   for (int i = threadIdx.x; i < kXMaxRows; i += kXThreads) {
-    uint32_t v = (uint32_t)(kXMaxB * kZPad) * 0x10001u;
+    uint32_t v = (uint32_t)(kZeroRow * kZPad) * 0x10001u;
     if (i < a.npair) { const int2 p = pairs[i]; v = (uint32_t)(p.x * kZPad) | ((uint32_t)(p.y * kZPad) << 16); }
     prs[i] = v;
   }
-  for (int i = threadIdx.x; i < 2 * kZPad; i += kXThreads) U2[i / kZPad][kXMaxB][i % kZPad] = 0.0;
-  for (int i = threadIdx.x; i < a.ncol; i += kXThreads) {
+  for (int i = threadIdx.x; i < 2 * kZPad; i += kXThreads) U2[i / kZPad][kZeroRow][i % kZPad] = 0.0;
+  for (int i = threadIdx.x; i < a.nload; i += kXThreads) {
     const int l = i / a.nb, b1 = i - l * a.nb;
-    cmap[i] = (uint8_t)(b1 * a.n_ell + l);
+    cmap[i] = a.t220 ? (uint8_t)(l == 1 ? b1 : 0xff) : (uint8_t)(b1 * a.n_ell + l);
   }
   for (int i = threadIdx.x; i < 2 * (kXCols - a.ncol) * kZPad; i += kXThreads) {
     const int bsel = i & 1, ii = i >> 1;
@@ -320,7 +331,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__res
 
   const long long c_begin = (long long)blockIdx.x * a.cells_per_wg;
   const long long c_end = min(a.ncell, c_begin + a.cells_per_wg);
-  const int npe = a.ncol * (kZKC / 2);  // cell pairs per stage
+  const int npe = a.nload * (kZKC / 2);  // cell pairs per stage
   const bool even = (a.ncell & 1) == 0;
   double2 pf[kZPf];
   auto load = [&](long long c0) {
@@ -348,8 +359,9 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__res
       const int e = threadIdx.x + q * kXThreads;
       if (e < npe) {
         const int fl = e >> 4, k = 2 * (e & 15);
-        *reinterpret_cast<double2 *>(&B2[bsel][cmap[fl]][k]) = pf[q];
-        if (fl < a.nb) *reinterpret_cast<double2 *>(&U2[bsel][fl][k]) = pf[q];
+        const int col = cmap[fl];
+        if (col != 0xff) *reinterpret_cast<double2 *>(&B2[bsel][col][k]) = pf[q];
+        if (fl < a.nu) *reinterpret_cast<double2 *>(&U2[bsel][fl][k]) = pf[q];
       }
     }
   };
@@ -571,50 +583,71 @@ size_t triple_mfma_dense_bytes() {
          256;
 }
 
-int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
+// FP32 plans: T_ell (t220 = false) with the job tables at tri_dense and the
+// pairs (F_0 b2, F_0 b3) at pair_tab, or T_220 (t220) with the job tables
+// of the N^T sums (one column group) and the pairs (F_2 b2, F_0 b3).
+static int triple_mfma_run(frsd_plan *pl, void *ws, const float *fields, bool t220, hipStream_t s) {
   const Layout &L = pl->L;
   XArgs a{};
   a.ncell = (long long)pl->M * pl->M * pl->M;
   a.nb = pl->p.bk_nbins;
-  a.n_ell = pl->n_ell;
-  a.ncol = pl->n_ell * a.nb;
+  const int ne = t220 ? 1 : pl->n_ell;
+  a.n_ell = ne;
+  a.ncol = ne * a.nb;
+  a.nload = t220 ? 2 * a.nb : a.ncol;
+  a.nu = t220 ? 2 * a.nb : a.nb;
+  a.t220 = t220 ? 1 : 0;
   a.npair = a.nb * (a.nb + 1) / 2;
   XJobs jobs;
   std::vector<int16_t> tile_job;
   int njobs = 0;
-  if (!make_jobs(pl, pl->n_ell, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
+  if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
   a.njobs = njobs;
   const int nwg = kTriMfmaBlocks;
   long long per = (a.ncell + nwg - 1) / nwg;
   per = (per + kXKC - 1) / kXKC * kXKC;
   a.cells_per_wg = per;
-  double *dense = ws_ptr<double>(ws, L.tri_dense);
+  double *dense = ws_ptr<double>(ws, t220 ? L.tri_dense_nt : L.tri_dense);
   const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
-  FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple_mfma, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
-                                             ws_ptr<const int2>(ws, L.pair_tab), ws_ptr<float>(ws, L.tri_part)));
+  FRSD_TIMED(t220 ? "triple_220" : "triple", s,
+             hipLaunchKernelGGL(k_triple_mfma, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
+                                ws_ptr<const int2>(ws, t220 ? L.pair_tab_220 : L.pair_tab),
+                                ws_ptr<float>(ws, L.tri_part)));
   const int nvals = njobs * 256;
   FRSD_TIMED("tri_reduce", s,
              hipLaunchKernelGGL(k_triple_mfma_reduce<float>, dim3((nvals + 255) / 256), dim3(256), 0, s,
                                 ws_ptr<const float>(ws, L.tri_part), nwg, nvals, dense));
+  const int nout = t220 ? (int)pl->ntri : pl->n_out;
+  const int4 *otab = ws_ptr<const int4>(ws, L.tri_tab) + (t220 ? pl->n_out : 0);
   FRSD_TIMED("tri_gather", s,
-             hipLaunchKernelGGL(k_triple_mfma_gather, dim3((pl->n_out + 255) / 256), dim3(256), 0, s, dense,
-                                ws_ptr<const int4>(ws, L.tri_tab), tj, a.nb, a.n_ell, pl->n_out,
-                                ws_ptr<double>(ws, L.tri_sum)));
+             hipLaunchKernelGGL(k_triple_mfma_gather, dim3((nout + 255) / 256), dim3(256), 0, s, dense, otab, tj,
+                                a.nb, a.n_ell, nout, ws_ptr<double>(ws, t220 ? L.tri_sum220 : L.tri_sum)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
+}
+
+int triple_mfma(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
+  return triple_mfma_run(pl, ws, fields, false, s);
+}
+int triple_mfma_220(frsd_plan *pl, void *ws, const float *fields, hipStream_t s) {
+  return triple_mfma_run(pl, ws, fields, true, s);
 }
 
 // FP64 on the matrix cores: ne column groups of fields (n_ell for T_ell,
 // 1 for the N^T indicator sums), with the job tables at `dense_off` and the
 // pair table at `pair_off`; writes tsum[o] for the nout outputs of otab.
 static int triple_mfma64_run(frsd_plan *pl, void *ws, const double *fields, int ne, size_t dense_off,
-                             size_t pair_off, const int4 *otab, int nout, hipStream_t s) {
+                             size_t pair_off, const int4 *otab, int nout, size_t sum_off, bool t220,
+                             hipStream_t s) {
   const Layout &L = pl->L;
   XArgs a{};
   a.ncell = (long long)pl->M * pl->M * pl->M;
   a.nb = pl->p.bk_nbins;
   a.n_ell = ne;
   a.ncol = ne * a.nb;
+  a.nload = t220 ? 2 * a.nb : a.ncol;
+  a.nu = t220 ? 2 * a.nb : a.nb;
+  a.t220 = t220 ? 1 : 0;
   a.npair = a.nb * (a.nb + 1) / 2;
   XJobs jobs;
   std::vector<int16_t> tile_job;
@@ -627,15 +660,16 @@ static int triple_mfma64_run(frsd_plan *pl, void *ws, const double *fields, int 
   a.cells_per_wg = per;
   double *dense = ws_ptr<double>(ws, dense_off);
   const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
-  FRSD_TIMED("triple", s, hipLaunchKernelGGL(k_triple_mfma64, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
-                                             ws_ptr<const int2>(ws, pair_off), ws_ptr<double>(ws, L.tri_part)));
+  FRSD_TIMED(t220 ? "triple_220" : "triple", s,
+             hipLaunchKernelGGL(k_triple_mfma64, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
+                                ws_ptr<const int2>(ws, pair_off), ws_ptr<double>(ws, L.tri_part)));
   const int nvals = njobs * 256;
   FRSD_TIMED("tri_reduce", s,
              hipLaunchKernelGGL(k_triple_mfma_reduce<double>, dim3((nvals + 255) / 256), dim3(256), 0, s,
                                 ws_ptr<const double>(ws, L.tri_part), nwg, nvals, dense));
   FRSD_TIMED("tri_gather", s,
              hipLaunchKernelGGL(k_triple_mfma_gather, dim3((nout + 255) / 256), dim3(256), 0, s, dense, otab, tj,
-                                a.nb, ne, nout, ws_ptr<double>(ws, L.tri_sum)));
+                                a.nb, ne, nout, ws_ptr<double>(ws, sum_off)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
@@ -643,19 +677,38 @@ static int triple_mfma64_run(frsd_plan *pl, void *ws, const double *fields, int 
 // FP64 plans: T_ell on the same job tiles as the FP32 path.
 int triple_mfma64(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) {
   return triple_mfma64_run(pl, ws, fields, pl->n_ell, pl->L.tri_dense, pl->L.pair_tab,
-                           ws_ptr<const int4>(ws, pl->L.tri_tab), pl->n_out, s);
+                           ws_ptr<const int4>(ws, pl->L.tri_tab), pl->n_out, pl->L.tri_sum, false, s);
 }
 
 // N^T indicator sums (plan init): one column group, the triangle list as outputs.
 int triple_mfma64_nt(frsd_plan *pl, void *ws, const double *indicators, hipStream_t s) {
   return triple_mfma64_run(pl, ws, indicators, 1, pl->L.tri_dense_nt, pl->L.pair_tab_nt,
-                           ws_ptr<const int4>(ws, pl->L.tri_tab) + pl->n_out, (int)pl->ntri, s);
+                           ws_ptr<const int4>(ws, pl->L.tri_tab) + pl->n_out, (int)pl->ntri, pl->L.tri_sum, false, s);
+}
+
+// T_220 of FP64 plans: the N^T job tiles (their dense region is free after
+// plan init), pairs (F_2 b2, F_0 b3), one output per triangle.
+int triple_mfma64_220(frsd_plan *pl, void *ws, const double *fields, hipStream_t s) {
+  return triple_mfma64_run(pl, ws, fields, 1, pl->L.tri_dense_nt, pl->L.pair_tab_220,
+                           ws_ptr<const int4>(ws, pl->L.tri_tab) + pl->n_out, (int)pl->ntri, pl->L.tri_sum220, true,
+                           s);
 }
 
 // The (row tile, column tile) -> job table, the row of each pair and the
 // pair (b2, b3) of each row for ne column groups, added to the plan's table
 // image: those of T_ell (ne = n_ell) at tri_dense / pair_tab, those of the
 // N^T indicator sums (for_nt, ne = 1) at tri_dense_nt / pair_tab_nt.
+// Pairs (F_2 b2, F_0 b3) of the T_220 rows, in the row order of the N^T
+// job tables (staged rows nb + b2 and b3).
+void triple_mfma_tables_220(frsd_plan *pl) {
+  const int nb = pl->p.bk_nbins;
+  const std::vector<int> row = pair_rows(pl, 1);
+  std::vector<int2> pairs(row.size());
+  for (int b2 = 0; b2 < nb; ++b2)
+    for (int b3 = 0; b3 <= b2; ++b3) pairs[row[b2 * (b2 + 1) / 2 + b3]] = make_int2(nb + b2, b3);
+  tab_add(pl, pl->L.pair_tab_220, pairs.data(), pairs.size() * sizeof(int2));
+}
+
 int triple_mfma_tables(frsd_plan *pl, int ne, bool for_nt) {
   XJobs jobs;
   std::vector<int16_t> tile_job;

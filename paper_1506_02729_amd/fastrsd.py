@@ -47,6 +47,7 @@ class frsd_params(ctypes.Structure):
         ("pk_kmin", ctypes.c_double), ("pk_dk", ctypes.c_double), ("pk_nbins", ctypes.c_int32),
         ("bk_kmin", ctypes.c_double), ("bk_dk", ctypes.c_double), ("bk_nbins", ctypes.c_int32),
         ("bk_grid", ctypes.c_int32), ("max_objects", ctypes.c_int64),
+        ("bk_ell_max", ctypes.c_int32), ("bk_shot_noise", ctypes.c_int32), ("bk_zero_area", ctypes.c_int32),
     ]
 
 
@@ -62,7 +63,7 @@ class frsd_pk_out(ctypes.Structure):
 
 class frsd_bk_out(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
-                ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4")]
+                ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4", "t220", "b4za")]
 
 
 _P = ctypes.c_void_p
@@ -204,6 +205,9 @@ class Config:
     bk_nbins: int = 0
     bk_grid: int = 0
     max_objects: int = 0
+    bk_ell_max: int = -1
+    bk_shot_noise: bool = False
+    bk_zero_area: bool = False
 
     def to_c(self) -> frsd_params:
         p = frsd_params()
@@ -215,6 +219,7 @@ class Config:
         p.pk_kmin, p.pk_dk, p.pk_nbins = self.pk_kmin, self.pk_dk, self.pk_nbins
         p.bk_kmin, p.bk_dk, p.bk_nbins = self.bk_kmin, self.bk_dk, self.bk_nbins
         p.bk_grid, p.max_objects = self.bk_grid, int(self.max_objects)
+        p.bk_ell_max, p.bk_shot_noise, p.bk_zero_area = self.bk_ell_max, int(self.bk_shot_noise), int(self.bk_zero_area)
         return p
 
 
@@ -274,6 +279,9 @@ class Plan:
         if self.ntri:
             for key in ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4"):
                 self.bk_buf[key] = torch.zeros(self.ntri, **f64)
+            if cfg.bk_zero_area:
+                for key in ("t220", "b4za"):
+                    self.bk_buf[key] = torch.zeros(self.ntri, **f64)
         frsd_plan_init(self.handle, self.ws_ptr, self.ws_bytes, self.stream.cuda_stream)
 
     def __del__(self):
@@ -304,7 +312,7 @@ class Plan:
     def bk(self) -> dict:
         o = frsd_bk_out()
         for name, _ in frsd_bk_out._fields_:
-            setattr(o, name, self.bk_buf[name].data_ptr())
+            setattr(o, name, self.bk_buf[name].data_ptr() if name in self.bk_buf else None)
         frsd_bk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
         return self.bk_buf
 

@@ -147,3 +147,79 @@ def test_empty_galaxy_catalogue(gpu_lib):
     assert np.max(_rel(out["s00"], refp["S00"], 0)) < 1e-10
     _check_pk(out, refp, prm, 64)
     _check_bk(out, refb, prm, 64, plan)
+
+
+def _check_bk_extras(out, refb, prm, precision, full_sn=True, zero_area=True):
+    """Complete l > 0 shot noise (eq. SNbisp2thin) and the zero-area
+    hexadecapole (eq. Bhexa2) against the oracle."""
+    tol = TOL[precision]
+    ok = refb["NT"] > 0
+    if full_sn:
+        for ell in (2, 4):
+            if ell > prm.ell_max:
+                continue
+            sn = refb[f"SN{ell}"]
+            assert np.max(np.abs(sn - refb[f"SN{ell}_q1"])) > 1e-3 * np.max(np.abs(sn))
+            e = _rel(out[f"bk_sn{ell}"], sn, np.max(np.abs(sn)))
+            assert np.max(e) < tol, (f"SN{ell}", np.max(e))
+    if zero_area:
+        e = _rel(out["bk_t220"][ok], refb["T220"][ok], refb["C220"][ok])
+        assert np.max(e) < tol, ("T220", np.max(e))
+        floor = (17.5 * refb["C220"] + 5.0 * refb["C2"] + 3.5 * refb["C0"])[ok] / (refb["NT"][ok] * refb["I33"])
+        e = _rel(out["bk_b4za"][ok], refb["B4za"][ok], floor)
+        assert np.max(e) < tol, ("B4za", np.max(e))
+        assert np.all(np.isnan(out["bk_b4za"][~ok]))
+
+
+@pytest.mark.parametrize("precision,N,order,interlace,ell_max", [(64, 48, 3, True, 4), (32, 48, 3, True, 4),
+                                                                 (32, 64, 3, True, 4), (64, 48, 2, False, 4),
+                                                                 (32, 64, 1, False, 2), (64, 48, 4, True, 2)])
+def test_complete_shot_noise_and_zero_area_hexadecapole(gpu_lib, precision, N, order, interlace, ell_max):
+    """Plans with bk_shot_noise = 1 (the w^2-weighted moment meshes gridded
+    again and transformed to the bispectrum sphere, Q_lw = sum Re F_0
+    (F^w_l)^*, the q2 and q3 terms of eq. SNbisp2thin) and bk_zero_area = 1
+    (T_220 on the matrix cores, B4za of eq. Bhexa2), on the gather and x-sweep
+    assignment, with and without interlacing (an odd moment count pairs the
+    last plane with zeros)."""
+    _log(f"case: complete shot noise + B4za N={N} order={order} interlace={interlace} ell_max={ell_max} "
+         f"precision={precision}")
+    gal, ran, alpha, prm = _bk_case(131 + order, N=N, order=order, interlace=interlace, ell_max=ell_max,
+                                    n_gal=4000, n_ran=20000)
+    fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True, with_w_ell=True)
+    refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
+    refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields, zero_area=True)
+    import torch
+    dev = torch.device("cuda:0")
+    cfg = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    cfg.bk_shot_noise, cfg.bk_zero_area = True, True
+    plan = gpu_lib.Plan(cfg, device=dev)
+    out = plan.run(gpu_lib.device_catalog(gal, dev), gpu_lib.device_catalog(ran, dev), alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
+    _check_bk_extras(out, refb, prm, precision)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_bispectrum_monopole_only(gpu_lib, precision):
+    """bk_ell_max = 0 on an ell_max = 4 plan (P_0,2,4 and B_0 only, as in the
+    served covariance workload): P_ell and B_0 as the oracle's, B_2 and B_4
+    NaN."""
+    _log(f"case: B_0 only with P up to l = 4, precision={precision}")
+    gal, ran, alpha, prm = _bk_case(141, nbk=5)
+    refp, refb = _oracle(gal, ran, alpha, prm)
+    import torch
+    dev = torch.device("cuda:0")
+    cfg = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    cfg.bk_ell_max = 0
+    plan = gpu_lib.Plan(cfg, device=dev)
+    out = plan.run(gpu_lib.device_catalog(gal, dev), gpu_lib.device_catalog(ran, dev), alpha)
+    _check_pk(out, refp, prm, precision)
+    tol = TOL[precision]
+    np.testing.assert_array_equal(out["bk_nt"], refb["NT"])
+    ok = refb["NT"] > 0
+    e = _rel(out["bk_t0"][ok], refb["T0"][ok], refb["C0"][ok])
+    assert np.max(e) < tol
+    e = _rel(out["bk_sn0"], refb["SN0"], np.abs(refb["SN0"]))
+    assert np.max(e) < tol
+    for key in ("bk_t2", "bk_t4", "bk_b2", "bk_b4", "bk_sn2", "bk_sn4"):
+        assert np.all(np.isnan(out[key])), key

@@ -112,3 +112,33 @@ def test_cfg3_all_triangles(cfg3, precision):
         assert np.max(_rel(out[f"bk_sn{ell}"], sn, np.max(np.abs(sn)))) < TOL[precision]
     del plan
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_cfg3_complete_shot_noise_and_zero_area(cfg3, precision):
+    """The same workload with bk_shot_noise = 1 (w^2-weighted moments gridded
+    and transformed again) and bk_zero_area = 1 (T_220 on the matrix cores):
+    the complete l > 0 thin-shell shot noise and B4za of every triangle."""
+    import torch
+    F, gold = cfg3["F"], cfg3["gold"]
+    _log(f"case: 256^3, 5416 triangles, complete shot noise + B4za, precision={precision}")
+    plan = F.Plan(config(F, precision, cfg3["obs"], cfg3["n_obj"], bk_shot_noise=True, bk_zero_area=True),
+                  device=torch.device("cuda:0"))
+    out = plan.run(cfg3["g"], cfg3["r"], cfg3["alpha"])
+    ok = check_all(out, gold, TOL[precision], plan)
+    bk, tol = gold["bk"], TOL[precision]
+    for ell in (2, 4):
+        sn = np.asarray(bk[f"SN{ell}"])
+        e = _rel(out[f"bk_sn{ell}"], sn, np.max(np.abs(sn)))
+        _log(f"  SN{ell} (complete): max rel err {e.max():.3e}")
+        assert e.max() < tol, (f"SN{ell}", e.max())
+    nt = np.asarray(bk["NT"])
+    C220 = np.asarray(bk["C220"])
+    e = _rel(out["bk_t220"][ok], np.asarray(bk["T220"])[ok], C220[ok])
+    _log(f"  T220: max rel err {e.max():.3e}")
+    assert e.max() < tol
+    floor = (17.5 * C220 + 5.0 * np.asarray(bk["C2"]) + 3.5 * np.asarray(bk["C0"]))[ok] / (nt[ok] * gold["scalars"]["I33"])
+    e = _rel(out["bk_b4za"][ok], np.asarray(bk["B4za"])[ok], floor)
+    assert e.max() < tol
+    del plan
+    torch.cuda.empty_cache()

@@ -38,7 +38,7 @@ def _outputs(F, torch, plan):
     for name, _ in F.frsd_pk_out._fields_:
         setattr(po, name, pk[name].data_ptr())
     for name, _ in F.frsd_bk_out._fields_:
-        setattr(bo, name, bk[name].data_ptr())
+        setattr(bo, name, bk[name].data_ptr() if name in bk else None)
     return pk, bk, po, bo
 
 
