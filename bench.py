@@ -13,7 +13,16 @@ the timed region and nothing is cached between requests.  --streams
 requests are in flight at once, each on its own plan (workspace) and HIP
 stream, so the kernels of consecutive requests overlap; the value is
 requests over the wall time of the whole loop.  The plain FP64 leg runs one
-mock at a time.
+mock at a time.  Per-kernel durations come from a separate pass with one
+request in flight (HIP events on the launch stream), with each kernel's
+algorithmic HBM bytes (and, when the committed counter summary matches the
+kernel source, its counter bytes) against the 8 TB/s peak; the triple
+product is priced in bf16 MFMA flops against 2.5 PF/s.
+
+The "serving" object is the served covariance run (Poisson arrivals of
+uneven mocks on 256^3, 384^3 and 512^3 meshes, admission by HBM footprint,
+p50/p99 latency, the plain FP64 path one request at a time beside it), and
+"cpu_baseline" the FP64 oracle on this host's cores.
 
 Prints one JSON line (see the "metric" key).  --gpus N > 1 is refused: the
 build targets one GPU.
@@ -66,20 +75,107 @@ def make_config(F, wl, precision, observer, max_objects):
                     bk_nbins=wl["bk_nbins"], max_objects=max_objects)
 
 
-def algorithmic_cost(name, plan_cfg, n_obj, n_slot, M, n_out, tbytes):
-    """Algorithmic bytes (HBM-bound kernels) or flops of one launch."""
-    N = plan_cfg.n_grid
-    cplx = 2 * tbytes
-    mesh = n_slot * N**3 * cplx
-    if name in ("grid", "grid_twin"):  # one grid's planes (half the mesh) written once, every record read once
-        return "hbm", mesh // 2 + n_obj * 4 * tbytes
-    if name.startswith("fft_"):  # read + write every mesh once per pass
-        return "hbm", 2 * mesh
-    if name == "shell_x":       # write two real M^3 fields per pair of 8 per launch
-        return "hbm", 16 * M**3 * tbytes
-    if name == "triple":        # 3 flops per listed output (triangle x multipole) per cell, on the matrix cores
-        return "mfma", 3.0 * n_out * M**3
-    return None, None
+def _squared_edges(kmin, dk, nb, kf):
+    """Squared bin edges in k_f units, snapped to integers within 1e-9 relative (the plan's rule)."""
+    e = (kmin + dk * np.arange(nb + 1, dtype=np.float64)) / kf
+    e2 = e * e
+    r = np.rint(e2)
+    return np.where(np.abs(e2 - r) <= 1e-9 * np.maximum(r, 1.0), r, e2)
+
+
+def _below(e2top):
+    """Largest integer strictly below sqrt(e2top)."""
+    c = int(math.floor(math.sqrt(e2top)))
+    while c > 0 and c * c >= e2top:
+        c -= 1
+    while (c + 1) * (c + 1) < e2top:
+        c += 1
+    return c
+
+
+def plan_geometry(cfg, M):
+    """Kept frequency range, binning sphere and bispectrum bins of a plan
+    (the same rules the library applies when it builds the plan)."""
+    kf = 2 * math.pi / cfg.box
+    pk_e2 = _squared_edges(cfg.pk_kmin, cfg.pk_dk, cfg.pk_nbins, kf)
+    g = {"N": cfg.n_grid, "M": M, "nc_p": _below(pk_e2[-1]), "pk_len": int(math.ceil(pk_e2[-1]))}
+    g["nmax"], g["m2max"] = g["nc_p"], g["pk_len"] - 1
+    if cfg.bk_nbins:
+        bk_e2 = _squared_edges(cfg.bk_kmin, cfg.bk_dk, cfg.bk_nbins, kf)
+        g["nc_b"] = _below(bk_e2[-1])
+        g["nmax"] = max(g["nmax"], g["nc_b"])
+        g["m2max"] = max(g["m2max"], int(math.ceil(bk_e2[-1])) - 1)
+        m = np.arange(1, int(math.ceil(bk_e2[-1])))
+        b = np.searchsorted(bk_e2, m, side="right") - 1
+        g["bk_hi"] = [int(m[b == i].max()) if np.any(b == i) else -1 for i in range(cfg.bk_nbins)]
+    return g
+
+
+def live_masks(positions, N, box, lo=-2, hi=1):
+    """Node columns (x, y) within reach of an object (cell columns holding an
+    object, dilated by the TSC window cells [lo, hi], periodic) and x slabs
+    holding such a column."""
+    occ = np.zeros((N, N), dtype=bool)
+    h = box / N
+    for pos in positions:
+        for s0 in range(0, len(pos), 4_000_000):
+            c = np.clip(np.floor(pos[s0:s0 + 4_000_000, :2] / h).astype(np.int64), 0, N - 1)
+            occ[c[:, 0], c[:, 1]] = True
+    col = np.zeros_like(occ)
+    for dx in range(lo, hi + 1):
+        for dy in range(lo, hi + 1):
+            col |= np.roll(np.roll(occ, -dx, axis=0), -dy, axis=1)
+    return col, col.any(axis=1)
+
+
+def _count_disc(nmax, m2max):
+    r = np.arange(-nmax, nmax + 1)
+    a2 = (r * r)[:, None] + (r * r)[None, :]
+    return int(np.sum(a2 <= m2max))
+
+
+def _count_sphere(nmax, m2max):
+    r = np.arange(-nmax, nmax + 1)
+    r2 = r * r
+    a2 = r2[:, None, None] + r2[None, :, None] + r2[None, None, :]
+    return int(np.sum(a2 <= m2max))
+
+
+def algorithmic_traffic(geom, col, xm, n_obj, n_slot, n_field, tb, n_batch_pairs=8):
+    """Algorithmic HBM bytes per launch of the memory-bound kernels: every
+    element a pass must read or write counted once (live survey columns and
+    slabs only, kept frequencies only), for an FP32 plan (tb = 4).  Shell
+    passes: the launch average over the request's batches of 8 field pairs."""
+    N, M, nmax, m2max = geom["N"], geom["M"], geom["nmax"], geom["m2max"]
+    c = 2 * tb
+    live_cols = int(col.sum())
+    live_rows = col.sum(axis=1)
+    nkz = 2 * nmax + 1
+    n_disc, n_sph = _count_disc(nmax, m2max), _count_sphere(nmax, m2max)
+    out = {}
+    out["grid"] = out["grid_twin"] = live_cols * N * tb * n_slot + n_obj * 4 * tb
+    out["fft_z"] = n_slot * (live_cols * N * 2 * tb + live_cols * nkz * c)
+    out["fft_y"] = n_slot * (int(live_rows[xm].sum()) * nkz * c + int(xm.sum()) * n_disc * c)
+    out["fft_x"] = n_slot * (n_disc * int(xm.sum()) * c + n_sph * c)
+    out["bin"] = n_slot * n_sph * c
+    nc = geom.get("nc_b")
+    if nc is not None:
+        nb = len(geom["bk_hi"])
+        r = np.arange(-nc, nc + 1)
+        a2 = (r * r)[:, None] + (r * r)[None, :]
+        npair = (n_field + 1) // 2
+        z = y = x = 0
+        for p in range(npair):
+            hp = max(geom["bk_hi"][f % nb] for f in (2 * p, 2 * p + 1) if f < n_field)
+            cols = int(np.sum(a2 <= hp))
+            nix = int(np.sum(r * r <= hp))
+            z += cols * M * c
+            y += cols * M * c + nix * M * M * c
+            x += nix * M * M * c + min(2, n_field - 2 * p) * M**3 * tb
+        nl = (npair + n_batch_pairs - 1) // n_batch_pairs
+        out["shell_z"], out["shell_y"], out["shell_x"] = z // nl, y // nl, x // nl
+        out["triple"] = n_field * M**3 * tb
+    return out
 
 
 def source_hash(kernel):
@@ -130,24 +226,55 @@ def run_steps(F, torch, plans, mocks, steps, timed: bool):
     return lat
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(wl, gal, ran, alpha, observer, M):
-    """FP64 oracle timed on a bounded sample of the same workload, scaled to one mock."""
+    """The FP64 oracle on this host's cores: the small 64^3 power-spectrum case
+    end to end, and the H512 stages timed on a bounded sample and scaled to
+    one mock.  The oracle's FFTs run with scipy workers on all cores (at most
+    16), its assignment loop (plain C, OpenMP) on OMP_NUM_THREADS threads;
+    the shell sums and triangle sums are single-threaded NumPy."""
+    from oracle import assign_c
     from oracle import estimator as est
+    from paper_1506_02729_amd import synth
+    import scipy.fft as sfft
+    assign_c.build()
+    nproc = os.cpu_count() or 1
+    fft_threads = est._WORKERS
+    omp_threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
     N = wl["n_mesh"]
     n_obj = len(gal["w"]) + len(ran["w"])
     t = {}
-    sample = 1_000_000
-    pos = ran["pos"][:sample]
-    u = pos / (wl["box"] / N)
+    # the small power-spectrum case, end to end (64^3 CIC, 2e4 + 1e5 objects)
+    g1, r1, a1, o1 = synth.tiny_survey(seed=1000)
+    kf1 = 2 * math.pi / 500.0
+    prm1 = est.Params(n_grid=64, box=500.0, observer=o1, order=2, interlace=False, compensate=True, ell_max=4,
+                      pk_kmin=0.0, pk_dk=2 * kf1, pk_nbins=16, assign=assign_c.assign_mesh)
+    t0 = time.perf_counter()
+    est.pk_multipoles(g1, r1, a1, prm1)
+    t["small_pk_64_end_to_end"] = time.perf_counter() - t0
+    # H512 stages
+    sample = 4_000_000
+    u = ran["pos"][:sample] / (wl["box"] / N)
     w = -alpha * ran["w"][:sample]
+    assign_c.assign_mesh(u, w, N, 3)
     t0 = time.perf_counter()
-    est.assign_mesh(u, w, N, 3)
-    t["grid_1moment_1e6obj"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
+    assign_c.assign_mesh(u, w, N, 3)
+    t["assign_1plane_4e6obj"] = time.perf_counter() - t0
     mesh = np.random.default_rng(0).standard_normal((N, N, N))
-    t1 = time.perf_counter()
-    np.fft.rfftn(mesh)
-    t["rfftn"] = time.perf_counter() - t1
+    t0 = time.perf_counter()
+    sfft.rfftn(mesh, workers=fft_threads)
+    t["rfftn_512"] = time.perf_counter() - t0
     del mesh
     prm = est.Params(n_grid=N, box=wl["box"], observer=observer, pk_kmin=0.0, pk_dk=wl["pk_dk"],
                      pk_nbins=wl["pk_nbins"])
@@ -155,7 +282,7 @@ def cpu_baseline(wl, gal, ran, alpha, observer, M):
               4: np.ones((N, N, N // 2 + 1), complex)}
     t0 = time.perf_counter()
     est.shell_sums(fields, prm, 0.0, wl["pk_dk"], wl["pk_nbins"])
-    t["bin"] = time.perf_counter() - t0
+    t["bin_60"] = time.perf_counter() - t0
     del fields
     bprm = est.Params(n_grid=N, box=wl["box"], observer=observer, bk_kmin=wl["bk_kmin"], bk_dk=wl["bk_dk"],
                       bk_nbins=wl["bk_nbins"])
@@ -166,19 +293,21 @@ def cpu_baseline(wl, gal, ran, alpha, observer, M):
     t["shell_ifft"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     for _ in range(3):
-        float(np.sum(f * f * f))
+        pair = f * f
+        float(np.sum(f * pair))
     t["triangle_sum"] = (time.perf_counter() - t0) / 3
     del f
     n_tri, n_ell, n_mom, n_fields = 5416, 3, 23, 111
-    per_mock = (t["grid_1moment_1e6obj"] * (n_obj / sample) * n_mom * 2 + t["rfftn"] * n_mom * 2 + t["bin"]
+    per_mock = (t["assign_1plane_4e6obj"] * (n_obj / sample) * n_mom * 2 + t["rfftn_512"] * n_mom * 2 + t["bin_60"]
                 + t["shell_ifft"] * n_fields + t["triangle_sum"] * n_tri * n_ell)
-    return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": 1, "kind": "oracle",
-            "seconds_per_mock": per_mock,
-            "sample": ("FP64 NumPy oracle stages timed once each on this host and scaled to one mock: TSC "
-                       "assignment of 1e6 randoms for one moment plane (x %.0f objects x 46 planes), one "
-                       "512^3 rfftn (x 46), the 60-bin shell sums of 3 multipoles, one %d^3 shell inverse "
-                       "FFT (x 111), one %d^3 triple-product sum (x 5416 triangles x 3 multipoles)"
-                       % (n_obj / sample, M, M)),
+    return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": max(fft_threads, omp_threads), "kind": "oracle",
+            "seconds_per_mock": per_mock, "nproc": nproc, "cpu_model": _cpu_model(),
+            "threads": {"fft": fft_threads, "assign": omp_threads, "bin": 1, "triangle_sum": 1},
+            "sample": ("FP64 oracle on this host: H512 stages timed once each and scaled to one mock -- TSC "
+                       "assignment of 4e6 randoms for one moment plane (x %.1f for all objects, x 46 planes), one "
+                       "512^3 rfftn (x 46), the 60-bin shell sums of 3 multipoles, one %d^3 shell inverse FFT "
+                       "(x 111), one %d^3 triangle sum (x 5416 triangles x 3 multipoles); plus the 64^3 CIC "
+                       "P_ell case of 2e4 + 1e5 objects end to end" % (n_obj / sample, M, M)),
             "stage_seconds": {k: round(v, 4) for k, v in t.items()}}
 
 
@@ -217,71 +346,95 @@ def oracle_check(F, torch, plan, mock0, gold_path):
     return res
 
 
-def open_loop(args, F, torch, synth, dev, log):
-    """Open-loop serving of requests of mixed mesh sizes: Poisson arrivals
-    (exponential gaps of mean --mean-gap s), N uniform in {256, 384, 512},
-    N_g uniform in [3e5, the pool size] and N_r = 50 N_g taken as prefixes of
-    shuffled pool catalogues resident in HBM, P_ell to min(0.3, k_Ny) in bins
-    of 0.005 and B_ell on 18 bins of 3 k_f (k <= 0.1).  Admission by HBM
-    footprint: every mesh size starts with one plan (workspace + stream); a
-    queued request takes a free plan of its size, or a new one when the
-    workspaces (exact sizes from the plan) stay within --hbm-budget-gb, or
-    waits.  Latency runs from arrival to the P_ell and B_ell arrays on the
-    host."""
+SERVE_SIZES = (256, 384, 512)
+
+
+def serving(args, F, torch, synth, dev, log):
+    """The served covariance workload: Poisson arrivals (exponential gaps of
+    mean --mean-gap s) of lognormal mocks of uneven size -- N_g uniform in
+    [3e5, 1.5e6], N_r = 50 N_g, taken as prefixes of shuffled pool catalogues
+    (two galaxy mocks of 1.5e6 and 7.5e7 randoms over the same survey),
+    with nbar and the FKP weight w = 1/(1 + nbar 1e4) rescaled to each
+    request's N_g -- on meshes of 256^3, 384^3 or 512^3 (uniform), P_ell
+    l = 0, 2, 4 to min(0.3, k_Nyquist) in bins of 0.005 and B_0 to k = 0.1
+    (18 bins of 3 k_f).  The loop admits requests by HBM footprint: a queued
+    request takes a free plan (workspace + stream) of its size, or a new one
+    while the workspaces (exact sizes from the plan) stay within
+    --hbm-budget-gb, or waits; requests in flight overlap on the device.
+    Latency runs from arrival to the P_ell and B_0 arrays on the host.
+    Compared with: the same requests one at a time on plain FP64 plans (a
+    sample per size), and each size's first request recomputed alone (FP32)
+    against its in-flight result."""
     from collections import deque
     box = 3500.0
     kf = 2 * math.pi / box
-    rng = np.random.Generator(np.random.PCG64(4000))
+    n_gal_pool, n_ran_pool = 1.5e6, 75_000_000
     t0 = time.perf_counter()
-    pool, ran, observer = synth.lognormal_pool(4, seed0=4100, n_mesh=512, box=box, n_gal=8.0e5, n_ran=40_000_000)
+    pool, ran, observer = synth.lognormal_pool(2, seed0=4100, n_mesh=512, box=box, n_gal=n_gal_pool,
+                                               n_ran=n_ran_pool)
+    vol = synth.survey_volume(1150.0, 1750.0, 60.0)
 
     def shuffled(c, seed):
         perm = np.random.Generator(np.random.PCG64(seed)).permutation(len(c["w"]))
         return {k: v[perm] for k, v in c.items()}
 
-    gals = [F.device_catalog(shuffled(g, 4200 + i), dev) for i, (g, _) in enumerate(pool)]
-    rand = F.device_catalog(shuffled(ran, 4300), dev)
-    ng_max = min(len(g["w"]) for g, _ in pool)
-    nr_all = len(ran["w"])
-    log(f"open loop: pool of {len(gals)} mocks, {ng_max}+ galaxies, {nr_all} randoms in {time.perf_counter() - t0:.1f} s")
-    sizes = (256, 384, 512)
+    gals = [torch.as_tensor(shuffled(g, 4200 + i)["pos"]).to(dev) for i, (g, _) in enumerate(pool)]
+    rand = torch.as_tensor(shuffled(ran, 4300)["pos"]).to(dev)
+    ng_max = min(int(g.shape[0]) for g in gals)
+    nr_all = int(rand.shape[0])
+    log(f"serving: pool of {len(gals)} mocks ({ng_max}+ galaxies), {nr_all} randoms in {time.perf_counter() - t0:.1f} s")
     plans, nbins, cfgs, ws_bytes = {}, {}, {}, {}
     budget = args.hbm_budget_gb * 1e9
-    for N in sizes:
+    for N in SERVE_SIZES:
         kny = math.pi * N / box
-        nbins[N] = min(60, int(math.floor(kny / 0.005 - 1e-9)))  # bins of 0.005 to min(0.3, k_Ny)
-        cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
-                       precision=32, pk_kmin=0.0, pk_dk=0.005, pk_nbins=nbins[N], bk_kmin=1.5 * kf, bk_dk=3 * kf,
-                       bk_nbins=18, max_objects=ng_max + nr_all)
-        cfgs[N] = cfg
-        h = F.frsd_plan_create(cfg.to_c())
+        nbins[N] = min(60, int(math.floor(kny / 0.005 - 1e-9)))
+        cfgs[N] = {p: F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True,
+                               ell_max=4, precision=p, pk_kmin=0.0, pk_dk=0.005, pk_nbins=nbins[N],
+                               bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=18, bk_ell_max=0,
+                               max_objects=ng_max + nr_all) for p in (32, 64)}
+        h = F.frsd_plan_create(cfgs[N][32].to_c())
         ws_bytes[N] = F.frsd_plan_workspace_bytes(h)
         F.frsd_plan_destroy(h)
-        plans[N] = [F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev))]
-    used = sum(ws_bytes[N] for N in sizes)
+        plans[N] = [F.Plan(cfgs[N][32], device=dev, stream=torch.cuda.Stream(dev))]
+    used = sum(ws_bytes[N] for N in SERVE_SIZES)
     if used > budget:
         raise SystemExit(f"--hbm-budget-gb {args.hbm_budget_gb} is below one workspace per size ({used / 1e9:.1f} GB)")
-    n = args.open_loop
+    rng = np.random.Generator(np.random.PCG64(4000))
+    n = args.serve_requests
     arrive = np.cumsum(rng.exponential(args.mean_gap, n))
-    n_of = rng.choice(np.array(sizes), n)
+    n_of = rng.choice(np.array(SERVE_SIZES), n)
     ng_of = rng.integers(300_000, ng_max + 1, n)
     mock_of = rng.integers(0, len(gals), n)
 
-    def submit(pl, k):
+    def catalogue(k, dtype=torch.float64):
+        """Device catalogue of request k: prefixes of the pool positions, nbar and
+        w rescaled to its galaxy count (constant over the survey)."""
         ng = int(ng_of[k])
         nr = min(50 * ng, nr_all)
-        g = {key: v[:ng] for key, v in gals[mock_of[k]].items()}
-        r = {key: v[:nr] for key, v in rand.items()}
-        pl.mesh_assign(g, r, ng / nr)
+        nbar = ng / vol
+        w = 1.0 / (1.0 + nbar * 1.0e4)
+        def cat(pos, m):
+            return {"pos": pos[:m].to(dtype), "w": torch.full((m,), w, dtype=dtype, device=dev),
+                    "nbar": torch.full((m,), nbar, dtype=dtype, device=dev)}
+        return cat(gals[mock_of[k]], ng), cat(rand, nr), ng / nr
+
+    def submit(pl, k):
+        g, r, a = catalogue(k)
+        pl.mesh_assign(g, r, a)
         pl.pk()
         pl.bk()
 
-    for N in sizes:  # one untimed request per plan: code objects loaded, tables resident
-        for pl in plans[N]:
-            submit(pl, 0)
+    def host_result(pl):
+        out = {key: pl.pk_buf[key].cpu().numpy().copy() for key in ("n_modes", "p0", "p2", "p4", "s00")}
+        out.update({"bk_" + key: pl.bk_buf[key].cpu().numpy().copy() for key in ("nt", "t0", "b0")})
+        return out
+
+    for N in SERVE_SIZES:  # one untimed request per plan: code objects loaded, tables resident
+        submit(plans[N][0], 0)
     torch.cuda.synchronize()
-    free = {id(pl): True for N in sizes for pl in plans[N]}
-    queue, inflight, lat, sizes_done = deque(), [], [], []
+    free = {id(pl): True for N in SERVE_SIZES for pl in plans[N]}
+    queue, inflight, lat, sizes_done, results = deque(), [], [], [], {}
+    keep = {int(np.nonzero(n_of == N)[0][0]) for N in SERVE_SIZES if np.any(n_of == N)}
     i = 0
     t0 = time.perf_counter()
     while i < n or queue or inflight:
@@ -292,17 +445,18 @@ def open_loop(args, F, torch, synth, dev, log):
         for rec in list(inflight):
             pl, ev, k = rec
             if ev.query():
-                host = [pl.pk_buf[key].cpu() for key in ("p0", "p2", "p4")]
-                host += [pl.bk_buf[key].cpu() for key in ("b0", "b2", "b4")]
+                res = host_result(pl)
                 lat.append(time.perf_counter() - t0 - arrive[k])
                 sizes_done.append(int(n_of[k]))
+                if k in keep:
+                    results[k] = res
                 inflight.remove(rec)
                 free[id(pl)] = True
-        for k in list(queue):  # admit every queued request that has (or may allocate) a plan of its size
+        for k in list(queue):
             N = int(n_of[k])
             pl = next((p for p in plans[N] if free[id(p)]), None)
             if pl is None and used + ws_bytes[N] <= budget:
-                pl = F.Plan(cfgs[N], device=dev, stream=torch.cuda.Stream(dev))
+                pl = F.Plan(cfgs[N][32], device=dev, stream=torch.cuda.Stream(dev))
                 plans[N].append(pl)
                 used += ws_bytes[N]
                 free[id(pl)] = True
@@ -316,25 +470,62 @@ def open_loop(args, F, torch, synth, dev, log):
             inflight.append((pl, ev, k))
         time.sleep(0.0002)
     elapsed = time.perf_counter() - t0
-    for N in sizes:
+    for N in SERVE_SIZES:
         for pl in plans[N]:
             assert pl.status() == 0
+    n_plans = {str(N): len(plans[N]) for N in SERVE_SIZES}
+    del plans
+    torch.cuda.empty_cache()
+
+    def max_rel(a, b, keys):
+        return float(max(np.max(np.abs(a[k] - b[k])) / max(np.max(np.abs(b[k])), 1e-300) for k in keys))
+
+    # each size's first request alone (FP32), against its in-flight result
+    alone = {}
+    for k in sorted(keep):
+        pl = F.Plan(cfgs[int(n_of[k])][32], device=dev)
+        submit(pl, k)
+        torch.cuda.synchronize()
+        ref = host_result(pl)
+        assert np.array_equal(ref["n_modes"], results[k]["n_modes"]) and np.array_equal(ref["bk_nt"], results[k]["bk_nt"])
+        alone[str(int(n_of[k]))] = max_rel(results[k], ref, ("p0", "p2", "p4", "bk_t0"))
+        del pl
+    # plain FP64, one request at a time: a sample of two requests per size
+    fp64_ms, fp64_err = [], {}
+    for N in SERVE_SIZES:
+        idx = np.nonzero(n_of == N)[0][:2]
+        if len(idx) == 0:
+            continue
+        pl64 = F.Plan(cfgs[N][64], device=dev)
+        submit(pl64, int(idx[0]))          # untimed: code objects loaded
+        torch.cuda.synchronize()
+        for k in idx:
+            t1 = time.perf_counter()
+            submit(pl64, int(k))
+            res64 = host_result(pl64)
+            fp64_ms.append(1e3 * (time.perf_counter() - t1))
+            if int(k) in results:
+                fp64_err[str(N)] = max_rel(results[int(k)], res64, ("p0", "p2", "p4", "bk_t0"))
+        del pl64
+        torch.cuda.empty_cache()
     lat_ms = 1e3 * np.asarray(lat)
     sz = np.asarray(sizes_done)
     per_size = {str(N): {"requests": int((sz == N).sum()), "p50_ms": float(np.percentile(lat_ms[sz == N], 50)),
-                         "p99_ms": float(np.percentile(lat_ms[sz == N], 99))} for N in sizes if (sz == N).any()}
-    out = {"metric": "open-loop request latency p99 (arrival to host result), mixed N in {256, 384, 512}",
-           "value": float(np.percentile(lat_ms, 99)), "unit": "ms", "higher_is_better": False, "n_gpus": 1,
-           "requests": n, "p50_ms": float(np.percentile(lat_ms, 50)), "mocks_per_s": n / elapsed,
-           "mean_gap_s": args.mean_gap, "hbm_budget_gb": args.hbm_budget_gb,
-           "plans_per_size": {str(N): len(plans[N]) for N in sizes}, "workspace_gb": used / 1e9, "per_size": per_size,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "open loop: lognormal pool (4 mocks, 8e5 galaxies, 4e7 randoms, 3500 Mpc/h box), "
-                                  "prefixes N_g in [3e5, pool], N_r = 50 N_g, P_ell l=0,2,4 to min(0.3, k_Ny), "
-                                  "B_ell l=0,2,4 on 18 bins of 3 k_f",
-                      "pk_bins": {str(N): nbins[N] for N in sizes}}}
-    print(json.dumps(out), flush=True)
-
+                         "p99_ms": float(np.percentile(lat_ms[sz == N], 99))} for N in SERVE_SIZES if (sz == N).any()}
+    return {"workload": "served covariance run: lognormal mocks, N_g uniform in [3e5, 1.5e6], N_r = 50 N_g, nbar and "
+                        "w rescaled per request, N uniform in {256, 384, 512}, Poisson arrivals, P_ell l=0,2,4 to "
+                        "min(0.3, k_Ny), B_0 on 18 bins of 3 k_f (k <= 0.1)",
+            "requests": n, "mean_gap_s": args.mean_gap, "mocks_per_s": n / elapsed,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "per_size": per_size, "hbm_budget_gb": args.hbm_budget_gb, "plans_per_size": n_plans,
+            "workspace_gb": used / 1e9, "pk_bins": {str(N): nbins[N] for N in SERVE_SIZES},
+            "alone_vs_in_flight_max_rel": alone,
+            "fp64_one_at_a_time": {"requests": len(fp64_ms),
+                                   "mocks_per_s": 1e3 / float(np.mean(fp64_ms)) if fp64_ms else None,
+                                   "p50_ms": float(np.percentile(fp64_ms, 50)) if fp64_ms else None,
+                                   "p99_ms": float(np.percentile(fp64_ms, 99)) if fp64_ms else None,
+                                   "fp32_vs_fp64_max_rel": fp64_err},
+            "dtype": "f32"}
 
 
 def main():
@@ -343,7 +534,7 @@ def main():
     ap.add_argument("--steps", type=int, default=64, help="requests served in the timed closed loop")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--fp64-steps", type=int, default=2)
-    ap.add_argument("--mocks", type=int, default=16, help="distinct mocks in the pool, cycled")
+    ap.add_argument("--mocks", type=int, default=8, help="distinct mocks in the pool, cycled")
     ap.add_argument("--streams", type=int, default=3,
                     help="requests in flight: one plan (workspace) and HIP stream each, default priority")
     ap.add_argument("--kernel-steps", type=int, default=8,
@@ -351,11 +542,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="256^3 workload for development runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--open-loop", type=int, default=0,
-                    help="instead of the closed loop: this many open-loop requests of mixed mesh sizes")
-    ap.add_argument("--mean-gap", type=float, default=0.5, help="open loop: mean inter-arrival time (s)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the served covariance run (Poisson arrivals, mixed mesh sizes); 0: skip it")
+    ap.add_argument("--serve-only", action="store_true", help="run only the served covariance run")
+    ap.add_argument("--mean-gap", type=float, default=0.5, help="served run: mean inter-arrival time (s)")
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0,
-                    help="open loop: device memory for plan workspaces (admission by footprint)")
+                    help="served run: device memory for plan workspaces (admission by footprint)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -377,8 +569,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    if args.open_loop > 0:
-        open_loop(args, F, torch, synth, dev, log)
+    if args.serve_only:
+        print(json.dumps(serving(args, F, torch, synth, dev, log)), flush=True)
         return
 
     # pool of distinct mocks sharing one random catalogue (a covariance run)
@@ -430,25 +622,45 @@ def main():
         F, torch, plan, (pool[0][0], ran, pool[0][1], observer, dev_mocks[0][0], r_dev),
         os.path.join(ROOT, "tests", "golden", "h512_golden.json"))
 
-    n_slot = 23
-    tbytes = 4
     M = plan.bk_grid
     assert f"M={M}" in wl["name"], (M, wl["name"])
     n_out = plan.ntri * 3
     ks = max(1, args.kernel_steps)
     n_obj_kern = float(np.mean([len(pool[i % len(pool)][0]["w"]) for i in range(ks)])) + len(ran["w"])
-    kernels = {k: {"launches": n, "total_ms": round(ms, 3), "avg_ms": round(ms / n, 4)} for k, (n, ms) in kern.items()}
+    geom = plan_geometry(cfg, M)
+    col, xm = live_masks([pool[0][0]["pos"], ran["pos"]], cfg.n_grid, cfg.box)
+    alg = algorithmic_traffic(geom, col, xm, n_obj_kern, 23, 3 * cfg.bk_nbins, 4)
+    mfma_flops = 6.0 * n_out * M**3      # three bf16 split products of 2 flops per listed output and cell
+    kernels = {}
+    for k, (n, ms) in kern.items():
+        avg = ms / n / 1e3
+        e = {"launches": n, "total_ms": round(ms, 3), "avg_ms": round(ms / n, 4)}
+        if k in alg:
+            e["alg_bytes"] = int(alg[k])
+            e["alg_GBps"] = round(alg[k] / avg / 1e9, 1)
+            e["alg_hbm_frac"] = round(alg[k] / avg / 1e9 / HBM_PEAK_GBS, 4)
+        ct = measured_traffic(k)
+        if ct:
+            e["counter_bytes"] = int(ct)
+            e["counter_hbm_frac"] = round(ct / avg / 1e9 / HBM_PEAK_GBS, 4)
+        if k == "triple":
+            e["mfma_TFLOPs"] = round(mfma_flops / avg / 1e12, 1)
+            e["mfma_frac"] = round(mfma_flops / avg / 1e12 / BF16_MFMA_PEAK_TFLOPS, 4)
+            e["fp32_equiv_frac"] = round(2.0 * n_out * M**3 / avg / 1e12 / FP32_VEC_PEAK_TFLOPS, 4)
+        kernels[k] = e
     dom = max(kern, key=lambda k: kern[k][1])
     n_launch, tot_ms = kern[dom]
     avg_s = tot_ms / n_launch / 1e3
-    bound, cost = algorithmic_cost(dom, cfg, n_obj_kern, n_slot, M, n_out, tbytes)
-    if cost is None:
-        bound = None
-    if bound == "hbm":
-        roof = {"kernel": dom, "bound": "hbm", "achieved": cost / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    elif bound == "mfma":
-        roof = {"kernel": dom, "bound": "mfma", "achieved": cost / avg_s / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
+    if dom == "triple":
+        roof = {"kernel": dom, "bound": "mfma", "achieved": mfma_flops / avg_s / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "flops_per_launch": mfma_flops,
+                "flops_rule": "6 x listed outputs (5416 triangles x 3 multipoles) x M^3: three bf16 hi/lo products "
+                              "of 2 flops per output and cell",
+                "fp32_equiv": {"achieved": 2.0 * n_out * M**3 / avg_s / 1e12, "peak": FP32_VEC_PEAK_TFLOPS,
+                               "unit": "TFLOP/s"}}
+    elif dom in alg:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": alg[dom] / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "bytes_per_launch": alg[dom]}
     else:
         roof = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None}
     if roof["achieved"] is not None:
@@ -490,6 +702,11 @@ def main():
         del plan64
         torch.cuda.empty_cache()
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args, F, torch, synth, dev, log)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, pool[0][0], ran, pool[0][1], observer, M)
@@ -510,11 +727,14 @@ def main():
         "config": {"workload": wl["name"], "requests": args.steps, "mocks_in_pool": len(pool),
                    "in_flight": nstream, "kernel_timing": f"{max(1, args.kernel_steps)} requests, one in flight",
                    "precision": "fp32 served (closed loop), fp64 plain (one mock at a time)"},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "note": "closed loop, enqueue to stream completion with --streams requests in flight; "
+                               "arrival-to-result latency of the served covariance run is in serving"},
         "roofline": roof,
         "kernels": kernels,
         "fp32_vs_oracle": gold,
         "fp64_plain": fp64,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
