@@ -84,6 +84,10 @@ typedef struct {
                             frsd_bk_multipoles, transformed to the bispectrum sphere) */
   int32_t bk_zero_area;  /* 1: also T_220 and the zero-area hexadecapole B4za of
                             Sec. II.C eq. (Bhexa2) (needs bk_ell_max >= 2)          */
+  int32_t random_cache;  /* 1: the workspace also holds the Fourier moment meshes of
+                            one random catalogue (frsd_random_cache), so that mocks
+                            sharing it run frsd_mesh_assign_cached on their galaxies
+                            alone (not with bk_shot_noise = 1)                      */
 } frsd_params;
 
 /* A catalogue in device memory.  pos is n x 3 interleaved (x, y, z);
@@ -154,6 +158,22 @@ int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *stream);
  * FRSD_ENOMEM if gal->n + ran->n > max_objects. */
 int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *gal,
                      const frsd_catalog *ran, double alpha, void *stream);
+
+/* Random-catalogue cache, for many mocks over one survey mask (the paper
+ * caches what depends only on the mask and grid, Sec. III.B; its randoms
+ * dominate the assignment time, Sec. III.C).  Needs a plan with
+ * random_cache = 1.  frsd_random_cache grids ran alone (weight +w for the
+ * 22 moments, w^2 for F_0^w), transforms it and keeps the spectra and the
+ * randoms' sums of nbar w^2, nbar^2 w^3, w^2, w^3 in ws.
+ * frsd_mesh_assign_cached then runs steps a1-a4 on the galaxies alone; the
+ * following frsd_pk_multipoles combines every mesh as F = F_gal - alpha
+ * F_ran (F_0^w: + alpha^2 F_ran^w), and I22, N_0, I33, W3 use the cached
+ * sums: the results are those of frsd_mesh_assign(gal, ran, alpha) up to
+ * rounding.  The cache stays valid until frsd_random_cache is called again
+ * or the workspace is initialised again.  Rejected randoms are counted by
+ * frsd_status after frsd_random_cache.  Asynchronous on `stream`. */
+int frsd_random_cache(frsd_plan *plan, void *ws, const frsd_catalog *ran, void *stream);
+int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_catalog *gal, double alpha, void *stream);
 
 /* Steps a5-a6: multipole combination and shell binning into P_0, P_2, P_4.
  * Requires a preceding frsd_mesh_assign on ws.  Also extracts the low-k

@@ -39,6 +39,8 @@ extern "C" int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *
   }
   plan->state = 1;
   plan->init_ws = ws;
+  plan->cache_ready = false;
+  plan->assigned_cached = false;
   return FRSD_OK;
 }
 
@@ -59,6 +61,46 @@ extern "C" int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *g
   else rc = run_mesh_assign<float>(plan, ws, gal, ran, alpha, s);
   if (rc) return rc;
   plan->state = 2;
+  plan->assigned_cached = false;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_random_cache(frsd_plan *plan, void *ws, const frsd_catalog *ran, void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (!plan->p.random_cache) return fail(FRSD_EINVAL, "plan was created without random_cache");
+  if (plan->state < 1 || plan->init_ws != ws) return fail(FRSD_ESTATE, "workspace not initialised by frsd_plan_init");
+  if ((rc = check_catalog(ran, true, "randoms"))) return rc;
+  if (ran->n > plan->p.max_objects) return fail(FRSD_ENOMEM, "randoms exceed max_objects of the plan");
+  if (ran->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->p.precision == FRSD_F64) rc = run_random_cache<double>(plan, ws, ran, s);
+  else rc = run_random_cache<float>(plan, ws, ran, s);
+  if (rc) return rc;
+  plan->cache_ready = true;
+  plan->state = 1;  // the mesh region holds no mock
+  return FRSD_OK;
+}
+
+extern "C" int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_catalog *gal, double alpha,
+                                       void *stream) {
+  clear_error();
+  int rc = check_ws(plan, ws);
+  if (rc) return rc;
+  if (!plan->cache_ready || plan->init_ws != ws)
+    return fail(FRSD_ESTATE, "frsd_mesh_assign_cached needs frsd_random_cache on this workspace first");
+  if ((rc = check_catalog(gal, false, "galaxies"))) return rc;
+  if (!std::isfinite(alpha)) return fail(FRSD_EINVAL, "alpha must be finite");
+  if (gal->n > plan->p.max_objects) return fail(FRSD_ENOMEM, "galaxies exceed max_objects of the plan");
+  if (gal->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan->p.precision == FRSD_F64) rc = run_mesh_assign_cached<double>(plan, ws, gal, alpha, s);
+  else rc = run_mesh_assign_cached<float>(plan, ws, gal, alpha, s);
+  if (rc) return rc;
+  plan->state = 2;
+  plan->assigned_cached = true;
+  plan->cached_alpha = alpha;
   return FRSD_OK;
 }
 
@@ -71,8 +113,8 @@ extern "C" int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *
       !out->s40 || !out->scalars)
     return fail(FRSD_EINVAL, "null output array");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (plan->p.precision == FRSD_F64) rc = run_pk<double>(plan, ws, out, s);
-  else rc = run_pk<float>(plan, ws, out, s);
+  if (plan->p.precision == FRSD_F64) rc = run_pk<double>(plan, ws, out, s, plan->assigned_cached);
+  else rc = run_pk<float>(plan, ws, out, s, plan->assigned_cached);
   if (rc) return rc;
   plan->state = 3;
   return FRSD_OK;

@@ -79,6 +79,7 @@ struct Layout {
   size_t bk_ctr = 0;                             // centre of every bispectrum bin, k_f units (double)
   size_t pair_tab_220 = 0, tri_sum220 = 0;       // pairs (F_2 b2, F_0 b3) and sums of T_220
   size_t tri_tab220 = 0;                         // vector-contraction outputs of T_220 (F_2 b1, F_2 b2, F_0 b3)
+  size_t rcache = 0, rcache_sums = 0;            // cached random spectra (mesh layout) and their sums
   size_t total = 0;
 };
 
@@ -126,6 +127,9 @@ struct frsd_plan {
   frsd::Layout L;
   int state = 0;                      // 0 created, 1 initialised, 2 assigned, 3 pk done
   void *init_ws = nullptr;
+  bool cache_ready = false;           // init_ws holds a random cache
+  bool assigned_cached = false;       // the last assignment used the random cache
+  double cached_alpha = 0;            // its alpha
   // Constant tables (twiddles, bin lookups, triangle and contraction tables),
   // built on the host once per plan and copied into a workspace at init.
   std::vector<unsigned char> tab_host;
@@ -188,8 +192,14 @@ inline T *ws_ptr(void *ws, size_t off) {
 template <typename T>
 int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
                     const frsd_catalog *ran, double alpha, hipStream_t s);
+// cached: the meshes hold galaxies alone, combined here with the random cache
 template <typename T>
-int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached);
+// random cache (grid.hip): spectra of the randoms alone; galaxies against it
+template <typename T>
+int run_random_cache(frsd_plan *pl, void *ws, const frsd_catalog *ran, hipStream_t s);
+template <typename T>
+int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, double alpha, hipStream_t s);
 int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s);
 // complete l > 0 shot noise: w^2-weighted moments (grid.hip), their sums (pk.hip)
 template <typename T>

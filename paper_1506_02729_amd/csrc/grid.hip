@@ -48,6 +48,8 @@ constexpr int kGStageBytes = 65536;         // staged object records (two workgr
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
                     hipStream_t s);
+void scal_keep(frsd_plan *pl, void *ws, hipStream_t s);
+void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s);
 
 // Floor cells that reach the main node i (at i) or the twin node (at i + 1/2),
 // relative to i: [LO, HI].
@@ -670,23 +672,60 @@ static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int
   }
 }
 
+// Assignment and forward transforms of the sorted records into the complex
+// meshes at mesh_off (the mesh region, or the random cache).
 template <typename T>
-int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
-                    hipStream_t s) {
-  int rc = ingest_and_sort<T>(pl, ws, gal, ran, alpha, s);
-  if (rc) return rc;
+static int grid_and_transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStream_t s) {
   const SlotDesc &sd = pl->slots;
   int n_ell_mom = 0, has_w = 0;
   for (int m = 0; m < sd.n_mom; ++m) {
     if (sd.mom_id[m] == kMomW) has_w = 1;
     else ++n_ell_mom;
   }
-  if ((rc = grid_order<T>(pl, ws, s, n_ell_mom, has_w, 0))) return rc;
+  int rc = grid_order<T>(pl, ws, s, n_ell_mom, has_w, 0);
+  if (rc) return rc;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
-                          ws_ptr<void>(ws, pl->L.mesh), pl->slots.n_slot, pl->nmax,
+                          ws_ptr<void>(ws, mesh_off), pl->slots.n_slot, pl->nmax,
                           std::max(pl->pk_lut_len, pl->p.bk_nbins > 0 ? pl->bk_lut_len : 0) - 1,
                           ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
 }
+
+template <typename T>
+int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
+                    hipStream_t s) {
+  int rc = ingest_and_sort<T>(pl, ws, gal, ran, alpha, s);
+  if (rc) return rc;
+  return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
+}
+
+// Random cache: the randoms alone with weight +w (ingested as "randoms" with
+// alpha = -1, so each record carries -alpha w = w), their moment meshes
+// transformed into the cache region and their raw sums kept.
+template <typename T>
+int run_random_cache(frsd_plan *pl, void *ws, const frsd_catalog *ran, hipStream_t s) {
+  const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
+  int rc = ingest_and_sort<T>(pl, ws, &none, ran, -1.0, s);
+  if (rc) return rc;
+  scal_keep(pl, ws, s);
+  return grid_and_transform<T>(pl, ws, pl->L.rcache, s);
+}
+
+// Galaxies alone against the random cache: their meshes into the mesh
+// region (the binning combines them with the cached ones), and the scalar
+// sums folded with the cached random sums for this alpha.
+template <typename T>
+int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, double alpha, hipStream_t s) {
+  const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
+  int rc = ingest_and_sort<T>(pl, ws, gal, &none, alpha, s);
+  if (rc) return rc;
+  scal_cached(pl, ws, alpha, s);
+  return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
+}
+
+template int run_random_cache<float>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
+template int run_random_cache<double>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
+template int run_mesh_assign_cached<float>(frsd_plan *, void *, const frsd_catalog *, double, hipStream_t);
+template int run_mesh_assign_cached<double>(frsd_plan *, void *, const frsd_catalog *, double, hipStream_t);
 
 // The w^2-weighted moment meshes of F^w_2, F^w_4 (Sec. III.B, the definition
 // of F^w_l below eq. SNbisp2): the first n_wmom moments gridded again from

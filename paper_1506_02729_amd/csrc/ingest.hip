@@ -144,6 +144,32 @@ __global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk
   }
 }
 
+// Random cache: keep the randoms' raw sums (columns 2-5: nbar w^2, nbar^2 w^3,
+// w^2, w^3) at cache time; for a cached assignment, fold them with the
+// galaxies' sums (columns 0-1) into I22, N_0, I33, W3 for this alpha.
+__global__ void k_scal_keep(const double *scal, double *keep) {
+  if (threadIdx.x < 4) keep[threadIdx.x] = scal[6 + threadIdx.x];
+}
+__global__ void k_scal_cached(const double *keep, double alpha, double *scal) {
+  if (threadIdx.x != 0) return;
+  const double g0 = scal[4], g1 = scal[5];
+  scal[0] = alpha * keep[0];
+  scal[1] = g0 + alpha * alpha * keep[2];
+  scal[2] = alpha * keep[1];
+  scal[3] = g1 - alpha * alpha * alpha * keep[3];
+  for (int k = 0; k < 4; ++k) scal[6 + k] = keep[k];
+}
+
+void scal_keep(frsd_plan *pl, void *ws, hipStream_t s) {
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_keep, dim3(1), dim3(64), 0, s, ws_ptr<const double>(ws, pl->L.scal),
+                                              ws_ptr<double>(ws, pl->L.rcache_sums)));
+}
+void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s) {
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_cached, dim3(1), dim3(64), 0, s,
+                                              ws_ptr<const double>(ws, pl->L.rcache_sums), alpha,
+                                              ws_ptr<double>(ws, pl->L.scal)));
+}
+
 // ---------------------------------------------------------------------------
 // Exclusive scan of int32 counts, in place (three kernels).
 // ---------------------------------------------------------------------------

@@ -33,6 +33,10 @@ struct BinArgs {
   int nc_b, D;  // low-k cube
   int n_slot, n_ell, has_w;
   double kf;
+  // random cache: slot s is Z_gal + cx[s] X_ran + i cy[s] Y_ran, with X_ran and
+  // Y_ran the real-plane spectra of the cached slot (cx = cy: one factor)
+  int cached;
+  double cx[kMaxSlots], cy[kMaxSlots];
 };
 
 // Sum v[NV] over every run of equal keys among consecutive lanes (a
@@ -127,7 +131,7 @@ template <typename T, bool GEOM, bool IL, bool WP = false>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict__ mesh, long long slot_stride,
                                                       BinArgs a, const int16_t *__restrict__ pk_lut,
                                                       const int16_t *__restrict__ bk_lut, cplx_t<T> *lowk,
-                                                      double *part) {
+                                                      double *part, const cplx_t<T> *__restrict__ rcache) {
   using C = cplx_t<T>;
   constexpr int NV = BinValues<GEOM>::n;
   __shared__ double bins[kMaxBinsAll * NV];
@@ -198,6 +202,19 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         if (sl < a.n_slot) {
           zp[sl] = mesh[sl * slot_stride + gp];
           zm[sl] = mesh[sl * slot_stride + gm];
+        }
+      }
+      if (!GEOM && !WP && a.cached) {
+        // F = F_gal + c F_ran per real plane: c X_ran(n) + i c' Y_ran(n) =
+        // (c + c')/2 Z_ran(n) + (c - c')/2 Z_ran(-n)^*
+#pragma unroll
+        for (int sl = 0; sl < kMaxSlots; ++sl) {
+          if (sl < a.n_slot) {
+            const C rp = rcache[sl * slot_stride + gp], rm = rcache[sl * slot_stride + gm];
+            const T ca = (T)(0.5 * (a.cx[sl] + a.cy[sl])), cb = (T)(0.5 * (a.cx[sl] - a.cy[sl]));
+            zp[sl] = cadd(zp[sl], cadd(cscale(rp, ca), cscale(cmake<C>(rm.x, -rm.y), cb)));
+            zm[sl] = cadd(zm[sl], cadd(cscale(rm, ca), cscale(cmake<C>(rp.x, -rp.y), cb)));
+          }
         }
       }
       const T ik = (T)(1.0 / sqrt((double)m2));
@@ -381,7 +398,8 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
                                                (const float2 *)nullptr, 0LL, a,
                                                ws_ptr<const int16_t>(ws, L.pk_lut),
                                                p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
-                                               (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part)));
+                                               (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part),
+                                               (const float2 *)nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));  // geometry
@@ -390,13 +408,25 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
 }
 
 template <typename T>
-int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
+int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached) {
   const Layout &L = pl->L;
   const frsd_params &p = pl->p;
   const int nall = p.pk_nbins + p.bk_nbins;
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
-  const BinArgs a = bin_args(pl);
+  BinArgs a = bin_args(pl);
   if (a.nmax >= kBinTab) return fail(FRSD_EINVAL, "k range too large for the binning tables");
+  if (cached) {
+    // factor of each moment position: -alpha (the moments of eqs. F0, Qab),
+    // +alpha^2 (the w^2 weights of F_0^w)
+    const SlotDesc &sd = pl->slots;
+    const double al = pl->cached_alpha;
+    auto coef = [&](int pos) { return pos < 0 || pos >= sd.n_mom ? 0.0 : (sd.mom_id[pos] == kMomW ? al * al : -al); };
+    a.cached = 1;
+    for (int sl = 0; sl < sd.n_slot; ++sl) {
+      a.cx[sl] = coef(sd.re_mom[sl]);
+      a.cy[sl] = coef(sd.im_mom[sl]);
+    }
+  }
   if (!slot_layout_ok(pl->slots, a, p.interlace != 0)) return fail(FRSD_EINVAL, "unexpected slot layout");
   using C = cplx_t<T>;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
@@ -406,7 +436,8 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
                                           NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                           p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                           p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr,
-                                          ws_ptr<double>(ws, L.bin_part)));
+                                          ws_ptr<double>(ws, L.bin_part),
+                                          a.cached ? ws_ptr<const C>(ws, L.rcache) : nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
@@ -417,8 +448,8 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
   return FRSD_OK;
 }
 
-template int run_pk<float>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t);
-template int run_pk<double>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t);
+template int run_pk<float>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t, bool);
+template int run_pk<double>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t, bool);
 
 // Q_lw = sum_b Re[F_0 (F^w_l)^*] (l = 2, 4) of every bispectrum bin from the
 // w^2-weighted moment meshes of run_w_moments (the q_2, q_3 terms of Sec. III.B
@@ -440,7 +471,7 @@ int run_bin_w(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_TIMED("bin_w", s, hipLaunchKernelGGL(kern, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
                                             NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                             ws_ptr<const int16_t>(ws, L.bk_lut), ws_ptr<C>(ws, L.lowk),
-                                            ws_ptr<double>(ws, L.bin_part)));
+                                            ws_ptr<double>(ws, L.bin_part), (const C *)nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
                                                  p.pk_nbins, 2, ws_ptr<double>(ws, L.bin_sum)));

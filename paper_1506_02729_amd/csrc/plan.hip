@@ -132,6 +132,9 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (p.bk_shot_noise != 0 && p.bk_shot_noise != 1) return fail(FRSD_EINVAL, "bk_shot_noise must be 0 or 1");
   if (p.bk_zero_area != 0 && p.bk_zero_area != 1) return fail(FRSD_EINVAL, "bk_zero_area must be 0 or 1");
   if (p.bk_zero_area && bk_ell < 2) return fail(FRSD_EINVAL, "bk_zero_area needs the quadrupole (bk_ell_max >= 2)");
+  if (p.random_cache != 0 && p.random_cache != 1) return fail(FRSD_EINVAL, "random_cache must be 0 or 1");
+  if (p.random_cache && p.bk_shot_noise && p.bk_nbins > 0)
+    return fail(FRSD_EINVAL, "random_cache does not combine with bk_shot_noise (its second pass grids every object)");
 
   frsd_plan *pl = new frsd_plan();
   pl->p = p;
@@ -224,6 +227,10 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));
   L.mesh = take(2 * T * NNN * sd.n_slot);
+  if (p.random_cache) {
+    L.rcache = take(2 * T * NNN * sd.n_slot);
+    L.rcache_sums = take(8 * 4);
+  }
   L.planar = take(2 * T * NNN * sd.n_slot);
   const int nbins_all = p.pk_nbins + p.bk_nbins;
   L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kBinBlocks);

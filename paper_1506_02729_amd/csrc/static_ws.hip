@@ -80,7 +80,7 @@ extern "C" int frsd_run_static(frsd_plan *plan, const frsd_catalog *gal, const f
   if ((rc = f64 ? run_mesh_assign<double>(plan, ws, gal, ran, alpha, s)
                 : run_mesh_assign<float>(plan, ws, gal, ran, alpha, s)))
     return rc;
-  if ((rc = f64 ? run_pk<double>(plan, ws, pk, s) : run_pk<float>(plan, ws, pk, s))) return rc;
+  if ((rc = f64 ? run_pk<double>(plan, ws, pk, s, false) : run_pk<float>(plan, ws, pk, s, false))) return rc;
   if (do_bk && (rc = f64 ? run_bk<double>(plan, ws, bk, s) : run_bk<float>(plan, ws, bk, s))) return rc;
   return FRSD_OK;
 }

@@ -48,6 +48,7 @@ class frsd_params(ctypes.Structure):
         ("bk_kmin", ctypes.c_double), ("bk_dk", ctypes.c_double), ("bk_nbins", ctypes.c_int32),
         ("bk_grid", ctypes.c_int32), ("max_objects", ctypes.c_int64),
         ("bk_ell_max", ctypes.c_int32), ("bk_shot_noise", ctypes.c_int32), ("bk_zero_area", ctypes.c_int32),
+        ("random_cache", ctypes.c_int32),
     ]
 
 
@@ -74,6 +75,8 @@ _proto = {
     "frsd_plan_init": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "frsd_mesh_assign": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
                                         ctypes.c_double, _P]),
+    "frsd_random_cache": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), _P]),
+    "frsd_mesh_assign_cached": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.c_double, _P]),
     "frsd_pk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_pk_out), _P]),
     "frsd_bk_ntriangles": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "frsd_bk_grid": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -127,6 +130,14 @@ def frsd_plan_init(plan: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
 
 def frsd_mesh_assign(plan, ws_ptr, gal: frsd_catalog, ran: frsd_catalog, alpha: float, stream) -> None:
     _check(_lib.frsd_mesh_assign(plan, ws_ptr, ctypes.byref(gal), ctypes.byref(ran), float(alpha), stream))
+
+
+def frsd_random_cache(plan, ws_ptr, ran: frsd_catalog, stream) -> None:
+    _check(_lib.frsd_random_cache(plan, ws_ptr, ctypes.byref(ran), stream))
+
+
+def frsd_mesh_assign_cached(plan, ws_ptr, gal: frsd_catalog, alpha: float, stream) -> None:
+    _check(_lib.frsd_mesh_assign_cached(plan, ws_ptr, ctypes.byref(gal), float(alpha), stream))
 
 
 def frsd_pk_multipoles(plan, ws_ptr, out: frsd_pk_out, stream) -> None:
@@ -208,6 +219,7 @@ class Config:
     bk_ell_max: int = -1
     bk_shot_noise: bool = False
     bk_zero_area: bool = False
+    random_cache: bool = False
 
     def to_c(self) -> frsd_params:
         p = frsd_params()
@@ -220,6 +232,7 @@ class Config:
         p.bk_kmin, p.bk_dk, p.bk_nbins = self.bk_kmin, self.bk_dk, self.bk_nbins
         p.bk_grid, p.max_objects = self.bk_grid, int(self.max_objects)
         p.bk_ell_max, p.bk_shot_noise, p.bk_zero_area = self.bk_ell_max, int(self.bk_shot_noise), int(self.bk_zero_area)
+        p.random_cache = int(self.random_cache)
         return p
 
 
@@ -301,6 +314,26 @@ class Plan:
         self._gal, self._ran = gal, (ran if ran is not None else empty)  # keep alive while queued
         frsd_mesh_assign(self.handle, self.ws_ptr, _c_catalog(self._gal), _c_catalog(self._ran), alpha,
                          self.stream.cuda_stream)
+
+    def random_cache(self, ran: dict) -> None:
+        """Grid, transform and keep the random catalogue (plans with random_cache)."""
+        self._ran = ran
+        frsd_random_cache(self.handle, self.ws_ptr, _c_catalog(ran), self.stream.cuda_stream)
+
+    def mesh_assign_cached(self, gal: dict, alpha: float) -> None:
+        self._gal = gal
+        frsd_mesh_assign_cached(self.handle, self.ws_ptr, _c_catalog(gal), alpha, self.stream.cuda_stream)
+
+    def run_cached(self, gal: dict, alpha: float, bispectrum: bool | None = None) -> dict:
+        """mesh_assign_cached + pk (+ bk); synchronises and returns host NumPy arrays."""
+        self.mesh_assign_cached(gal, alpha)
+        out = {k: v for k, v in self.pk().items()}
+        if (bispectrum is None and self.ntri) or bispectrum:
+            out.update({"bk_" + k: v for k, v in self.bk().items()})
+        rej = self.status()
+        if rej:
+            raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
+        return {k: v.cpu().numpy() for k, v in out.items()}
 
     def pk(self) -> dict:
         o = frsd_pk_out()

@@ -223,3 +223,45 @@ def test_bispectrum_monopole_only(gpu_lib, precision):
     assert np.max(e) < tol
     for key in ("bk_t2", "bk_t4", "bk_b2", "bk_b4", "bk_sn2", "bk_sn4"):
         assert np.all(np.isnan(out[key])), key
+
+
+@pytest.mark.parametrize("precision,N,interlace,ell_max", [(32, 64, True, 4), (64, 48, True, 4),
+                                                           (32, 48, False, 2), (64, 48, False, 4)])
+def test_random_cache(gpu_lib, precision, N, interlace, ell_max):
+    """Plans with random_cache: the randoms gridded and transformed once
+    (frsd_random_cache), then two galaxy catalogues with different alpha
+    against them (frsd_mesh_assign_cached): P_ell and B_ell as the oracle's
+    for galaxies + randoms, and as the uncached path on the same plan
+    (within 1e-5 of the largest value for FP32, 1e-11 for FP64).  Without
+    interlacing and with ell_max = 2 one slot pairs a moment plane (factor
+    -alpha) with the w^2 plane (factor +alpha^2)."""
+    import torch
+    _log(f"case: random cache N={N} interlace={interlace} ell_max={ell_max} precision={precision}")
+    dev = torch.device("cuda:0")
+    gal, ran, alpha, prm = _bk_case(151, N=N, interlace=interlace, ell_max=ell_max, n_gal=4000, n_ran=20000)
+    gal2 = _bk_case(152, N=N, n_gal=2500, n_ran=20000)[0]
+    cfg = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    cfg.random_cache = True
+    plan = gpu_lib.Plan(cfg, device=dev)
+    r = gpu_lib.device_catalog(ran, dev)
+    plan.random_cache(r)
+    assert plan.status() == 0
+    close = 1e-5 if precision == 32 else 1e-11
+    for g_host, a in ((gal, alpha), (gal2, 2500 / 20000)):
+        g = gpu_lib.device_catalog(g_host, dev)
+        out = plan.run_cached(g, a)
+        refp, refb = _oracle(g_host, ran, a, prm)
+        _check_pk(out, refp, prm, precision)
+        _check_bk(out, refb, prm, precision, plan)
+        plain = gpu_lib.Plan(_cfg(gpu_lib, prm, precision, len(g_host["w"]) + len(ran["w"])), device=dev).run(g, r, a)
+        for key in ("p0", "p2", "p4", "p4b", "s00", "bk_t0", "bk_t2", "bk_t4", "bk_sn0"):
+            if np.all(np.isnan(plain[key])):
+                continue
+            scale = np.nanmax(np.abs(plain[key]))
+            assert np.nanmax(np.abs(out[key] - plain[key])) <= close * scale, key
+        np.testing.assert_allclose(out["scalars"], plain["scalars"], rtol=1e-12)
+    # a plain assignment on the same workspace leaves the cache usable
+    out_plain = plan.run(gpu_lib.device_catalog(gal, dev), r, alpha)
+    out_again = plan.run_cached(gpu_lib.device_catalog(gal, dev), alpha)
+    scale = np.max(np.abs(out_plain["p0"]))
+    assert np.max(np.abs(out_again["p0"] - out_plain["p0"])) <= close * scale
