@@ -217,6 +217,24 @@ int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *
 int frsd_run_static(frsd_plan *plan, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
                     const frsd_pk_out *pk, const frsd_bk_out *bk, void *stream);
 
+/* A request captured as a HIP graph (serving loops that replay one plan):
+ * frsd_graph_create records every kernel of frsd_mesh_assign,
+ * frsd_pk_multipoles and (bk non-NULL, plan with bispectrum bins)
+ * frsd_bk_multipoles for these catalogue buffers, outputs and workspace on
+ * `stream` (non-null; stream capture, so nothing runs then) and
+ * instantiates it.  The catalogue sizes given here are capacities: the
+ * ingest kernels read N_g, N_r and alpha from device memory, which
+ * frsd_graph_launch sets (with a kernel, not a copy) before each replay, so a
+ * replay takes the first n_gal / n_ran objects of the same buffers with any
+ * contents.  Replays on one workspace must be ordered on one stream, as any
+ * call.  The graph owns no device memory; destroy it before the plan or the
+ * workspace.  FRSD_ESTATE while frsd_profile is on. */
+typedef struct frsd_graph frsd_graph;
+int frsd_graph_create(frsd_plan *plan, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
+                      const frsd_pk_out *pk, const frsd_bk_out *bk, void *stream, frsd_graph **graph);
+int frsd_graph_launch(frsd_graph *graph, int64_t n_gal, int64_t n_ran, double alpha, void *stream);
+void frsd_graph_destroy(frsd_graph *graph);
+
 /* Synchronises `stream` and reports the number of objects rejected by the
  * last frsd_mesh_assign (outside [0, L)^3 or at the observer).  Returns
  * FRSD_EDOM when that number is non-zero. */

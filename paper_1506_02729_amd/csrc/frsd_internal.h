@@ -80,6 +80,7 @@ struct Layout {
   size_t pair_tab_220 = 0, tri_sum220 = 0;       // pairs (F_2 b2, F_0 b3) and sums of T_220
   size_t tri_tab220 = 0;                         // vector-contraction outputs of T_220 (F_2 b1, F_2 b2, F_0 b3)
   size_t rcache = 0, rcache_sums = 0;            // cached random spectra (mesh layout) and their sums
+  size_t dyn = 0;                                // {N_g, N_r, alpha} of graph replays (double)
   size_t total = 0;
 };
 
@@ -189,9 +190,11 @@ inline T *ws_ptr(void *ws, size_t off) {
 }
 
 // launch wrappers (defined in the .hip translation units) --------------------
+// dyn (may be null): device {N_g, N_r, alpha} read by the ingest kernels in
+// place of the catalogue sizes and alpha (graph replays)
 template <typename T>
 int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
-                    const frsd_catalog *ran, double alpha, hipStream_t s);
+                    const frsd_catalog *ran, double alpha, hipStream_t s, const double *dyn = nullptr);
 // cached: the meshes hold galaxies alone, combined here with the random cache
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached);

@@ -47,7 +47,7 @@ constexpr int kGStageBytes = 65536;         // staged object records (two workgr
 
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
-                    hipStream_t s);
+                    hipStream_t s, const double *dyn);
 void scal_keep(frsd_plan *pl, void *ws, hipStream_t s);
 void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s);
 
@@ -692,8 +692,8 @@ static int grid_and_transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStrea
 
 template <typename T>
 int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
-                    hipStream_t s) {
-  int rc = ingest_and_sort<T>(pl, ws, gal, ran, alpha, s);
+                    hipStream_t s, const double *dyn) {
+  int rc = ingest_and_sort<T>(pl, ws, gal, ran, alpha, s, dyn);
   if (rc) return rc;
   return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
 }
@@ -704,7 +704,7 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
 template <typename T>
 int run_random_cache(frsd_plan *pl, void *ws, const frsd_catalog *ran, hipStream_t s) {
   const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
-  int rc = ingest_and_sort<T>(pl, ws, &none, ran, -1.0, s);
+  int rc = ingest_and_sort<T>(pl, ws, &none, ran, -1.0, s, nullptr);
   if (rc) return rc;
   scal_keep(pl, ws, s);
   return grid_and_transform<T>(pl, ws, pl->L.rcache, s);
@@ -716,7 +716,7 @@ int run_random_cache(frsd_plan *pl, void *ws, const frsd_catalog *ran, hipStream
 template <typename T>
 int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, double alpha, hipStream_t s) {
   const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
-  int rc = ingest_and_sort<T>(pl, ws, gal, &none, alpha, s);
+  int rc = ingest_and_sort<T>(pl, ws, gal, &none, alpha, s, nullptr);
   if (rc) return rc;
   scal_cached(pl, ws, alpha, s);
   return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
@@ -747,8 +747,8 @@ template int run_w_moments<float>(frsd_plan *, void *, hipStream_t);
 template int run_w_moments<double>(frsd_plan *, void *, hipStream_t);
 
 template int run_mesh_assign<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
-                                    hipStream_t);
+                                    hipStream_t, const double *);
 template int run_mesh_assign<double>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
-                                     hipStream_t);
+                                     hipStream_t, const double *);
 
 }  // namespace frsd

@@ -63,11 +63,22 @@ __device__ void block_sum4(double v0, double v1, double v2, double v3, double *p
 
 // Pass 1.  Galaxies write partial columns 0,1 (sum w^2, sum w^3); randoms
 // write columns 2..5 (sum nbar w^2, sum nbar^2 w^3, sum w^2, sum w^3).
+// dyn (graph replays, may be null): {N_g, N_r, alpha} in device memory,
+// which then replace the launch's n and offset (and alpha below).
+__device__ __forceinline__ void dyn_sizes(const double *dyn, int is_ran, long long &n, long long &obj_off) {
+  if (dyn) {
+    n = (long long)dyn[is_ran ? 1 : 0];
+    obj_off = is_ran ? (long long)dyn[0] : 0;
+  }
+}
+
 template <typename TIN>
 __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const TIN *w, const TIN *nbar,
                                                            long long n, int is_ran, long long obj_off,
                                                            GeomArgs g, int *cnt, int *slot, int *cellkey,
-                                                           double *part, unsigned long long *reject) {
+                                                           double *part, unsigned long long *reject,
+                                                           const double *dyn) {
+  dyn_sizes(dyn, is_ran, n, obj_off);
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -101,7 +112,9 @@ template <typename TIN, typename T>
 __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, const TIN *w, long long n, int is_ran,
                                                              long long obj_off, double alpha, GeomArgs g,
                                                              const int *offs, const int *slot, const int *cellkey,
-                                                             Rec4<T> *rec) {
+                                                             Rec4<T> *rec, const double *dyn) {
+  dyn_sizes(dyn, is_ran, n, obj_off);
+  if (dyn) alpha = dyn[2];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const int cell = cellkey[obj_off + i];
@@ -127,7 +140,9 @@ __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, cons
 // I33 = alpha S_r[nbar^2 w^3], W3 = S_g[w^3] - alpha^3 S_r[w^3].
 // One wavefront per partial column (6 columns, 384 threads), then the
 // scalars.
-__global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk, double alpha, double *scal) {
+__global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk, double alpha, double *scal,
+                                                    const double *dyn) {
+  if (dyn) alpha = dyn[2];
   __shared__ double col[6];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double s = 0;
@@ -271,28 +286,28 @@ __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const in
 // ---------------------------------------------------------------------------
 template <typename TIN>
 static void launch_count(const frsd_catalog *c, int is_ran, long long off, const GeomArgs &g, void *ws,
-                         const frsd_plan *pl, hipStream_t s) {
+                         const frsd_plan *pl, hipStream_t s, const double *dyn) {
   const Layout &L = pl->L;
   FRSD_TIMED("count", s, hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
                      (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
                      ws_ptr<double>(ws, L.scal_part),
-                     ws_ptr<unsigned long long>(ws, L.reject)));
+                     ws_ptr<unsigned long long>(ws, L.reject), dyn));
 }
 
 template <typename TIN, typename T>
 static void launch_scatter(const frsd_catalog *c, int is_ran, long long off, double alpha, const GeomArgs &g,
-                           void *ws, const frsd_plan *pl, hipStream_t s) {
+                           void *ws, const frsd_plan *pl, hipStream_t s, const double *dyn) {
   const Layout &L = pl->L;
   FRSD_TIMED("scatter", s, hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
                      (const TIN *)c->pos, (const TIN *)c->w, (long long)c->n, is_ran, off, alpha, g,
                      ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<Rec4<T>>(ws, L.sorted)));
+                     ws_ptr<Rec4<T>>(ws, L.sorted), dyn));
 }
 
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
-                    hipStream_t s) {
+                    hipStream_t s, const double *dyn) {
   const Layout &L = pl->L;
   const int N = pl->N;
   const long long ncell = (long long)N * N * N;
@@ -303,8 +318,8 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   const frsd_catalog *cats[2] = {gal, ran};
   long long off = 0;
   for (int k = 0; k < 2; ++k) {
-    if (cats[k]->dtype == FRSD_F64) launch_count<double>(cats[k], k, off, g, ws, pl, s);
-    else launch_count<float>(cats[k], k, off, g, ws, pl, s);
+    if (cats[k]->dtype == FRSD_F64) launch_count<double>(cats[k], k, off, g, ws, pl, s, dyn);
+    else launch_count<float>(cats[k], k, off, g, ws, pl, s, dyn);
     off += cats[k]->n;
   }
   FRSD_LAUNCH_CHECK();
@@ -315,19 +330,19 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
   FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk)));
   off = 0;
   for (int k = 0; k < 2; ++k) {
-    if (cats[k]->dtype == FRSD_F64) launch_scatter<double, T>(cats[k], k, off, alpha, g, ws, pl, s);
-    else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s);
+    if (cats[k]->dtype == FRSD_F64) launch_scatter<double, T>(cats[k], k, off, alpha, g, ws, pl, s, dyn);
+    else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s, dyn);
     off += cats[k]->n;
   }
   FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(384), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
-                     ws_ptr<double>(ws, L.scal)));
+                     ws_ptr<double>(ws, L.scal), dyn));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template int ingest_and_sort<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
-                                    hipStream_t);
+                                    hipStream_t, const double *);
 template int ingest_and_sort<double>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
-                                     hipStream_t);
+                                     hipStream_t, const double *);
 
 }  // namespace frsd

@@ -218,6 +218,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.scal_part = take(8 * 6 * kIngestBlocks);
   L.scal = take(8 * 16);
   L.reject = take(8);
+  L.dyn = take(8 * 4);
   L.cnt = take(4 * (NNN + 1));
   L.scan_blk = take(4 * ((NNN + 1 + 4095) / 4096 + 1));
   L.colmask = take((size_t)N * N);

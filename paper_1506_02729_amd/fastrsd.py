@@ -84,6 +84,11 @@ _proto = {
     "frsd_bk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_bk_out), _P]),
     "frsd_run_static": (ctypes.c_int, [_P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
                                        ctypes.c_double, ctypes.POINTER(frsd_pk_out), ctypes.POINTER(frsd_bk_out), _P]),
+    "frsd_graph_create": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
+                                         ctypes.c_double, ctypes.POINTER(frsd_pk_out), ctypes.POINTER(frsd_bk_out),
+                                         _P, ctypes.POINTER(_P)]),
+    "frsd_graph_launch": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _P]),
+    "frsd_graph_destroy": (None, [_P]),
     "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "frsd_profile": (ctypes.c_int, [ctypes.c_int]),
     "frsd_profile_report": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -171,6 +176,22 @@ def frsd_run_static(plan, gal: frsd_catalog, ran: frsd_catalog, alpha: float, pk
                     bk: frsd_bk_out | None, stream) -> None:
     _check(_lib.frsd_run_static(plan, ctypes.byref(gal), ctypes.byref(ran), float(alpha), ctypes.byref(pk),
                                 ctypes.byref(bk) if bk is not None else None, stream))
+
+
+def frsd_graph_create(plan, ws_ptr, gal: frsd_catalog, ran: frsd_catalog, alpha: float, pk: frsd_pk_out,
+                      bk: frsd_bk_out | None, stream) -> int:
+    h = _P()
+    _check(_lib.frsd_graph_create(plan, ws_ptr, ctypes.byref(gal), ctypes.byref(ran), float(alpha), ctypes.byref(pk),
+                                  ctypes.byref(bk) if bk is not None else None, stream, ctypes.byref(h)))
+    return h.value
+
+
+def frsd_graph_launch(graph: int, n_gal: int, n_ran: int, alpha: float, stream) -> None:
+    _check(_lib.frsd_graph_launch(graph, int(n_gal), int(n_ran), float(alpha), stream))
+
+
+def frsd_graph_destroy(graph: int) -> None:
+    _lib.frsd_graph_destroy(graph)
 
 
 def frsd_status(plan, ws_ptr, stream) -> int:
@@ -349,6 +370,19 @@ class Plan:
         frsd_bk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
         return self.bk_buf
 
+    def capture(self, gal: dict, ran: dict, alpha: float, bispectrum: bool = True) -> "Graph":
+        """Capture one request on this plan's stream into a HIP graph.  gal and ran
+        are the (capacity-sized) device buffers the replays read."""
+        po, bo = frsd_pk_out(), frsd_bk_out()
+        for name, _ in frsd_pk_out._fields_:
+            setattr(po, name, self.pk_buf[name].data_ptr())
+        for name, _ in frsd_bk_out._fields_:
+            setattr(bo, name, self.bk_buf[name].data_ptr() if name in self.bk_buf else None)
+        use_bk = bispectrum and self.ntri > 0
+        h = frsd_graph_create(self.handle, self.ws_ptr, _c_catalog(gal), _c_catalog(ran), alpha, po,
+                              bo if use_bk else None, self.stream.cuda_stream)
+        return Graph(self, h, (gal, ran))
+
     def status(self) -> int:
         return frsd_status(self.handle, self.ws_ptr, self.stream.cuda_stream)
 
@@ -364,6 +398,23 @@ class Plan:
         if rej:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
         return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+class Graph:
+    """A request captured on a Plan; launch() replays it with the first n_gal /
+    n_ran objects of the captured buffers."""
+
+    def __init__(self, plan: Plan, handle: int, keep):
+        self.plan, self.handle, self._keep = plan, handle, keep
+
+    def launch(self, n_gal: int, n_ran: int, alpha: float) -> None:
+        frsd_graph_launch(self.handle, n_gal, n_ran, alpha, self.plan.stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            frsd_graph_destroy(h)
+            self.handle = None
 
 
 def kf(box: float) -> float:
