@@ -355,6 +355,10 @@ def served_with_random_cache(args, F, torch, wl, dev_mocks, r_dev, observer, max
     cfg = make_config(F, wl, 32, observer, max_obj)
     cfg.random_cache = True
     plans = [F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev)) for _ in range(nstream)]
+    if not args.no_tuning:
+        from paper_1506_02729_amd import autotune
+        for pl in plans:
+            autotune.apply(pl)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pl in plans:
@@ -597,6 +601,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-random-cache", action="store_true", help="skip the closed loop with the random cache")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the served plan's launch parameters first and store them in the tuning cache")
+    ap.add_argument("--no-tuning", action="store_true", help="library default launch parameters (ignore the cache)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the served covariance run (Poisson arrivals, mixed mesh sizes); 0: skip it")
     ap.add_argument("--serve-only", action="store_true", help="run only the served covariance run")
@@ -648,6 +655,16 @@ def main():
     torch.cuda.synchronize()
     log(f"fp32 plan init (tables + N^T) {time.perf_counter() - t0:.2f} s, {nstream} workspace(s) of "
         f"{plan.ws_bytes / 1e9:.1f} GB")
+    from paper_1506_02729_amd import autotune
+    if args.autotune:
+        def one(pl, it=iter(range(1 << 30))):
+            g, r, a = dev_mocks[next(it) % len(dev_mocks)]
+            pl.mesh_assign(g, r, a)
+            pl.pk()
+            pl.bk()
+        autotune.tune(plan, one, torch.cuda.synchronize, path=autotune.DEFAULT_CACHE, log=log)
+    tuning = None if args.no_tuning else [autotune.apply(pl) for pl in plans][0]
+    log(f"tuning: {tuning if tuning else 'library defaults'}")
     run_steps(F, torch, plans, dev_mocks, max(args.warmup, nstream), False)
     torch.cuda.synchronize()
     log("warmup done")
@@ -788,6 +805,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "requests": args.steps, "mocks_in_pool": len(pool),
                    "in_flight": nstream, "kernel_timing": f"{max(1, args.kernel_steps)} requests, one in flight",
+                   "tuning": tuning,
                    "precision": "fp32 served (closed loop), fp64 plain (one mock at a time)"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "note": "closed loop, enqueue to stream completion with --streams requests in flight; "

@@ -136,6 +136,20 @@ typedef struct {
                              (N^T I33), eq. (Bhexa2), no shot noise subtracted      */
 } frsd_bk_out;
 
+/* Launch parameters chosen by the autotuner (paper_1506_02729_amd/autotune.py,
+ * cached as JSON per plan shape); any value in range gives the same results
+ * up to rounding order.  frsd_plan_set_tuning may be called at any time
+ * between requests (the workspace is sized for the largest values);
+ * FRSD_EINVAL outside the ranges. */
+typedef struct {
+  int32_t tri_wg;      /* workgroups of the matrix-core contraction, 256..2048 (1024)      */
+  int32_t row_grid;    /* workgroups of the persistent forward z pass, 256..16384 (4096)   */
+  int32_t bin_blocks;  /* workgroups of the binning kernel, 256..4096 (2048)               */
+  int32_t pair_batch;  /* shell-field pairs per inverse-FFT launch, 1..8 (8)               */
+} frsd_tuning;
+int frsd_plan_set_tuning(frsd_plan *plan, const frsd_tuning *tuning);
+int frsd_plan_get_tuning(const frsd_plan *plan, frsd_tuning *tuning);
+
 /* Validates parameters and builds the host-side plan: bins, triangle list,
  * FFT radix schedules and the workspace layout.  Host only. */
 int frsd_plan_create(const frsd_params *params, frsd_plan **plan);

@@ -382,9 +382,10 @@ static int shell_pipeline_ct(frsd_plan *pl, void *ws, int nfield, const void *tw
   FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y_ct<T, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shy));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x_ct<T, TO, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shx));
   const int npairs = (nfield + 1) / 2;
-  for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
+  const int pb = pl->tune.pair_batch;
+  for (int p0 = 0; p0 < npairs; p0 += pb) {
     a.pair0 = p0;
-    a.npair = std::min(kPairBatch, npairs - p0);
+    a.npair = std::min(pb, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * LEN,
                     nx = (long long)a.npair * LEN * LEN;
     FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z_ct<T, IND, LEN>), dim3((unsigned)((nz + PZ - 1) / PZ)), dim3(NTZ), shz, s,
@@ -415,9 +416,10 @@ static int shell_pipeline_rt(frsd_plan *pl, void *ws, int nfield, const void *tw
   FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_y<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_shell_x<T, TO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   const int npairs = (nfield + 1) / 2;
-  for (int p0 = 0; p0 < npairs; p0 += kPairBatch) {
+  const int pb = pl->tune.pair_batch;
+  for (int p0 = 0; p0 < npairs; p0 += pb) {
     a.pair0 = p0;
-    a.npair = std::min(kPairBatch, npairs - p0);
+    a.npair = std::min(pb, npairs - p0);
     const long long nz = (long long)a.npair * D * D, ny = (long long)a.npair * D * M,
                     nx = (long long)a.npair * M * M;
     FRSD_TIMED("shell_z", s, hipLaunchKernelGGL((k_shell_z<T, IND>), dim3((unsigned)((nz + P - 1) / P)), dim3(FftTune<T>::threads), shmem, s,

@@ -152,7 +152,6 @@ template <typename T, int LEN> constexpr int p_row() {
 // Row pass (z), persistent: a fixed grid of workgroups walks the groups of
 // P_ROW rows, slot by slot, and moves on at once from groups whose rows are
 // all empty, so the empty part of the box costs no workgroup launches.
-constexpr unsigned kRowGrid = 4096;
 
 template <typename T, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data, const T *planar,
@@ -270,7 +269,7 @@ static Keep make_keep(int N, int P, int nmax) {
 
 template <typename T, int LEN>
 static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
+                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid) {
   using C = cplx_t<T>;
   constexpr int PR = p_row<T, LEN>(), PC = FwdTune<T>::p_col;
   constexpr long long NN = (long long)LEN * LEN;
@@ -282,7 +281,7 @@ static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int 
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   const long long bs = NN * LEN;
-  const dim3 gz(kRowGrid), gy((unsigned)LEN * nzb, n_batch),
+  const dim3 gz((unsigned)row_grid), gy((unsigned)LEN * nzb, n_batch),
       gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_row<T, LEN>), gz, dim3(FwdTune<T>::nt_row), sh_row, s, (C *)mesh,
                                             (const T *)planar, (const C *)tw, bs, k, colmask, n_batch));
@@ -323,10 +322,10 @@ static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar,
 
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, m2max, colmask, xmask, s);
+  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, m2max, colmask, xmask, s, row_grid);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
     default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
@@ -334,8 +333,8 @@ int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mes
 }
 
 template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
-                                  const uint8_t *, hipStream_t);
+                                  const uint8_t *, hipStream_t, int);
 template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
-                                   const uint8_t *, hipStream_t);
+                                   const uint8_t *, hipStream_t, int);
 
 }  // namespace frsd

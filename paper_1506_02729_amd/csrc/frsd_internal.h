@@ -94,10 +94,13 @@ inline size_t sorted_bytes(size_t nobj, size_t tbytes) { return ((nobj * 4 * tby
 constexpr int kBinSums = 8;     // per bin: count, sum|k|, then S00 S20 S40 S22 (P bins) or -, -, -, S0w S2w S4w (B bins)
 constexpr int kScalars = 4;     // I22, N0, I33, W3
 constexpr int kIngestBlocks = 1024;
-constexpr int kBinBlocks = 2048;
+constexpr int kBinBlocks = 2048;       // default of the tunable bin_blocks (tuning limits below)
 constexpr int kTriBlocks = 1024;
 constexpr int kTriMfmaBlocks = 1024;
-constexpr int kPairBatch = 8;   // shell-field pairs per inverse-FFT batch
+constexpr int kPairBatch = 8;   // default shell-field pairs per inverse-FFT batch
+// Tunable launch parameters (frsd_plan_set_tuning); the workspace is sized for
+// the largest values so that a plan can be retuned at any time.
+constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 8;
 
 // One constant table of a plan: bytes at host_off of the plan's host table
 // image go to workspace offset ws_off.
@@ -109,6 +112,7 @@ struct TabSeg {
 
 struct frsd_plan {
   frsd_params p{};
+  frsd_tuning tune{frsd::kTriMfmaBlocks, 4096, frsd::kBinBlocks, frsd::kPairBatch};
   int N = 0;
   double h = 0, kf = 0;
   frsd::SlotDesc slots{};
@@ -227,7 +231,7 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s, bool pageable);
 // |n|^2 <= m2max are guaranteed in the output.
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s);
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid);
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);

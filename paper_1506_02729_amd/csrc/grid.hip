@@ -687,7 +687,8 @@ static int grid_and_transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStrea
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
                           ws_ptr<void>(ws, mesh_off), pl->slots.n_slot, pl->nmax,
                           std::max(pl->pk_lut_len, pl->p.bk_nbins > 0 ? pl->bk_lut_len : 0) - 1,
-                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
+                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s,
+                          pl->tune.row_grid);
 }
 
 template <typename T>
@@ -740,7 +741,8 @@ int run_w_moments(frsd_plan *pl, void *ws, hipStream_t s) {
   const int n_slot = pl->p.interlace ? pl->n_wmom : (pl->n_wmom + 1) / 2;
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
                           ws_ptr<void>(ws, pl->L.mesh), n_slot, pl->nc_b, pl->bk_lut_len - 1,
-                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s);
+                          ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s,
+                          pl->tune.row_grid);
 }
 
 template int run_w_moments<float>(frsd_plan *, void *, hipStream_t);

@@ -394,14 +394,14 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
   const BinArgs a = bin_args(pl);
   constexpr int NV = BinValues<true>::n;
-  FRSD_TIMED("bin_geom", s, hipLaunchKernelGGL((k_bin<float, true, true>), dim3(kBinBlocks), dim3(kBinThreads), 0, s,
+  FRSD_TIMED("bin_geom", s, hipLaunchKernelGGL((k_bin<float, true, true>), dim3(pl->tune.bin_blocks), dim3(kBinThreads), 0, s,
                                                (const float2 *)nullptr, 0LL, a,
                                                ws_ptr<const int16_t>(ws, L.pk_lut),
                                                p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                                (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part),
                                                (const float2 *)nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
-                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
                                                  p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));  // geometry
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
@@ -432,14 +432,14 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool 
   const long long NNN = (long long)pl->N * pl->N * pl->N;
   constexpr int NV = BinValues<false>::n;
   auto kern = p.interlace ? k_bin<T, false, true> : k_bin<T, false, false>;
-  FRSD_TIMED("bin", s, hipLaunchKernelGGL(kern, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
+  FRSD_TIMED("bin", s, hipLaunchKernelGGL(kern, dim3(pl->tune.bin_blocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
                                           NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                           p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                           p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr,
                                           ws_ptr<double>(ws, L.bin_part),
                                           a.cached ? ws_ptr<const C>(ws, L.rcache) : nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
-                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
                      ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
@@ -468,12 +468,12 @@ int run_bin_w(frsd_plan *pl, void *ws, hipStream_t s) {
   const long long NNN = (long long)pl->N * pl->N * pl->N;
   constexpr int NV = BinValues<false>::n;
   auto kern = p.interlace ? k_bin<T, false, true, true> : k_bin<T, false, false, true>;
-  FRSD_TIMED("bin_w", s, hipLaunchKernelGGL(kern, dim3(kBinBlocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
+  FRSD_TIMED("bin_w", s, hipLaunchKernelGGL(kern, dim3(pl->tune.bin_blocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
                                             NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                             ws_ptr<const int16_t>(ws, L.bk_lut), ws_ptr<C>(ws, L.lowk),
                                             ws_ptr<double>(ws, L.bin_part), (const C *)nullptr));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
-                                                 ws_ptr<const double>(ws, L.bin_part), kBinBlocks, NV, nall,
+                                                 ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
                                                  p.pk_nbins, 2, ws_ptr<double>(ws, L.bin_sum)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;

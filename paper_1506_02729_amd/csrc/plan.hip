@@ -234,11 +234,11 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   }
   L.planar = take(2 * T * NNN * sd.n_slot);
   const int nbins_all = p.pk_nbins + p.bk_nbins;
-  L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kBinBlocks);
+  L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kMaxBinBlocks);
   L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);
   if (p.bk_nbins > 0) {
     const size_t D = pl->D, M = pl->M;
-    const size_t npair_batch = kPairBatch;
+    const size_t npair_batch = kMaxPairBatch;
     L.lowk = take(2 * T * 3 * D * D * D);
     // intermediates sized for FP64 (the N^T indicator fields are FP64 for every plan)
     const size_t buf1_bytes = 16 * npair_batch * D * D * M, buf2_bytes = 16 * npair_batch * D * M * M;
@@ -265,7 +265,7 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     size_t vec_part = 0;
     if (!triple_mfma_supported(pl)) vec_part = std::max(vec_part, 8 * (size_t)pl->n_out * kTriBlocks);
     if (!triple_mfma_supported(pl, 1)) vec_part = std::max(vec_part, 8 * (size_t)pl->ntri * kTriBlocks);
-    L.tri_part = take(std::max(vec_part, triple_mfma_part_bytes(pl, kTriMfmaBlocks)));
+    L.tri_part = take(std::max(vec_part, triple_mfma_part_bytes(pl, kMaxTriWg)));
     L.pair_tab = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
     L.tri_dense = take(triple_mfma_dense_bytes());
     L.pair_tab_nt = take(8 * (size_t)p.bk_nbins * (p.bk_nbins + 1) / 2);
@@ -315,6 +315,23 @@ extern "C" int frsd_bk_ntriangles(const frsd_plan *plan, int64_t *ntri) {
   clear_error();
   if (!plan || !ntri) return fail(FRSD_EINVAL, "null argument");
   *ntri = plan->ntri;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_plan_set_tuning(frsd_plan *plan, const frsd_tuning *t) {
+  clear_error();
+  if (!plan || !t) return fail(FRSD_EINVAL, "null argument");
+  if (t->tri_wg < 256 || t->tri_wg > kMaxTriWg || t->row_grid < 256 || t->row_grid > kMaxRowGrid ||
+      t->bin_blocks < 256 || t->bin_blocks > kMaxBinBlocks || t->pair_batch < 1 || t->pair_batch > kMaxPairBatch)
+    return fail(FRSD_EINVAL, "tuning value out of range");
+  plan->tune = *t;
+  return FRSD_OK;
+}
+
+extern "C" int frsd_plan_get_tuning(const frsd_plan *plan, frsd_tuning *t) {
+  clear_error();
+  if (!plan || !t) return fail(FRSD_EINVAL, "null argument");
+  *t = plan->tune;
   return FRSD_OK;
 }
 

@@ -95,19 +95,22 @@ __device__ __forceinline__ void split2_prod_bf16(float a0, float b0, float a1, f
 // FP32 for the on-the-fly pair products.  Stages alternate between two LDS
 // buffers: the global loads of stage s + 1 are issued before the MFMAs of
 // stage s and stored into the other buffer after them.
+// NU: staged rows (F_0 of every bin and a zero row for T_ell; F_0 and F_2
+// of every bin and a zero row for T_220).
+template <int NU>
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                float *__restrict__ part) {
   // two stage buffers; row kXMaxB of U stays zero.  B2[buffer][0] holds the
   // hi parts, B2[buffer][1] the lo parts, at a fixed byte distance so one
   // address serves both reads.
-  __shared__ __attribute__((aligned(16))) float U2[2][kXMaxU][kXUPad];
+  __shared__ __attribute__((aligned(16))) float U2[2][NU][kXUPad];
   __shared__ __attribute__((aligned(16))) __bf16 B2[2][2][kXCols][kXBPad];
   __shared__ uint32_t prs[kXMaxRows];  // byte offsets in U of rows b2 (low half) and b3 (high half)
   __shared__ uint8_t cmap[kXCols];     // staged field -> column (0xff: not a column)
-  constexpr int kURow = kXUPad * 4, kUBuf = kXMaxU * kURow;  // bytes
+  constexpr int kURow = kXUPad * 4, kUBuf = NU * kURow;  // bytes
   constexpr int kBRow = kXBPad * 2, kBHalf = kXCols * kBRow, kBBuf = 2 * kBHalf;
-  constexpr int kZeroRow = kXMaxU - 1;
+  constexpr int kZeroRow = NU - 1;
   static_assert(kZeroRow * kURow < 65536 && kBHalf < 65536, "offsets must fit 16 bits / the DS immediate");
 
   const int lane = threadIdx.x & 63;
@@ -285,14 +288,15 @@ constexpr int kZKC = 32;         // cells per LDS stage (8 MFMA k-steps of 4)
 constexpr int kZPad = kZKC + 2;  // doubles per staged row: rows 68 dwords apart keep 8-byte reads conflict-free
 constexpr int kZPf = (kXCols * (kZKC / 2) + kXThreads - 1) / kXThreads;  // cell pairs per thread per stage
 
+template <int NU>
 __global__ __launch_bounds__(kXThreads) void k_triple_mfma64(const double *__restrict__ f, XArgs a, XJobs jobs,
                                                                const int2 *__restrict__ pairs,
                                                                double *__restrict__ part) {
-  __shared__ __attribute__((aligned(16))) double U2[2][kXMaxU][kZPad];  // the last row stays zero
+  __shared__ __attribute__((aligned(16))) double U2[2][NU][kZPad];  // the last row stays zero
   __shared__ __attribute__((aligned(16))) double B2[2][kXCols][kZPad];
   __shared__ uint32_t prs[kXMaxRows];  // U row offsets (doubles) of b2 (low half) and b3 (high half)
   __shared__ uint8_t cmap[kXCols];     // staged field -> column (0xff: not a column)
-  constexpr int kZeroRow = kXMaxU - 1;
+  constexpr int kZeroRow = NU - 1;
   static_assert(kZeroRow * kZPad < 65536, "row offsets must fit 16 bits");
 
   const int lane = threadIdx.x & 63;
@@ -603,14 +607,15 @@ static int triple_mfma_run(frsd_plan *pl, void *ws, const float *fields, bool t2
   int njobs = 0;
   if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
   a.njobs = njobs;
-  const int nwg = kTriMfmaBlocks;
+  const int nwg = pl->tune.tri_wg;
   long long per = (a.ncell + nwg - 1) / nwg;
   per = (per + kXKC - 1) / kXKC * kXKC;
   a.cells_per_wg = per;
   double *dense = ws_ptr<double>(ws, t220 ? L.tri_dense_nt : L.tri_dense);
   const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
+  auto kern = t220 ? k_triple_mfma<kXMaxU> : k_triple_mfma<kXMaxB + 1>;
   FRSD_TIMED(t220 ? "triple_220" : "triple", s,
-             hipLaunchKernelGGL(k_triple_mfma, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
+             hipLaunchKernelGGL(kern, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
                                 ws_ptr<const int2>(ws, t220 ? L.pair_tab_220 : L.pair_tab),
                                 ws_ptr<float>(ws, L.tri_part)));
   const int nvals = njobs * 256;
@@ -654,14 +659,15 @@ static int triple_mfma64_run(frsd_plan *pl, void *ws, const double *fields, int 
   int njobs = 0;
   if (!make_jobs(pl, ne, &jobs, &tile_job, &njobs)) return fail(FRSD_EINVAL, "too many contraction tiles");
   a.njobs = njobs;
-  const int nwg = kTriMfmaBlocks;
+  const int nwg = pl->tune.tri_wg;
   long long per = (a.ncell + nwg - 1) / nwg;
   per = (per + kZKC - 1) / kZKC * kZKC;
   a.cells_per_wg = per;
   double *dense = ws_ptr<double>(ws, dense_off);
   const int16_t *tj = reinterpret_cast<const int16_t *>(dense + (size_t)kXWaves * kXMaxJobs * 256);
+  auto kern = t220 ? k_triple_mfma64<kXMaxU> : k_triple_mfma64<kXMaxB + 1>;
   FRSD_TIMED(t220 ? "triple_220" : "triple", s,
-             hipLaunchKernelGGL(k_triple_mfma64, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
+             hipLaunchKernelGGL(kern, dim3(nwg), dim3(kXThreads), 0, s, fields, a, jobs,
                                 ws_ptr<const int2>(ws, pair_off), ws_ptr<double>(ws, L.tri_part)));
   const int nvals = njobs * 256;
   FRSD_TIMED("tri_reduce", s,

@@ -52,6 +52,10 @@ class frsd_params(ctypes.Structure):
     ]
 
 
+class frsd_tuning(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in ("tri_wg", "row_grid", "bin_blocks", "pair_batch")]
+
+
 class frsd_catalog(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("dtype", ctypes.c_int32)]
@@ -72,6 +76,8 @@ _proto = {
     "frsd_plan_create": (ctypes.c_int, [ctypes.POINTER(frsd_params), ctypes.POINTER(_P)]),
     "frsd_plan_destroy": (None, [_P]),
     "frsd_plan_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "frsd_plan_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(frsd_tuning)]),
+    "frsd_plan_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(frsd_tuning)]),
     "frsd_plan_init": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "frsd_mesh_assign": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.POINTER(frsd_catalog),
                                         ctypes.c_double, _P]),
@@ -127,6 +133,17 @@ def frsd_plan_workspace_bytes(plan: int) -> int:
     v = ctypes.c_size_t()
     _check(_lib.frsd_plan_workspace_bytes(plan, ctypes.byref(v)))
     return v.value
+
+
+def frsd_plan_set_tuning(plan: int, tuning: dict) -> None:
+    t = frsd_tuning(**{k: int(v) for k, v in tuning.items()})
+    _check(_lib.frsd_plan_set_tuning(plan, ctypes.byref(t)))
+
+
+def frsd_plan_get_tuning(plan: int) -> dict:
+    t = frsd_tuning()
+    _check(_lib.frsd_plan_get_tuning(plan, ctypes.byref(t)))
+    return {name: int(getattr(t, name)) for name, _ in frsd_tuning._fields_}
 
 
 def frsd_plan_init(plan: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:

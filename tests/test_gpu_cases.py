@@ -265,3 +265,29 @@ def test_random_cache(gpu_lib, precision, N, interlace, ell_max):
     out_again = plan.run_cached(gpu_lib.device_catalog(gal, dev), alpha)
     scale = np.max(np.abs(out_plain["p0"]))
     assert np.max(np.abs(out_again["p0"] - out_plain["p0"])) <= close * scale
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_tuned_launch_parameters(gpu_lib, precision):
+    """Other launch parameters (contraction, z-pass and binning workgroups,
+    shell pairs per launch) give the same results as the defaults, within
+    rounding (1e-5 of the largest value FP32, 1e-11 FP64), and the oracle's."""
+    import torch
+    _log(f"case: tuned launch parameters precision={precision}")
+    dev = torch.device("cuda:0")
+    gal, ran, alpha, prm = _bk_case(171, N=64, nbk=6, n_gal=4000, n_ran=20000)
+    cfg = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    g, r = gpu_lib.device_catalog(gal, dev), gpu_lib.device_catalog(ran, dev)
+    base = gpu_lib.Plan(cfg, device=dev).run(g, r, alpha)
+    refp, refb = _oracle(gal, ran, alpha, prm)
+    close = 1e-5 if precision == 32 else 1e-11
+    for t in ({"tri_wg": 512, "row_grid": 1024, "bin_blocks": 4096, "pair_batch": 1},
+              {"tri_wg": 2048, "row_grid": 16384, "bin_blocks": 256, "pair_batch": 3}):
+        plan = gpu_lib.Plan(cfg, device=dev)
+        gpu_lib.frsd_plan_set_tuning(plan.handle, t)
+        out = plan.run(g, r, alpha)
+        _check_pk(out, refp, prm, precision)
+        _check_bk(out, refb, prm, precision, plan)
+        for key in ("p0", "p2", "p4", "bk_t0", "bk_t2", "bk_t4"):
+            scale = np.max(np.abs(base[key]))
+            assert np.max(np.abs(out[key] - base[key])) <= close * scale, (t, key)
