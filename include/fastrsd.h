@@ -88,6 +88,10 @@ typedef struct {
                             one random catalogue (frsd_random_cache), so that mocks
                             sharing it run frsd_mesh_assign_cached on their galaxies
                             alone (not with bk_shot_noise = 1)                      */
+  int32_t stream_moments;/* 1: P_ell only, for meshes whose moment meshes do not fit at
+                            once (N = 1024): the moments are gridded, transformed and
+                            accumulated into A_0, A_2, A_4 two complex slots at a time
+                            (no bispectrum, no random cache)                        */
 } frsd_params;
 
 /* A catalogue in device memory.  pos is n x 3 interleaved (x, y, z);

@@ -57,8 +57,14 @@ extern "C" int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *g
     return fail(FRSD_ENOMEM, "galaxies + randoms exceed max_objects of the plan");
   if (gal->n + ran->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (plan->p.precision == FRSD_F64) rc = run_mesh_assign<double>(plan, ws, gal, ran, alpha, s);
-  else rc = run_mesh_assign<float>(plan, ws, gal, ran, alpha, s);
+  if (plan->p.stream_moments) {
+    if (plan->p.precision == FRSD_F64) rc = run_stream_assign<double>(plan, ws, gal, ran, alpha, s);
+    else rc = run_stream_assign<float>(plan, ws, gal, ran, alpha, s);
+  } else if (plan->p.precision == FRSD_F64) {
+    rc = run_mesh_assign<double>(plan, ws, gal, ran, alpha, s);
+  } else {
+    rc = run_mesh_assign<float>(plan, ws, gal, ran, alpha, s);
+  }
   if (rc) return rc;
   plan->state = 2;
   plan->assigned_cached = false;
@@ -113,7 +119,9 @@ extern "C" int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *
       !out->s40 || !out->scalars)
     return fail(FRSD_EINVAL, "null output array");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (plan->p.precision == FRSD_F64) rc = run_pk<double>(plan, ws, out, s, plan->assigned_cached);
+  if (plan->p.stream_moments) rc = plan->p.precision == FRSD_F64 ? run_stream_pk<double>(plan, ws, out, s)
+                                                                  : run_stream_pk<float>(plan, ws, out, s);
+  else if (plan->p.precision == FRSD_F64) rc = run_pk<double>(plan, ws, out, s, plan->assigned_cached);
   else rc = run_pk<float>(plan, ws, out, s, plan->assigned_cached);
   if (rc) return rc;
   plan->state = 3;

@@ -81,6 +81,7 @@ struct Layout {
   size_t tri_tab220 = 0;                         // vector-contraction outputs of T_220 (F_2 b1, F_2 b2, F_0 b3)
   size_t rcache = 0, rcache_sums = 0;            // cached random spectra (mesh layout) and their sums
   size_t dyn = 0;                                // {N_g, N_r, alpha} of graph replays (double)
+  size_t acc = 0;                                // streamed plans: class-sum accumulators R_0, R_2, R_4
   size_t total = 0;
 };
 
@@ -98,6 +99,7 @@ constexpr int kBinBlocks = 2048;       // default of the tunable bin_blocks (tun
 constexpr int kTriBlocks = 1024;
 constexpr int kTriMfmaBlocks = 1024;
 constexpr int kPairBatch = 8;   // default shell-field pairs per inverse-FFT batch
+constexpr int kStreamSlots = 2;  // complex slots gridded and transformed per pass of a streamed plan
 // Tunable launch parameters (frsd_plan_set_tuning); the workspace is sized for
 // the largest values so that a plan can be retuned at any time.
 constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 8;
@@ -202,6 +204,13 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
 // cached: the meshes hold galaxies alone, combined here with the random cache
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached);
+// streamed plans (stream.hip): moment groups accumulated into R_0, R_2, R_4
+template <typename T>
+int run_stream_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
+                      hipStream_t s);
+template <typename T>
+int run_stream_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+size_t stream_acc_bytes(const frsd_plan *pl, size_t tbytes);
 // random cache (grid.hip): spectra of the randoms alone; galaxies against it
 template <typename T>
 int run_random_cache(frsd_plan *pl, void *ws, const frsd_catalog *ran, hipStream_t s);

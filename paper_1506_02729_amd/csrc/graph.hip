@@ -37,6 +37,7 @@ extern "C" int frsd_graph_create(frsd_plan *plan, void *ws, const frsd_catalog *
   if (!plan || !ws || !out) return fail(FRSD_EINVAL, "null argument");
   if (plan->state < 1 || plan->init_ws != ws) return fail(FRSD_ESTATE, "workspace not initialised by frsd_plan_init");
   if (prof_on()) return fail(FRSD_ESTATE, "per-kernel profiling must be off while a request is captured");
+  if (plan->p.stream_moments) return fail(FRSD_EINVAL, "streamed plans are not captured");
   int rc;
   if ((rc = check_catalog(gal, false, "galaxies"))) return rc;
   if ((rc = check_catalog(ran, true, "randoms"))) return rc;

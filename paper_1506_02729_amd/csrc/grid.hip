@@ -94,6 +94,8 @@ struct GridArgs {
   int has_w;           // w^2 plane present (position n_ell_mom)
   int interlace;
   int wsq;             // 1: every object weighs t0^2 (the w^2-weighted moments of F^w_l)
+  int m0;              // first moment position written (streamed plans grid a group of positions
+                       // m0..n_ell_mom-1 per pass; planes are numbered from m0)
   double ou[3];        // observer in grid units
   long long plane_stride;
 };
@@ -338,12 +340,12 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
   if (!live) return;
   const long long g = ((long long)(X0 + lx) * N + (Y0 + ly)) * N + (Z0 + lz);
   const long long ps = ga.plane_stride;
-  const int n_mom = ga.n_ell_mom + ga.has_w;
+  const int n_mom = ga.n_ell_mom + ga.has_w - ga.m0;
 #pragma unroll
   for (int id = 0; id < kMaxMom; ++id) {
-    const bool present = id < ga.n_ell_mom || (id == kMomW && ga.has_w);
+    const bool present = (id < ga.n_ell_mom && id >= ga.m0) || (id == kMomW && ga.has_w);
     if (!present) continue;
-    const int pos = id < ga.n_ell_mom ? id : ga.n_ell_mom;  // position of the moment in the slot list
+    const int pos = (id < ga.n_ell_mom ? id : ga.n_ell_mom) - ga.m0;  // position of the moment in the slot list
     if (ga.interlace) {
       planar[(2LL * pos) * ps + g] = am[id];
       planar[(2LL * pos + 1) * ps + g] = at[id];
@@ -591,14 +593,14 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         // far more data than the caches hold has passed
 #pragma unroll
         for (int id = 0; id < kMaxMom; ++id) {
-          const bool present = id < nmom || (id == kMomW && has_w);
+          const bool present = (id < nmom && id >= ga.m0) || (id == kMomW && has_w);
           if (!present) continue;
-          const int pos = id < nmom ? id : nmom;
+          const int pos = (id < nmom ? id : nmom) - ga.m0;
           if (ga.interlace) __builtin_nontemporal_store(a[id], &planar[(2LL * pos + (TWIN ? 1 : 0)) * ps + g]);
           else __builtin_nontemporal_store(a[id], &planar[(long long)pos * ps + g]);
         }
-        if (!TWIN && !ga.interlace && ((nmom + (has_w ? 1 : 0)) & 1))
-          planar[(long long)(nmom + (has_w ? 1 : 0)) * ps + g] = 0.f;
+        const int nw = nmom + (has_w ? 1 : 0) - ga.m0;
+        if (!TWIN && !ga.interlace && (nw & 1)) planar[(long long)nw * ps + g] = 0.f;
       }
     }
 #pragma unroll
@@ -619,7 +621,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
 // wsq: weights t0^2 instead of t0 (a second pass after the first, whose
 // occupancy masks it reuses).
 template <typename T, int P>
-static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq) {
+static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0) {
   const Layout &L = pl->L;
   const int N = pl->N;
   GridArgs ga{};
@@ -627,10 +629,11 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
   ga.n_ell_mom = n_ell_mom;
   ga.has_w = has_w;
   ga.wsq = wsq;
+  ga.m0 = m0;
   ga.interlace = pl->p.interlace;
   for (int d = 0; d < 3; ++d) ga.ou[d] = pl->p.observer[d] / pl->h;
   ga.plane_stride = (long long)N * N * N;
-  if (!wsq)
+  if (!wsq && m0 == 0)
     FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
                                                  ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
                                                  ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
@@ -663,14 +666,22 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
 }
 
 template <typename T>
-static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq) {
+static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0 = 0) {
   switch (pl->p.order) {
-    case 1: return launch_grid<T, 1>(pl, ws, s, n_ell_mom, has_w, wsq);
-    case 2: return launch_grid<T, 2>(pl, ws, s, n_ell_mom, has_w, wsq);
-    case 3: return launch_grid<T, 3>(pl, ws, s, n_ell_mom, has_w, wsq);
-    default: return launch_grid<T, 4>(pl, ws, s, n_ell_mom, has_w, wsq);
+    case 1: return launch_grid<T, 1>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
+    case 2: return launch_grid<T, 2>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
+    case 3: return launch_grid<T, 3>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
+    default: return launch_grid<T, 4>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
   }
 }
+
+// Moment positions m0..m1-1 only (streamed plans), planes numbered from m0.
+template <typename T>
+int run_grid_group(frsd_plan *pl, void *ws, int m0, int m1, hipStream_t s) {
+  return grid_order<T>(pl, ws, s, m1, 0, 0, m0);
+}
+template int run_grid_group<float>(frsd_plan *, void *, int, int, hipStream_t);
+template int run_grid_group<double>(frsd_plan *, void *, int, int, hipStream_t);
 
 // Assignment and forward transforms of the sorted records into the complex
 // meshes at mesh_off (the mesh region, or the random cache).

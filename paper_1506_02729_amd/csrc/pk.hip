@@ -407,6 +407,8 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
   return FRSD_OK;
 }
 
+int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached) {
   const Layout &L = pl->L;
@@ -441,6 +443,14 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool 
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
+  FRSD_LAUNCH_CHECK();
+  return run_pk_final(pl, ws, out, s);
+}
+
+// P_ell from the bin sums (slots 0-5 of every P_ell bin) and the scalars.
+int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
+  const Layout &L = pl->L;
+  const frsd_params &p = pl->p;
   FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
                      ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
                      out->p4, out->s00, out->s20, out->s40, out->scalars, out->p4b, out->s22));

@@ -135,6 +135,9 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (p.random_cache != 0 && p.random_cache != 1) return fail(FRSD_EINVAL, "random_cache must be 0 or 1");
   if (p.random_cache && p.bk_shot_noise && p.bk_nbins > 0)
     return fail(FRSD_EINVAL, "random_cache does not combine with bk_shot_noise (its second pass grids every object)");
+  if (p.stream_moments != 0 && p.stream_moments != 1) return fail(FRSD_EINVAL, "stream_moments must be 0 or 1");
+  if (p.stream_moments && (p.bk_nbins > 0 || p.random_cache))
+    return fail(FRSD_EINVAL, "stream_moments plans compute P_ell only (no bispectrum, no random cache)");
 
   frsd_plan *pl = new frsd_plan();
   pl->p = p;
@@ -227,12 +230,14 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.slot = take(4 * nobj);
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));
-  L.mesh = take(2 * T * NNN * sd.n_slot);
+  const size_t slots_resident = p.stream_moments ? (size_t)std::min(kStreamSlots, sd.n_slot) : (size_t)sd.n_slot;
+  L.mesh = take(2 * T * NNN * slots_resident);
+  if (p.stream_moments) L.acc = take(stream_acc_bytes(pl, T));
   if (p.random_cache) {
     L.rcache = take(2 * T * NNN * sd.n_slot);
     L.rcache_sums = take(8 * 4);
   }
-  L.planar = take(2 * T * NNN * sd.n_slot);
+  L.planar = take(2 * T * NNN * slots_resident);
   const int nbins_all = p.pk_nbins + p.bk_nbins;
   L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kMaxBinBlocks);
   L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);

@@ -50,6 +50,8 @@ extern "C" int frsd_run_static(frsd_plan *plan, const frsd_catalog *gal, const f
                                const frsd_pk_out *pk, const frsd_bk_out *bk, void *stream) {
   clear_error();
   if (!plan) return fail(FRSD_EINVAL, "null plan");
+  if (plan->p.stream_moments || plan->p.random_cache)
+    return fail(FRSD_EINVAL, "frsd_run_static takes plans without stream_moments and random_cache");
   if (plan->L.total > kScratchBytes)
     return fail(FRSD_ENOMEM, "the plan's workspace (" + std::to_string(plan->L.total) +
                                  " bytes) exceeds the static scratch (" + std::to_string(kScratchBytes) + " bytes)");

@@ -48,7 +48,7 @@ class frsd_params(ctypes.Structure):
         ("bk_kmin", ctypes.c_double), ("bk_dk", ctypes.c_double), ("bk_nbins", ctypes.c_int32),
         ("bk_grid", ctypes.c_int32), ("max_objects", ctypes.c_int64),
         ("bk_ell_max", ctypes.c_int32), ("bk_shot_noise", ctypes.c_int32), ("bk_zero_area", ctypes.c_int32),
-        ("random_cache", ctypes.c_int32),
+        ("random_cache", ctypes.c_int32), ("stream_moments", ctypes.c_int32),
     ]
 
 
@@ -258,6 +258,7 @@ class Config:
     bk_shot_noise: bool = False
     bk_zero_area: bool = False
     random_cache: bool = False
+    stream_moments: bool = False
 
     def to_c(self) -> frsd_params:
         p = frsd_params()
@@ -271,6 +272,7 @@ class Config:
         p.bk_grid, p.max_objects = self.bk_grid, int(self.max_objects)
         p.bk_ell_max, p.bk_shot_noise, p.bk_zero_area = self.bk_ell_max, int(self.bk_shot_noise), int(self.bk_zero_area)
         p.random_cache = int(self.random_cache)
+        p.stream_moments = int(self.stream_moments)
         return p
 
 
