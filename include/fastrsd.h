@@ -28,6 +28,7 @@
  *  - All device memory is owned by the caller.  The library never allocates
  *    device memory: every call works inside the caller's workspace `ws`
  *    (device pointer, 256-byte aligned, at least frsd_plan_workspace_bytes).
+ *    Catalogues and outputs may also be page-locked host memory (`where`).
  *  - `stream` is a hipStream_t passed as void*.  Device calls only enqueue
  *    work on it and return; results are valid once the stream is
  *    synchronised.  Calls on one workspace must be ordered on one stream.
@@ -55,6 +56,7 @@ enum {
 };
 
 enum { FRSD_F32 = 32, FRSD_F64 = 64 };
+enum { FRSD_DEVICE = 0, FRSD_HOST = 1 };  /* where an array lives */
 
 typedef struct frsd_plan frsd_plan;
 
@@ -94,20 +96,25 @@ typedef struct {
                             (no bispectrum, no random cache)                        */
 } frsd_params;
 
-/* A catalogue in device memory.  pos is n x 3 interleaved (x, y, z);
- * w and nbar have n entries.  nbar may be NULL for galaxies (it only enters
- * I22 and I33 through the randoms).  dtype is FRSD_F32 or FRSD_F64 and
- * applies to all three arrays. */
+/* A catalogue.  pos is n x 3 interleaved (x, y, z); w and nbar have n
+ * entries.  nbar may be NULL for galaxies (it only enters I22 and I33
+ * through the randoms).  dtype is FRSD_F32 or FRSD_F64 and applies to all
+ * three arrays.  where: FRSD_DEVICE (device memory) or FRSD_HOST
+ * (page-locked host memory from hipHostMalloc, read by the ingest kernels
+ * over the host link, twice per call; other host memory gives FRSD_EINVAL). */
 typedef struct {
   const void *pos;
   const void *w;
   const void *nbar;
   int64_t n;
   int32_t dtype;
+  int32_t where;
 } frsd_catalog;
 
-/* Power-spectrum outputs: caller-owned DEVICE arrays of pk_nbins entries
- * (scalars: 4 entries).  Written by frsd_pk_multipoles. */
+/* Power-spectrum outputs: caller-owned arrays of pk_nbins entries (scalars:
+ * 4 entries), in device memory or, with where = FRSD_HOST, in page-locked
+ * host memory (written by the kernels over the host link).  Written by
+ * frsd_pk_multipoles. */
 typedef struct {
   int64_t *n_modes;  /* N_b, full-grid mode count                                  */
   double *k_eff;     /* mean |k| over the modes of the bin                          */
@@ -121,10 +128,12 @@ typedef struct {
                         7/2 S00) / (N_b I22) with the raw S00; needs ell_max >= 2 only
                         (7 FFTs), NaN for ell_max 0                                  */
   double *s22;       /* optional (NULL: not written).  Raw sum_b |F_2|^2              */
+  int32_t where;     /* FRSD_DEVICE or FRSD_HOST, for every array above               */
 } frsd_pk_out;
 
-/* Bispectrum outputs: caller-owned DEVICE arrays of ntri entries, one per
- * triangle of frsd_bk_triangles (in that order). */
+/* Bispectrum outputs: caller-owned arrays of ntri entries, one per triangle
+ * of frsd_bk_triangles (in that order), in device memory or (where =
+ * FRSD_HOST) page-locked host memory. */
 typedef struct {
   double *nt;             /* N^T, exact count of closed lattice triangles (eq. NT)  */
   double *t0, *t2, *t4;   /* raw triangle sums sum_T Re F_ell(q1) F_0(q2) F_0(q3)   */
@@ -138,6 +147,7 @@ typedef struct {
   double *t220;           /* optional (bk_zero_area): sum_T Re F_2(q1) F_2(q2) F_0(q3) */
   double *b4za;           /* optional (bk_zero_area): (35/2 T_220 - 5 T_2 - 7/2 T_0) /
                              (N^T I33), eq. (Bhexa2), no shot noise subtracted      */
+  int32_t where;          /* FRSD_DEVICE or FRSD_HOST, for every array above        */
 } frsd_bk_out;
 
 /* Launch parameters chosen by the autotuner (paper_1506_02729_amd/autotune.py,

@@ -13,6 +13,64 @@ static int check_ws(const frsd_plan *pl, const void *ws) {
   return FRSD_OK;
 }
 
+static int host_to_device(void *p, int where, void **out) {
+  *out = p;
+  if (!p || where == FRSD_DEVICE) return FRSD_OK;
+  if (where != FRSD_HOST) return fail(FRSD_EINVAL, "where must be FRSD_DEVICE or FRSD_HOST");
+  void *d = nullptr;
+  if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess || !d) {
+    (void)hipGetLastError();
+    return fail(FRSD_EINVAL, "a host array is not page-locked (allocate it with hipHostMalloc)");
+  }
+  *out = d;
+  return FRSD_OK;
+}
+
+int frsd::device_view(const frsd_catalog *in, frsd_catalog *out) {
+  *out = *in;
+  if (in->n == 0) return FRSD_OK;
+  int rc;
+  void *d;
+  if ((rc = host_to_device(const_cast<void *>(in->pos), in->where, &d))) return rc;
+  out->pos = d;
+  if ((rc = host_to_device(const_cast<void *>(in->w), in->where, &d))) return rc;
+  out->w = d;
+  if ((rc = host_to_device(const_cast<void *>(in->nbar), in->where, &d))) return rc;
+  out->nbar = d;
+  out->where = FRSD_DEVICE;
+  return FRSD_OK;
+}
+
+int frsd::device_view(const frsd_pk_out *in, frsd_pk_out *out) {
+  *out = *in;
+  double **f[] = {&out->k_eff, &out->p0, &out->p2, &out->p4, &out->s00, &out->s20, &out->s40, &out->scalars,
+                  &out->p4b, &out->s22};
+  int rc;
+  void *d;
+  if ((rc = host_to_device(out->n_modes, in->where, &d))) return rc;
+  out->n_modes = static_cast<int64_t *>(d);
+  for (double **p : f) {
+    if ((rc = host_to_device(*p, in->where, &d))) return rc;
+    *p = static_cast<double *>(d);
+  }
+  out->where = FRSD_DEVICE;
+  return FRSD_OK;
+}
+
+int frsd::device_view(const frsd_bk_out *in, frsd_bk_out *out) {
+  *out = *in;
+  double **f[] = {&out->nt, &out->t0, &out->t2, &out->t4, &out->b0, &out->b2, &out->b4, &out->sn0, &out->sn2,
+                  &out->sn4, &out->t220, &out->b4za};
+  int rc;
+  void *d;
+  for (double **p : f) {
+    if ((rc = host_to_device(*p, in->where, &d))) return rc;
+    *p = static_cast<double *>(d);
+  }
+  out->where = FRSD_DEVICE;
+  return FRSD_OK;
+}
+
 int frsd::check_catalog(const frsd_catalog *c, bool need_nbar, const char *what) {
   if (!c) return fail(FRSD_EINVAL, std::string("null catalogue: ") + what);
   if (c->n < 0) return fail(FRSD_EINVAL, std::string("negative size: ") + what);
@@ -56,6 +114,10 @@ extern "C" int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *g
   if (gal->n + ran->n > plan->p.max_objects)
     return fail(FRSD_ENOMEM, "galaxies + randoms exceed max_objects of the plan");
   if (gal->n + ran->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  frsd_catalog gd, rd;
+  if ((rc = device_view(gal, &gd)) || (rc = device_view(ran, &rd))) return rc;
+  gal = &gd;
+  ran = &rd;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.stream_moments) {
     if (plan->p.precision == FRSD_F64) rc = run_stream_assign<double>(plan, ws, gal, ran, alpha, s);
@@ -80,6 +142,9 @@ extern "C" int frsd_random_cache(frsd_plan *plan, void *ws, const frsd_catalog *
   if ((rc = check_catalog(ran, true, "randoms"))) return rc;
   if (ran->n > plan->p.max_objects) return fail(FRSD_ENOMEM, "randoms exceed max_objects of the plan");
   if (ran->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  frsd_catalog rd;
+  if ((rc = device_view(ran, &rd))) return rc;
+  ran = &rd;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.precision == FRSD_F64) rc = run_random_cache<double>(plan, ws, ran, s);
   else rc = run_random_cache<float>(plan, ws, ran, s);
@@ -100,6 +165,9 @@ extern "C" int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_cat
   if (!std::isfinite(alpha)) return fail(FRSD_EINVAL, "alpha must be finite");
   if (gal->n > plan->p.max_objects) return fail(FRSD_ENOMEM, "galaxies exceed max_objects of the plan");
   if (gal->n > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+  frsd_catalog gd;
+  if ((rc = device_view(gal, &gd))) return rc;
+  gal = &gd;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.precision == FRSD_F64) rc = run_mesh_assign_cached<double>(plan, ws, gal, alpha, s);
   else rc = run_mesh_assign_cached<float>(plan, ws, gal, alpha, s);
@@ -118,6 +186,9 @@ extern "C" int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *
   if (!out || !out->n_modes || !out->k_eff || !out->p0 || !out->p2 || !out->p4 || !out->s00 || !out->s20 ||
       !out->s40 || !out->scalars)
     return fail(FRSD_EINVAL, "null output array");
+  frsd_pk_out od;
+  if ((rc = device_view(out, &od))) return rc;
+  out = &od;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.stream_moments) rc = plan->p.precision == FRSD_F64 ? run_stream_pk<double>(plan, ws, out, s)
                                                                   : run_stream_pk<float>(plan, ws, out, s);
@@ -137,6 +208,9 @@ extern "C" int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *
   if (!out || !out->nt || !out->t0 || !out->t2 || !out->t4 || !out->b0 || !out->b2 || !out->b4 || !out->sn0 ||
       !out->sn2 || !out->sn4)
     return fail(FRSD_EINVAL, "null output array");
+  frsd_bk_out od;
+  if ((rc = device_view(out, &od))) return rc;
+  out = &od;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.precision == FRSD_F64) rc = run_bk<double>(plan, ws, out, s);
   else rc = run_bk<float>(plan, ws, out, s);

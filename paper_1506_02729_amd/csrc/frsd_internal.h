@@ -154,6 +154,11 @@ int fail(int code, const std::string &msg);
 void clear_error();
 // FRSD_EINVAL unless c is a valid catalogue (randoms need nbar)
 int check_catalog(const frsd_catalog *c, bool need_nbar, const char *what);
+// Device-visible copies of catalogues and output structs: page-locked host
+// arrays (where = FRSD_HOST) replaced by their device pointers.
+int device_view(const frsd_catalog *in, frsd_catalog *out);
+int device_view(const frsd_pk_out *in, frsd_pk_out *out);
+int device_view(const frsd_bk_out *in, frsd_bk_out *out);
 
 #define FRSD_HIP(call)                                                       \
   do {                                                                       \

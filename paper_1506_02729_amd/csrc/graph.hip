@@ -51,6 +51,17 @@ extern "C" int frsd_graph_create(frsd_plan *plan, void *ws, const frsd_catalog *
   if (do_bk && (!bk->nt || !bk->t0 || !bk->t2 || !bk->t4 || !bk->b0 || !bk->b2 || !bk->b4 || !bk->sn0 || !bk->sn2 ||
                 !bk->sn4))
     return fail(FRSD_EINVAL, "null bispectrum output array");
+  frsd_catalog gd, rd;
+  frsd_pk_out pkd;
+  frsd_bk_out bkd;
+  if ((rc = device_view(gal, &gd)) || (rc = device_view(ran, &rd)) || (rc = device_view(pk, &pkd))) return rc;
+  gal = &gd;
+  ran = &rd;
+  pk = &pkd;
+  if (do_bk) {
+    if ((rc = device_view(bk, &bkd))) return rc;
+    bk = &bkd;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!s) return fail(FRSD_EINVAL, "capture needs an explicit (non-null) stream");
   double *dyn = ws_ptr<double>(ws, plan->L.dyn);

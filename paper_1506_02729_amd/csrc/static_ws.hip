@@ -69,6 +69,17 @@ extern "C" int frsd_run_static(frsd_plan *plan, const frsd_catalog *gal, const f
   if (do_bk && (!bk->nt || !bk->t0 || !bk->t2 || !bk->t4 || !bk->b0 || !bk->b2 || !bk->b4 || !bk->sn0 || !bk->sn2 ||
                 !bk->sn4))
     return fail(FRSD_EINVAL, "null bispectrum output array");
+  frsd_catalog gd, rd;
+  frsd_pk_out pkd;
+  frsd_bk_out bkd;
+  if ((rc = device_view(gal, &gd)) || (rc = device_view(ran, &rd)) || (rc = device_view(pk, &pkd))) return rc;
+  gal = &gd;
+  ran = &rd;
+  pk = &pkd;
+  if (do_bk) {
+    if ((rc = device_view(bk, &bkd))) return rc;
+    bk = &bkd;
+  }
   void *ws = nullptr;
   if ((rc = scratch_address(&ws))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -56,19 +56,24 @@ class frsd_tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in ("tri_wg", "row_grid", "bin_blocks", "pair_batch")]
 
 
+FRSD_DEVICE, FRSD_HOST = 0, 1
+
+
 class frsd_catalog(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+                ("n", ctypes.c_int64), ("dtype", ctypes.c_int32), ("where", ctypes.c_int32)]
+
+
+PK_ARRAYS = ("n_modes", "k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "scalars", "p4b", "s22")
+BK_ARRAYS = ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4", "t220", "b4za")
 
 
 class frsd_pk_out(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_void_p) for name in
-                ("n_modes", "k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "scalars", "p4b", "s22")]
+    _fields_ = [(name, ctypes.c_void_p) for name in PK_ARRAYS] + [("where", ctypes.c_int32)]
 
 
 class frsd_bk_out(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_void_p) for name in
-                ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4", "t220", "b4za")]
+    _fields_ = [(name, ctypes.c_void_p) for name in BK_ARRAYS] + [("where", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -276,6 +281,13 @@ class Config:
         return p
 
 
+def pinned_catalog(cat: dict, dtype=torch.float64) -> dict:
+    """Copy a host catalogue (NumPy arrays) into page-locked host tensors,
+    which the library reads in place (no copy to the device)."""
+    return {key: torch.as_tensor(np.ascontiguousarray(cat[key]), dtype=dtype).pin_memory()
+            for key in ("pos", "w", "nbar")}
+
+
 def device_catalog(cat: dict | None, device, dtype=torch.float64) -> dict:
     """Copy a host catalogue (NumPy arrays) to device tensors of `dtype`."""
     if cat is None or len(cat["w"]) == 0:
@@ -295,10 +307,12 @@ def _c_catalog(cat: dict) -> frsd_catalog:
         c.pos = c.w = c.nbar = None
         c.dtype = FRSD_F64
         return c
+    host = not cat["pos"].is_cuda
     for key in ("pos", "w", "nbar"):
         t = cat[key]
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError(f"catalogue array {key} must be a contiguous device tensor")
+        if not t.is_contiguous() or t.is_cuda == host or (host and not t.is_pinned()):
+            raise ValueError(f"catalogue array {key} must be a contiguous device tensor, or all three pinned host tensors")
+    c.where = FRSD_HOST if host else FRSD_DEVICE
     dt = cat["pos"].dtype
     if dt not in (torch.float32, torch.float64) or cat["w"].dtype != dt or cat["nbar"].dtype != dt:
         raise ValueError("catalogue arrays must share one dtype, float32 or float64")
@@ -310,9 +324,13 @@ def _c_catalog(cat: dict) -> frsd_catalog:
 class Plan:
     """A plan plus its device workspace and output buffers on one GPU."""
 
-    def __init__(self, cfg: Config, device="cuda", stream: torch.cuda.Stream | None = None):
+    def __init__(self, cfg: Config, device="cuda", stream: torch.cuda.Stream | None = None,
+                 host_outputs: bool = False):
+        """host_outputs: the output arrays are page-locked host tensors that the
+        kernels write over the host link (no device-to-host copy afterwards)."""
         self.cfg = cfg
         self.device = torch.device(device)
+        self.host_outputs = host_outputs
         self.handle = frsd_plan_create(cfg.to_c())
         self.ws_bytes = frsd_plan_workspace_bytes(self.handle)
         # 256-byte alignment: over-allocate and offset
@@ -321,8 +339,9 @@ class Plan:
         self.ws_ptr = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nb = cfg.pk_nbins
-        f64 = dict(dtype=torch.float64, device=self.device)
-        self.pk_buf = {"n_modes": torch.zeros(nb, dtype=torch.int64, device=self.device)}
+        out_dev = torch.device("cpu") if host_outputs else self.device
+        f64 = dict(dtype=torch.float64, device=out_dev, pin_memory=host_outputs)
+        self.pk_buf = {"n_modes": torch.zeros(nb, dtype=torch.int64, device=out_dev, pin_memory=host_outputs)}
         for key in ("k_eff", "p0", "p2", "p4", "s00", "s20", "s40", "p4b", "s22"):
             self.pk_buf[key] = torch.zeros(nb, **f64)
         self.pk_buf["scalars"] = torch.zeros(4, **f64)
@@ -373,19 +392,21 @@ class Plan:
         rej = self.status()
         if rej:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
-        return {k: v.cpu().numpy() for k, v in out.items()}
+        return {k: v.cpu().numpy().copy() for k, v in out.items()}
 
     def pk(self) -> dict:
         o = frsd_pk_out()
-        for name, _ in frsd_pk_out._fields_:
+        for name in PK_ARRAYS:
             setattr(o, name, self.pk_buf[name].data_ptr())
+        o.where = FRSD_HOST if self.host_outputs else FRSD_DEVICE
         frsd_pk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
         return self.pk_buf
 
     def bk(self) -> dict:
         o = frsd_bk_out()
-        for name, _ in frsd_bk_out._fields_:
+        for name in BK_ARRAYS:
             setattr(o, name, self.bk_buf[name].data_ptr() if name in self.bk_buf else None)
+        o.where = FRSD_HOST if self.host_outputs else FRSD_DEVICE
         frsd_bk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
         return self.bk_buf
 
@@ -393,10 +414,11 @@ class Plan:
         """Capture one request on this plan's stream into a HIP graph.  gal and ran
         are the (capacity-sized) device buffers the replays read."""
         po, bo = frsd_pk_out(), frsd_bk_out()
-        for name, _ in frsd_pk_out._fields_:
+        for name in PK_ARRAYS:
             setattr(po, name, self.pk_buf[name].data_ptr())
-        for name, _ in frsd_bk_out._fields_:
+        for name in BK_ARRAYS:
             setattr(bo, name, self.bk_buf[name].data_ptr() if name in self.bk_buf else None)
+        po.where = bo.where = FRSD_HOST if self.host_outputs else FRSD_DEVICE
         use_bk = bispectrum and self.ntri > 0
         h = frsd_graph_create(self.handle, self.ws_ptr, _c_catalog(gal), _c_catalog(ran), alpha, po,
                               bo if use_bk else None, self.stream.cuda_stream)
@@ -416,7 +438,7 @@ class Plan:
         rej = self.status()
         if rej:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
-        return {k: v.cpu().numpy() for k, v in out.items()}
+        return {k: v.cpu().numpy().copy() for k, v in out.items()}
 
 
 class Graph:

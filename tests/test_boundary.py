@@ -155,3 +155,35 @@ def test_tuning_ranges_and_cache(tmp_path):
     assert autotune.apply(fake, str(path)) == want
     assert F.frsd_plan_get_tuning(h) == want
     F.frsd_plan_destroy(h)
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """Every struct of the header has the size and field offsets the
+    binding's ctypes mirror assumes (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_1506_02729_amd import fastrsd as F
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"frsd_params": F.frsd_params, "frsd_tuning": F.frsd_tuning, "frsd_catalog": F.frsd_catalog,
+               "frsd_pk_out": F.frsd_pk_out, "frsd_bk_out": F.frsd_bk_out}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fastrsd.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

@@ -322,3 +322,55 @@ def test_streamed_moments(gpu_lib, precision, N, order, interlace, ell_max):
             continue
         scale = np.nanmax(np.abs(full[key]))
         assert np.nanmax(np.abs(out[key] - full[key])) <= close * scale, key
+
+
+@pytest.mark.parametrize("precision,cat_dtype", [(32, "float32"), (64, "float64")])
+def test_host_catalogue_and_outputs(gpu_lib, precision, cat_dtype):
+    """Catalogues in page-locked host memory (where = FRSD_HOST, read by the
+    ingest kernels over the host link) and outputs in page-locked host
+    memory: the oracle's results, and the device path's on the same plan
+    shape (within 1e-5 of the largest value for FP32, 1e-11 for FP64), on
+    the plain path and on the random cache.  Pageable host arrays are
+    refused with FRSD_EINVAL."""
+    import torch
+    _log(f"case: host catalogue and outputs precision={precision} catalogue {cat_dtype}")
+    dev = torch.device("cuda:0")
+    dt = getattr(torch, cat_dtype)
+    gal, ran, alpha, prm = _bk_case(191, N=48, nbk=5, n_gal=4000, n_ran=20000)
+    cfg = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    gh, rh = gpu_lib.pinned_catalog(gal, dt), gpu_lib.pinned_catalog(ran, dt)
+    gd, rd = gpu_lib.device_catalog(gal, dev, dt), gpu_lib.device_catalog(ran, dev, dt)
+    ref = gpu_lib.Plan(cfg, device=dev).run(gd, rd, alpha)
+    plan = gpu_lib.Plan(cfg, device=dev, host_outputs=True)
+    assert not plan.pk_buf["p0"].is_cuda and plan.pk_buf["p0"].is_pinned()
+    out = plan.run(gh, rh, alpha)
+    if cat_dtype == "float64":
+        refp, refb = _oracle(gal, ran, alpha, prm)
+        _check_pk(out, refp, prm, precision)
+        _check_bk(out, refb, prm, precision, plan)
+    close = 1e-5 if precision == 32 else 1e-11
+    np.testing.assert_array_equal(out["n_modes"], ref["n_modes"])
+    np.testing.assert_array_equal(out["bk_nt"], ref["bk_nt"])
+    for key in ("p0", "p2", "p4", "p4b", "bk_t0", "bk_t2", "bk_t4", "bk_sn0"):
+        scale = np.max(np.abs(ref[key]))
+        assert np.max(np.abs(out[key] - ref[key])) <= close * scale, key
+    # the random cache reads host randoms and host galaxies the same way
+    cfg_c = _cfg(gpu_lib, prm, precision, len(gal["w"]) + len(ran["w"]))
+    cfg_c.random_cache = True
+    cplan = gpu_lib.Plan(cfg_c, device=dev, host_outputs=True)
+    cplan.random_cache(rh)
+    outc = cplan.run_cached(gh, alpha)
+    for key in ("p0", "p2", "p4", "bk_t0"):
+        scale = np.max(np.abs(ref[key]))
+        assert np.max(np.abs(outc[key] - ref[key])) <= close * scale, key
+    # pageable host memory is not readable by the kernels: refused before any launch
+    pageable = {k: torch.as_tensor(np.ascontiguousarray(v), dtype=dt) for k, v in gal.items()
+                if k in ("pos", "w", "nbar")}
+    c = gpu_lib.frsd_catalog()
+    c.n, c.dtype, c.where = len(gal["w"]), (gpu_lib.FRSD_F32 if dt == torch.float32 else gpu_lib.FRSD_F64), \
+        gpu_lib.FRSD_HOST
+    c.pos, c.w, c.nbar = pageable["pos"].data_ptr(), pageable["w"].data_ptr(), pageable["nbar"].data_ptr()
+    with pytest.raises(gpu_lib.FrsdError) as e:
+        gpu_lib.frsd_mesh_assign(plan.handle, plan.ws_ptr, c, gpu_lib._c_catalog(rh), alpha, plan.stream.cuda_stream)
+    assert e.value.code == gpu_lib.FRSD_EINVAL
+    assert plan.status() == 0

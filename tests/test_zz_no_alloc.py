@@ -35,9 +35,9 @@ def _outputs(F, torch, plan):
     bk = {key: torch.full((plan.ntri,), np.nan, **f64)
           for key in ("nt", "t0", "t2", "t4", "b0", "b2", "b4", "sn0", "sn2", "sn4")}
     po, bo = F.frsd_pk_out(), F.frsd_bk_out()
-    for name, _ in F.frsd_pk_out._fields_:
+    for name in F.PK_ARRAYS:
         setattr(po, name, pk[name].data_ptr())
-    for name, _ in F.frsd_bk_out._fields_:
+    for name in F.BK_ARRAYS:
         setattr(bo, name, bk[name].data_ptr() if name in bk else None)
     return pk, bk, po, bo
 
