@@ -172,7 +172,7 @@ template <typename T, int LEN, int PASS> struct ShellTune {
   static constexpr bool wide =
       sizeof(T) == 4 && PASS != 0 && fft_pencils_lds<cplx_t<T>, LEN, 32>() <= (size_t)112 * 1024;
   static constexpr int nt = wide ? 1024 : (sizeof(T) == 4 ? 512 : 256);
-  static constexpr int p = wide ? 32 : (sizeof(T) == 4 ? 16 : 8);
+  static constexpr int p = wide ? 32 : fit_pencils<cplx_t<T>, LEN, (sizeof(T) == 4 ? 16 : 8)>();
 };
 
 __device__ __forceinline__ int band_index(int e, int M, int nc) {

@@ -329,6 +329,16 @@ template <typename C, int LEN, int P> constexpr size_t fft_pencils_lds() {
   return sizeof(C) * ((size_t)LEN + (size_t)P * fft_ld<LEN>());
 }
 
+// Dynamic LDS one workgroup of the compiled-length transforms may take:
+// P pencils are halved until P padded pencils and the twiddles fit.
+constexpr size_t kFftLdsBudget = 100 * 1024;
+template <typename C, int LEN, int P> constexpr int fit_pencils() {
+  if constexpr (P > 1) {
+    if (fft_pencils_lds<C, LEN, P>() > kFftLdsBudget) return fit_pencils<C, LEN, P / 2>();
+  }
+  return P;
+}
+
 // Pencil batching of the LDS transforms: P = pn / n pencils per workgroup.
 // FP32 stages 8192 complex values with 512 threads so that the strided
 // passes move rows of >= 16 consecutive complex values (>= 128 bytes).

@@ -146,8 +146,10 @@ template <typename T> struct FwdTune {
   static constexpr int p_col = sizeof(T) == 4 ? 16 : 8;
 };
 template <typename T, int LEN> constexpr int p_row() {
-  return FwdTune<T>::row_elems / LEN > 0 ? FwdTune<T>::row_elems / LEN : 1;
+  return fit_pencils<cplx_t<T>, LEN, (FwdTune<T>::row_elems / LEN > 0 ? FwdTune<T>::row_elems / LEN : 1)>();
 }
+// column pencils: 16 (FP32) or 8 (FP64), fewer where the LDS would not fit (N >= 768)
+template <typename T, int LEN> constexpr int p_col() { return fit_pencils<cplx_t<T>, LEN, FwdTune<T>::p_col>(); }
 
 // Row pass (z), persistent: a fixed grid of workgroups walks the groups of
 // P_ROW rows, slot by slot, and moves on at once from groups whose rows are
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
                                                                 const uint8_t *__restrict__ colmask,
                                                                 const uint8_t *__restrict__ xmask) {
   using C = cplx_t<T>;
-  constexpr int P = FwdTune<T>::p_col, NT = FwdTune<T>::nt_col;
+  constexpr int P = p_col<T, LEN>(), NT = FwdTune<T>::nt_col;
   constexpr long long NN = (long long)LEN * LEN;
   const int nzb = keep.nba + keep.nbb;
   const int outer_i = blockIdx.x / nzb;
@@ -271,7 +273,7 @@ template <typename T, int LEN>
 static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
                             const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid) {
   using C = cplx_t<T>;
-  constexpr int PR = p_row<T, LEN>(), PC = FwdTune<T>::p_col;
+  constexpr int PR = p_row<T, LEN>(), PC = p_col<T, LEN>();
   constexpr long long NN = (long long)LEN * LEN;
   Keep k = make_keep(LEN, PC, nmax);
   k.m2max = m2max;

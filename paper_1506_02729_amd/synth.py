@@ -85,7 +85,7 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
                    n_ran: int = 40_000_000, f: float = 0.7, seed: int = 2000,
                    r_min: float = 1150.0, r_max: float = 1750.0, cap_deg: float = 60.0,
                    observer=(-400.0, 1750.0, 1750.0), p_fkp: float = 1.0e4,
-                   ran_seed: int | None = None, make_randoms: bool = True):
+                   ran_seed: int | None = None, make_randoms: bool = True, r_smooth: float = 0.0):
     """Lognormal redshift-space mock in a shell x cap survey.
 
     G is Gaussian on an n_mesh^3 grid with power P(k) (``power_law_bump``);
@@ -98,6 +98,10 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     Constant nbar = n_gal / V_survey and w = 1 / (1 + nbar P_FKP).
     With make_randoms=False the random catalogue is returned empty (alpha is
     still N_g / n_ran, for a random catalogue drawn separately).
+    r_smooth > 0 (Mpc/h) multiplies P(k) by exp(-k^2 r_smooth^2), which keeps
+    sigma^2 finite on fine meshes: the power law alone gives sigma^2 = 2.1,
+    6.9 and 22.5 at N = 256, 512, 1024 in the 3500 Mpc/h box, and at 22.5
+    single cells hold millions of galaxies; r_smooth = 3 gives 2.6 at 1024.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N, L = n_mesh, box
@@ -112,6 +116,8 @@ def lognormal_mock(n_mesh: int = 512, box: float = 3500.0, n_gal: float = 8.0e5,
     kx, kz = _kgrid(N, L)
     k2 = kx[:, None, None] ** 2 + kx[None, :, None] ** 2 + kz[None, None, :] ** 2
     pk = power_law_bump(np.sqrt(k2))
+    if r_smooth > 0.0:
+        pk *= np.exp(-k2 * r_smooth**2)
     pk[0, 0, 0] = 0.0
     # sigma^2 over the full grid: half-grid modes 0 < nz < N/2 count twice
     mult = np.full(N // 2 + 1, 2.0)

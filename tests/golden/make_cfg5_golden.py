@@ -2,7 +2,9 @@
 
 Runs only the oracle (``oracle/``) on the seeded lognormal mock of
 ``paper_1506_02729_amd.synth.lognormal_mock`` at N = 1024 in the 3500 Mpc/h
-box (4e6 galaxies, 2e8 randoms, seed 5000): interlaced TSC, 100 bins of
+box (4e6 galaxies, 2e8 randoms, seed 5000, P(k) smoothed with
+exp(-k^2 R^2), R = 3 Mpc/h, so that the lognormal variance per cell stays
+near that of the coarser meshes): interlaced TSC, 100 bins of
 0.005 h/Mpc to k = 0.5, the monopole and quadrupole moment meshes (7 of the
 22: the oracle's 1024^3 FFTs and array passes take about a minute per moment
 on 16 cores, so the 15 rank-4 moments of P_4 would not fit one run) and the
@@ -35,10 +37,11 @@ OUT = os.path.join(HERE, "cfg5_golden.json")
 SEED = 5000
 N, BOX, N_GAL, N_RAN = 1024, 3500.0, 4.0e6, 200_000_000
 PK_DK, PK_NBINS = 0.005, 100
+R_SMOOTH = 3.0
 
 
 def mock():
-    return synth.lognormal_mock(n_mesh=N, box=BOX, n_gal=N_GAL, n_ran=N_RAN, seed=SEED)
+    return synth.lognormal_mock(n_mesh=N, box=BOX, n_gal=N_GAL, n_ran=N_RAN, seed=SEED, r_smooth=R_SMOOTH)
 
 
 def main():
@@ -65,7 +68,8 @@ def main():
         return [float(v) for v in np.asarray(a, dtype=np.float64)]
 
     res = {
-        "about": "FP64 oracle P_0, P_2, P_4b for the 1024^3 lognormal mock (seed 5000), written by make_cfg5_golden.py",
+        "about": "FP64 oracle P_0, P_2, P_4b for the 1024^3 lognormal mock (seed 5000, r_smooth 3), written by "
+                 "make_cfg5_golden.py",
         "catalog_sha256": digest, "n_gal": int(len(gal["w"])), "n_ran": int(len(ran["w"])),
         "alpha": float(alpha), "observer": [float(v) for v in observer],
         "scalars": {k: float(pk[k]) for k in ("I22", "N0", "I33", "W3")},

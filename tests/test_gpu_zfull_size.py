@@ -106,3 +106,66 @@ def test_h512_against_oracle(h512, precision):
         assert np.max(_rel(out[f"bk_sn{ell}"][idx], sn, np.max(np.abs(sn)))) < tol
     del plan
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# 1024^3: streamed moment meshes against the stored FP64 oracle results
+# (tests/golden/cfg5_golden.json, written by make_cfg5_golden.py: P_0, P_2
+# and the split hexadecapole P_4b in 100 bins of 0.005 h/Mpc).
+
+GOLDEN_1024 = os.path.join(HERE, "golden", "cfg5_golden.json")
+
+
+@pytest.fixture(scope="module")
+def mesh1024():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    with open(GOLDEN_1024) as fh:
+        gold = json.load(fh)
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_cfg5_golden as m5
+    _log("case: 1024^3 mock generation (seed 5000, r_smooth 3)")
+    gal, ran, alpha, obs, _ = m5.mock()
+    digest = synth.catalog_digest(gal, ran, alpha, obs)
+    assert digest == gold["catalog_sha256"], (
+        f"this host drew a different mock ({digest[:16]} vs stored {gold['catalog_sha256'][:16]})")
+    from paper_1506_02729_amd import fastrsd as F
+    dev = torch.device("cuda:0")
+    n_obj = len(gal["w"]) + len(ran["w"])
+    g, r = F.device_catalog(gal, dev), F.device_catalog(ran, dev)
+    del gal, ran
+    yield dict(gold=gold, F=F, m5=m5, alpha=alpha, obs=obs, n_obj=n_obj, g=g, r=r)
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [64, 32])
+def test_1024_streamed_against_oracle(mesh1024, precision):
+    """Streamed plan (two complex slots resident) at N = 1024, P_0, P_2, P_4b
+    per bin against the oracle, floors as in the small-case tests; P_4 (22
+    moments) is not in the stored results and is checked as finite."""
+    import torch
+    _log(f"case: 1024^3 streamed parity precision={precision}")
+    F, gold, m5 = mesh1024["F"], mesh1024["gold"], mesh1024["m5"]
+    tol = TOL[precision]
+    cfg = F.Config(n_grid=m5.N, box=m5.BOX, observer=mesh1024["obs"], order=3, interlace=True, compensate=True,
+                   ell_max=4, precision=precision, pk_kmin=0.0, pk_dk=m5.PK_DK, pk_nbins=m5.PK_NBINS,
+                   max_objects=mesh1024["n_obj"], stream_moments=True)
+    plan = F.Plan(cfg, device=torch.device("cuda:0"))
+    out = plan.run(mesh1024["g"], mesh1024["r"], mesh1024["alpha"], bispectrum=False)
+    pk, sc = gold["pk"], gold["scalars"]
+    nb = np.asarray(pk["n_modes"])
+    np.testing.assert_array_equal(out["n_modes"], nb)
+    np.testing.assert_allclose(out["scalars"], [sc["I22"], sc["N0"], sc["I33"], sc["W3"]], rtol=1e-12)
+    I22 = sc["I22"]
+    floors = {"P0": np.asarray(pk["S00"]) / (nb * I22), "P2": 5 * np.asarray(pk["C20"]) / (nb * I22),
+              "P4b": (17.5 * np.asarray(pk["S22"]) + 5 * np.asarray(pk["C20"]) + 3.5 * np.asarray(pk["S00"]))
+              / (nb * I22)}
+    for key, name in (("P0", "p0"), ("P2", "p2"), ("P4b", "p4b")):
+        e = _rel(out[name], np.asarray(pk[key]), floors[key])
+        _log(f"  {key}: max rel err {e.max():.3e}")
+        assert e.max() < tol, (key, e)
+    assert np.all(np.isfinite(out["p4"]))
+    del plan
+    torch.cuda.empty_cache()
