@@ -92,8 +92,12 @@ typedef struct {
                             alone (not with bk_shot_noise = 1)                      */
   int32_t stream_moments;/* 1: P_ell only, for meshes whose moment meshes do not fit at
                             once (N = 1024): the moments are gridded, transformed and
-                            accumulated into A_0, A_2, A_4 two complex slots at a time
-                            (no bispectrum, no random cache)                        */
+                            accumulated into A_0, A_2, A_4 stream_slots complex slots
+                            at a time (no bispectrum, no random cache)              */
+  int32_t stream_slots;  /* streamed plans: complex slots resident at once, each
+                            4 T N^3 bytes (T = 4 or 8: the complex mesh and its two
+                            assignment planes); 0: 2; values above the number of
+                            slots are clamped to it.  Must be 0 without stream_moments */
 } frsd_params;
 
 /* A catalogue.  pos is n x 3 interleaved (x, y, z); w and nbar have n

@@ -99,7 +99,7 @@ constexpr int kBinBlocks = 2048;       // default of the tunable bin_blocks (tun
 constexpr int kTriBlocks = 1024;
 constexpr int kTriMfmaBlocks = 1024;
 constexpr int kPairBatch = 8;   // default shell-field pairs per inverse-FFT batch
-constexpr int kStreamSlots = 2;  // complex slots gridded and transformed per pass of a streamed plan
+constexpr int kStreamSlots = 2;  // default complex slots gridded and transformed per pass of a streamed plan
 // Tunable launch parameters (frsd_plan_set_tuning); the workspace is sized for
 // the largest values so that a plan can be retuned at any time.
 constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 8;
@@ -136,6 +136,7 @@ struct frsd_plan {
   void *init_ws = nullptr;
   bool cache_ready = false;           // init_ws holds a random cache
   bool assigned_cached = false;       // the last assignment used the random cache
+  int stream_slots = 0;               // streamed plans: complex slots resident per group
   double cached_alpha = 0;            // its alpha
   // Constant tables (twiddles, bin lookups, triangle and contraction tables),
   // built on the host once per plan and copied into a workspace at init.

@@ -102,13 +102,17 @@ struct GridArgs {
 
 // Add the moment-weighted contribution s of one object to the 23
 // accumulators: q holds the rank-2 monomials of the line of sight in table
-// order (xx yy zz xy yz zx), q4 the rank-4 ones.
+// order (xx yy zz xy yz zx), q4 the rank-4 ones.  Moments below m0 (not
+// written by this pass of a streamed plan) are skipped by rank.
 template <typename T>
-__device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const T *q4, int n_ell_mom, bool has_w) {
-  acc[0] += s;
+__device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const T *q4, int n_ell_mom, bool has_w,
+                                            int m0) {
+  if (m0 == 0) acc[0] += s;
   if (n_ell_mom > 1) {
+    if (m0 < 7) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc[1 + i] += s * q[i];
+      for (int i = 0; i < 6; ++i) acc[1 + i] += s * q[i];
+    }
     if (n_ell_mom > 7) {
 #pragma unroll
       for (int i = 0; i < 15; ++i) acc[7 + i] += s * q4[i];
@@ -154,12 +158,14 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
 // The same sum with the rank-4 monomials taken as (s q_a) q_b, a < 3: no
 // rank-4 table is held across a ring of nodes.
 __device__ __forceinline__ void add_moments_u(float *acc, float s, float t0, const float *q, int n_ell_mom,
-                                              bool has_w) {
-  acc[0] += s;
+                                              bool has_w, int m0) {
+  if (m0 == 0) acc[0] += s;
   if (n_ell_mom > 1) {
     const float u0 = s * q[0], u1 = s * q[1], u2 = s * q[2];
-    acc[1] += u0; acc[2] += u1; acc[3] += u2;
-    acc[4] += s * q[3]; acc[5] += s * q[4]; acc[6] += s * q[5];
+    if (m0 < 7) {
+      acc[1] += u0; acc[2] += u1; acc[3] += u2;
+      acc[4] += s * q[3]; acc[5] += s * q[4]; acc[6] += s * q[5];
+    }
     if (n_ell_mom > 7) {
       // xxxx yyyy zzzz xxxy xxxz yyyx yyyz zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy
       acc[7] += u0 * q[0]; acc[8] += u1 * q[1]; acc[9] += u2 * q[2];
@@ -331,8 +337,8 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
       q4[0] = q[0] * q[0]; q4[1] = q[1] * q[1]; q4[2] = q[2] * q[2]; q4[3] = q[0] * q[3]; q4[4] = q[0] * q[5];
       q4[5] = q[1] * q[3]; q4[6] = q[1] * q[4]; q4[7] = q[2] * q[5]; q4[8] = q[2] * q[4]; q4[9] = q[0] * q[1];
       q4[10] = q[1] * q[2]; q4[11] = q[2] * q[0]; q4[12] = q[0] * q[4]; q4[13] = q[1] * q[5]; q4[14] = q[2] * q[3];
-      add_moments<T>(am, sm, r.w, q, q4, ga.n_ell_mom, has_w);
-      if (ga.interlace) add_moments<T>(at, stw, r.w, q, q4, ga.n_ell_mom, has_w);
+      add_moments<T>(am, sm, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
+      if (ga.interlace) add_moments<T>(at, stw, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
     }
   }
 
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   }
   __syncthreads();
   const bool has_w = ga.has_w != 0;
-  const int nmom = ga.n_ell_mom;
+  const int nmom = ga.n_ell_mom, m0 = ga.m0;
   const float ny_ = (float)ly + SH, nz_ = (float)lz + SH;  // node position relative to (Y0, Z0)
   const float nf = (float)N;
   const float oyr = (float)((double)Y0 - ga.ou[1]), ozr = (float)((double)Z0 - ga.ou[2]);
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
 #pragma unroll
         for (int q = 0; q < RING; ++q) wr[q] = r.a.w * kernel_w<float, P>(r.a.x + (float)(HI - q) - SH);
 #pragma unroll
-        for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w);
+        for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w, m0);
       }
     }
     }  // step_live

@@ -138,6 +138,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   if (p.stream_moments != 0 && p.stream_moments != 1) return fail(FRSD_EINVAL, "stream_moments must be 0 or 1");
   if (p.stream_moments && (p.bk_nbins > 0 || p.random_cache))
     return fail(FRSD_EINVAL, "stream_moments plans compute P_ell only (no bispectrum, no random cache)");
+  if (p.stream_slots < 0 || (p.stream_slots != 0 && !p.stream_moments))
+    return fail(FRSD_EINVAL, "stream_slots must be >= 0, and 0 unless stream_moments is set");
 
   frsd_plan *pl = new frsd_plan();
   pl->p = p;
@@ -230,7 +232,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.slot = take(4 * nobj);
   L.cellkey = take(4 * nobj);
   L.sorted = take(sorted_bytes(nobj, T));
-  const size_t slots_resident = p.stream_moments ? (size_t)std::min(kStreamSlots, sd.n_slot) : (size_t)sd.n_slot;
+  pl->stream_slots = p.stream_moments ? std::min(p.stream_slots > 0 ? p.stream_slots : kStreamSlots, sd.n_slot) : 0;
+  const size_t slots_resident = p.stream_moments ? (size_t)pl->stream_slots : (size_t)sd.n_slot;
   L.mesh = take(2 * T * NNN * slots_resident);
   if (p.stream_moments) L.acc = take(stream_acc_bytes(pl, T));
   if (p.random_cache) {

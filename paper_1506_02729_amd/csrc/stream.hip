@@ -2,9 +2,9 @@
 // meshes does not fit the device (e.g. N = 1024: 22 interlaced complex FP32
 // meshes would take 190 GB, twice that with the assignment planes).
 //
-// The moment meshes are gridded, transformed and consumed a group of two
-// complex slots at a time: after each group's forward FFTs, k_stream_acc adds
-// that group's part of the class sums
+// The moment meshes are gridded, transformed and consumed a group of
+// stream_slots complex slots at a time: after each group's forward FFTs,
+// k_stream_acc adds that group's part of the class sums
 //   R_0 = Q_0,  R_2 = sum_m mult_m khat^m Q_m (rank 2),  R_4 (rank 4)
 // (Sec. II.B eqs. delta2b, delta4b, with Q_m unpacked from the packed slot,
 // interlaced and compensated as in the binning kernel) into accumulators on
@@ -14,8 +14,9 @@
 // 3/8 R_0 per mode and the FP64 shell sums S_00, S_20, S_40, S_22 of P_ell
 // (Sec. III.A eqs. P0_impl-P4_impl) and P_4b.
 //
-// Resident at once: the records, two slots of assignment planes, two complex
-// slots and three accumulators of (2 n_max + 1)^2 (n_max + 1) modes.
+// Resident at once: the records, stream_slots slots of assignment planes and
+// of complex meshes (2 unless the plan asks for more), and three accumulators
+// of (2 n_max + 1)^2 (n_max + 1) modes.
 #include <algorithm>
 #include <cmath>
 
@@ -246,7 +247,7 @@ int run_stream_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const fr
   const Layout &L = pl->L;
   AccArgs a = acc_args(pl);
   const int per_slot = pl->p.interlace ? 1 : 2;          // moment positions per complex slot
-  const int pos_per_group = kStreamSlots * per_slot;
+  const int pos_per_group = pl->stream_slots * per_slot;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
   for (int p0 = 0; p0 < a.n_mom; p0 += pos_per_group) {
     const int p1 = std::min(a.n_mom, p0 + pos_per_group);

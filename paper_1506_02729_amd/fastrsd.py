@@ -48,7 +48,7 @@ class frsd_params(ctypes.Structure):
         ("bk_kmin", ctypes.c_double), ("bk_dk", ctypes.c_double), ("bk_nbins", ctypes.c_int32),
         ("bk_grid", ctypes.c_int32), ("max_objects", ctypes.c_int64),
         ("bk_ell_max", ctypes.c_int32), ("bk_shot_noise", ctypes.c_int32), ("bk_zero_area", ctypes.c_int32),
-        ("random_cache", ctypes.c_int32), ("stream_moments", ctypes.c_int32),
+        ("random_cache", ctypes.c_int32), ("stream_moments", ctypes.c_int32), ("stream_slots", ctypes.c_int32),
     ]
 
 
@@ -264,6 +264,7 @@ class Config:
     bk_zero_area: bool = False
     random_cache: bool = False
     stream_moments: bool = False
+    stream_slots: int = 0
 
     def to_c(self) -> frsd_params:
         p = frsd_params()
@@ -278,7 +279,17 @@ class Config:
         p.bk_ell_max, p.bk_shot_noise, p.bk_zero_area = self.bk_ell_max, int(self.bk_shot_noise), int(self.bk_zero_area)
         p.random_cache = int(self.random_cache)
         p.stream_moments = int(self.stream_moments)
+        p.stream_slots = int(self.stream_slots)
         return p
+
+
+def workspace_bytes(cfg: "Config") -> int:
+    """Workspace bytes a plan of this configuration needs (no device memory touched)."""
+    h = frsd_plan_create(cfg.to_c())
+    try:
+        return frsd_plan_workspace_bytes(h)
+    finally:
+        frsd_plan_destroy(h)
 
 
 def pinned_catalog(cat: dict, dtype=torch.float64) -> dict:

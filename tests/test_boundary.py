@@ -48,12 +48,23 @@ def test_plan_validation_on_host():
         dict(pk_dk=0.0), dict(box=-1.0),
         dict(bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=11),   # bk beyond Nyquist
         dict(bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=4, bk_grid=32),  # M too small
+        dict(stream_slots=2),                  # slots without stream_moments
+        dict(stream_moments=True, stream_slots=-1),
+        dict(stream_moments=True, random_cache=True),
     ]
     for change in bad:
         cfg = F.Config(**{**good.__dict__, **change})
         with pytest.raises(F.FrsdError) as ei:
             F.frsd_plan_create(cfg.to_c())
         assert ei.value.code == F.FRSD_EINVAL, change
+    # streamed plans: each resident slot adds its complex mesh and two assignment planes
+    # (4 x 4 bytes x N^3 for FP32); slots beyond the 22 of the moments are clamped
+    base = {**good.__dict__, "stream_moments": True, "ell_max": 4, "interlace": True}
+    sizes = {k: F.workspace_bytes(F.Config(**{**base, "stream_slots": k})) for k in (1, 2, 3, 22, 40)}
+    assert sizes[2] == F.workspace_bytes(F.Config(**base))
+    assert sizes[2] - sizes[1] == pytest.approx(16 * 64**3, abs=1024)
+    assert sizes[3] - sizes[2] == pytest.approx(16 * 64**3, abs=1024)
+    assert sizes[40] == sizes[22]
 
 
 def test_triangle_list_matches_oracle_rule():

@@ -298,9 +298,10 @@ def test_tuned_launch_parameters(gpu_lib, precision):
                                                                  (32, 48, 4, True, 2)])
 def test_streamed_moments(gpu_lib, precision, N, order, interlace, ell_max):
     """Plans with stream_moments: the moment meshes gridded, transformed and
-    accumulated into R_0, R_2, R_4 two complex slots at a time (the large-mesh
-    path) give the oracle's P_ell and P_4b, and the full path's on the same
-    catalogue (1e-5 of the largest value FP32, 1e-11 FP64)."""
+    accumulated into R_0, R_2, R_4 a group of complex slots at a time (the
+    large-mesh path; groups of 2 (default), 1, 5 and all slots) give the
+    oracle's P_ell and P_4b, and the full path's on the same catalogue (1e-5
+    of the largest value FP32, 1e-11 FP64)."""
     import torch
     _log(f"case: streamed moments N={N} order={order} interlace={interlace} ell_max={ell_max} precision={precision}")
     dev = torch.device("cuda:0")
@@ -312,16 +313,19 @@ def test_streamed_moments(gpu_lib, precision, N, order, interlace, ell_max):
     g, r = gpu_lib.device_catalog(gal, dev), gpu_lib.device_catalog(ran, dev)
     full = gpu_lib.Plan(cfg, device=dev).run(g, r, alpha)
     cfg.stream_moments = True
-    plan = gpu_lib.Plan(cfg, device=dev)
-    out = plan.run(g, r, alpha)
-    _check_pk(out, refp, prm, precision)
     close = 1e-5 if precision == 32 else 1e-11
-    np.testing.assert_array_equal(out["n_modes"], full["n_modes"])
-    for key in ("p0", "p2", "p4", "p4b", "s00", "s20", "s40"):
-        if np.all(np.isnan(full[key])):
-            continue
-        scale = np.nanmax(np.abs(full[key]))
-        assert np.nanmax(np.abs(out[key] - full[key])) <= close * scale, key
+    for slots in (0, 1, 5, 64):
+        cfg.stream_slots = slots
+        plan = gpu_lib.Plan(cfg, device=dev)
+        out = plan.run(g, r, alpha)
+        _check_pk(out, refp, prm, precision)
+        np.testing.assert_array_equal(out["n_modes"], full["n_modes"])
+        for key in ("p0", "p2", "p4", "p4b", "s00", "s20", "s40"):
+            if np.all(np.isnan(full[key])):
+                continue
+            scale = np.nanmax(np.abs(full[key]))
+            assert np.nanmax(np.abs(out[key] - full[key])) <= close * scale, (slots, key)
+        del plan
 
 
 @pytest.mark.parametrize("precision,cat_dtype", [(32, "float32"), (64, "float64")])
