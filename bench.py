@@ -1,8 +1,9 @@
 """Throughput of the FFT multipole estimators on one MI355X.
 
 One step = one request: a synthetic BOSS-like mock through the whole hot path:
-ingest + sort, interlaced TSC assignment of the 22 moment meshes and the
-w^2 mesh, their forward FFTs, multipole combination and binning into
+ingest + sort, interlaced TSC assignment of the 15 independent moment meshes
+(the 22 of the paper less those fixed by the trace relations) and the w^2
+mesh, their forward FFTs, multipole combination and binning into
 P_0, P_2, P_4 (60 bins to k = 0.3 h/Mpc), shell-filtered inverse FFTs on the
 M = 343 grid and the triple-product sums of B_0, B_2, B_4 over all 5416
 triangles of 37 bins of width 3 k_f up to k = 0.2 h/Mpc.  The served FP32
@@ -46,6 +47,7 @@ METRIC = "mocks/s for P_0,2,4+B_0,2,4 at 512^3 (served FP32 vs plain FP64), HBM 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30                 # calibration copy: reads and writes 1 GiB
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+N_SLOT_H512 = 16  # complex slots of an interlaced l_max = 4 plan with the w^2 plane (15 moments + F_0^w)
 KERNEL_SOURCES = {"grid": "grid.hip", "grid_twin": "grid.hip", "fft_z": "fft.hip", "fft_y": "fft.hip",
                   "fft_x": "fft.hip", "triple": "triple_mfma.hip", "bin": "pk.hip", "shell_x": "bk.hip",
                   "shell_y": "bk.hip", "shell_z": "bk.hip"}
@@ -62,7 +64,7 @@ def workload(quick: bool):
                     n_mesh=256, n_gal=2.0e5, n_ran=10_000_000, pk_dk=0.005, pk_nbins=45,
                     bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
     return dict(name="H512: lognormal mock 8.0e5 galaxies + 4.0e7 randoms in a 3500 Mpc/h box, N=512 TSC "
-                     "interlaced, 23 moment meshes, P_ell l=0,2,4 in 60 bins of 0.005 to k=0.3, B_ell l=0,2,4 "
+                     "interlaced, 16 moment meshes, P_ell l=0,2,4 in 60 bins of 0.005 to k=0.3, B_ell l=0,2,4 "
                      "over 5416 triangles of 37 bins of 3k_f to k=0.202, M=343",
                 n_mesh=512, n_gal=8.0e5, n_ran=40_000_000, pk_dk=0.005, pk_nbins=60,
                 bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=37, box=box)
@@ -427,7 +429,7 @@ def large_mesh(args, F, torch, synth, dev, log):
     n_obj = len(gal["w"]) + len(ran["w"])
     del ran
     res, outs = {}, {}
-    n_mom = 22
+    n_mom = 15
     for prec in (32, 64):
         cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
                        precision=prec, pk_kmin=0.0, pk_dk=0.005, pk_nbins=100, max_objects=n_obj,
@@ -506,7 +508,8 @@ def large_mesh(args, F, torch, synth, dev, log):
 def p4_study(args, F, torch, synth, dev, log):
     """The two hexadecapole estimators over many mocks (Sec. III.A, the
     comparison of Figs. P4LD and P4PTH, here on synthetic mocks): P_4 from the
-    22 moment meshes and the split P_4b from the 7 of the quadrupole, on the
+    moment meshes (22 in the paper, 15 independent) and the split P_4b from
+    those of the quadrupole (7, 6 independent), on the
     same catalogues.  Lognormal mocks of 2e5 galaxies (seeds 6000 + i) over
     one shared random catalogue of 1e7, 256^3 TSC interlaced, 45 bins of
     0.005 to k = 0.225.  Per bin: the bias ratio b_4 = <P_4b>/<P_4> with its
@@ -539,7 +542,7 @@ def p4_study(args, F, torch, synth, dev, log):
     b4 = m4b / m4
     b4_err = np.abs(b4) * np.sqrt((v4b / m4b**2 + v4 / m4**2 - 2 * c / (m4 * m4b)) / n)
     sel = k >= 0.02
-    return {"metric": "hexadecapole estimators P_4 (22 FFTs) vs split P_4b (7 FFTs) over synthetic mocks",
+    return {"metric": "hexadecapole estimators P_4 (all moments) vs split P_4b (quadrupole moments) over synthetic mocks",
             "mocks": n, "config": {"workload": "lognormal mocks 2e5 galaxies (seeds 6000+i) + one shared 1e7-random "
                                                "catalogue, 3500 Mpc/h box, 256^3 TSC interlaced, 45 bins of 0.005"},
             "data": "synthetic", "k": [float(v) for v in k],
@@ -858,7 +861,7 @@ def main():
     n_obj_kern = float(np.mean([len(pool[i % len(pool)][0]["w"]) for i in range(ks)])) + len(ran["w"])
     geom = plan_geometry(cfg, M)
     col, xm = live_masks([pool[0][0]["pos"], ran["pos"]], cfg.n_grid, cfg.box)
-    alg = algorithmic_traffic(geom, col, xm, n_obj_kern, 23, 3 * cfg.bk_nbins, 4)
+    alg = algorithmic_traffic(geom, col, xm, n_obj_kern, N_SLOT_H512, 3 * cfg.bk_nbins, 4)
     mfma_flops = 6.0 * n_out * M**3      # three bf16 split products of 2 flops per listed output and cell
     kernels = {}
     for k, (n, ms) in kern.items():

@@ -66,7 +66,9 @@ typedef struct {
   int32_t order;       /* mass assignment order p: 1 NGP, 2 CIC, 3 TSC, 4 PCS          */
   int32_t interlace;   /* 1: interlaced twin grid at half-cell offset (Sec. III.A)    */
   int32_t compensate;  /* 1: divide by prod_d sinc(pi n_d / N)^p                      */
-  int32_t ell_max;     /* 0, 2 or 4: multipoles computed (1, 7 or 22 moment meshes)   */
+  int32_t ell_max;     /* 0, 2 or 4: multipoles computed (1, 6 or 15 moment meshes:
+                          the 1, 7 or 22 moments of Sec. II.B less those fixed by the
+                          trace relations of a unit line of sight)                  */
   int32_t precision;   /* FRSD_F32 (served) or FRSD_F64 (plain) arithmetic            */
   double box;          /* L, box side (Mpc/h)                                         */
   double observer[3];  /* observer position in the box frame (may lie outside)        */
@@ -130,7 +132,7 @@ typedef struct {
   double *p4b;       /* optional (NULL: not written).  Split hexadecapole of Sec. II.B
                         eqs. (factorizeL4), (split), (P4fast): (35/2 S22 - 5 S20 -
                         7/2 S00) / (N_b I22) with the raw S00; needs ell_max >= 2 only
-                        (7 FFTs), NaN for ell_max 0                                  */
+                        (the quadrupole's moments), NaN for ell_max 0                */
   double *s22;       /* optional (NULL: not written).  Raw sum_b |F_2|^2              */
   int32_t where;     /* FRSD_DEVICE or FRSD_HOST, for every array above               */
 } frsd_pk_out;
@@ -195,7 +197,7 @@ int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *gal,
  * caches what depends only on the mask and grid, Sec. III.B; its randoms
  * dominate the assignment time, Sec. III.C).  Needs a plan with
  * random_cache = 1.  frsd_random_cache grids ran alone (weight +w for the
- * 22 moments, w^2 for F_0^w), transforms it and keeps the spectra and the
+ * moments, w^2 for F_0^w), transforms it and keeps the spectra and the
  * randoms' sums of nbar w^2, nbar^2 w^3, w^2, w^3 in ws.
  * frsd_mesh_assign_cached then runs steps a1-a4 on the galaxies alone; the
  * following frsd_pk_multipoles combines every mesh as F = F_gal - alpha
@@ -208,8 +210,9 @@ int frsd_random_cache(frsd_plan *plan, void *ws, const frsd_catalog *ran, void *
 int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_catalog *gal, double alpha, void *stream);
 
 /* Steps a5-a6: multipole combination and shell binning into P_0, P_2, P_4.
- * Requires a preceding frsd_mesh_assign on ws.  Also extracts the low-k
- * multipole fields that frsd_bk_multipoles uses. */
+ * Requires a preceding frsd_mesh_assign (or frsd_mesh_assign_cached) on ws
+ * and no frsd_bk_multipoles since then (FRSD_ESTATE otherwise).  Also
+ * extracts the low-k multipole fields that frsd_bk_multipoles uses. */
 int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *out, void *stream);
 
 /* Number of listed triangles and the list itself (host array of 3*ntri
@@ -224,7 +227,10 @@ int frsd_bk_grid(const frsd_plan *plan, int32_t *m);
 
 /* Steps a7-a9: shell-filtered inverse FFTs of F_0, F_2, F_4 on the M^3 grid,
  * triple-product contraction over all listed triangles and normalisation
- * (Sec. III.B).  Requires a preceding frsd_pk_multipoles on ws. */
+ * (Sec. III.B).  Requires a preceding frsd_pk_multipoles on ws.  Its shell
+ * buffers reuse the workspace's mesh region, so the next
+ * frsd_pk_multipoles needs a new assignment; it may be called again on
+ * the same assignment. */
 int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *out, void *stream);
 
 /* For callers that cannot allocate device memory (code under stream

@@ -99,6 +99,7 @@ extern "C" int frsd_plan_init(frsd_plan *plan, void *ws, size_t ws_bytes, void *
   plan->init_ws = ws;
   plan->cache_ready = false;
   plan->assigned_cached = false;
+  plan->mesh_live = false;
   return FRSD_OK;
 }
 
@@ -130,6 +131,7 @@ extern "C" int frsd_mesh_assign(frsd_plan *plan, void *ws, const frsd_catalog *g
   if (rc) return rc;
   plan->state = 2;
   plan->assigned_cached = false;
+  plan->mesh_live = true;
   return FRSD_OK;
 }
 
@@ -151,6 +153,7 @@ extern "C" int frsd_random_cache(frsd_plan *plan, void *ws, const frsd_catalog *
   if (rc) return rc;
   plan->cache_ready = true;
   plan->state = 1;  // the mesh region holds no mock
+  plan->mesh_live = false;
   return FRSD_OK;
 }
 
@@ -173,6 +176,7 @@ extern "C" int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_cat
   else rc = run_mesh_assign_cached<float>(plan, ws, gal, alpha, s);
   if (rc) return rc;
   plan->state = 2;
+  plan->mesh_live = true;
   plan->assigned_cached = true;
   plan->cached_alpha = alpha;
   return FRSD_OK;
@@ -183,6 +187,8 @@ extern "C" int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *
   int rc = check_ws(plan, ws);
   if (rc) return rc;
   if (plan->state < 2 || plan->init_ws != ws) return fail(FRSD_ESTATE, "frsd_pk_multipoles needs frsd_mesh_assign first");
+  if (!plan->mesh_live)
+    return fail(FRSD_ESTATE, "the meshes were overwritten by frsd_bk_multipoles: call frsd_mesh_assign again");
   if (!out || !out->n_modes || !out->k_eff || !out->p0 || !out->p2 || !out->p4 || !out->s00 || !out->s20 ||
       !out->s40 || !out->scalars)
     return fail(FRSD_EINVAL, "null output array");
@@ -214,6 +220,8 @@ extern "C" int frsd_bk_multipoles(frsd_plan *plan, void *ws, const frsd_bk_out *
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (plan->p.precision == FRSD_F64) rc = run_bk<double>(plan, ws, out, s);
   else rc = run_bk<float>(plan, ws, out, s);
+  // the shell buffers (and the w^2-weighted moments) may take the mesh region
+  if (plan->L.buf1 == plan->L.mesh || plan->n_wmom > 0) plan->mesh_live = false;
   return rc;
 }
 

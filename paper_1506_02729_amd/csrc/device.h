@@ -38,6 +38,38 @@ template <typename C, bool INV> __device__ __forceinline__ C cmul_mi(C a) {
 // ---------------------------------------------------------------------------
 // Wavefront (64-lane) sum of a double.
 // ---------------------------------------------------------------------------
+// Coefficients of the kept moments (IDs 0-14, see frsd_internal.h) in the
+// class sums R_2 = sum_j w_j (khat.xhat_j)^2 = sum_ab khat_a khat_b Q_ab and
+// R_4 = sum_j w_j (khat.xhat_j)^4, with the eliminated components folded in
+// through the trace relations: c2[p] for R_2 (p = 0-5), c4[p] for R_4
+// (p = 0-14).  (R_0 = Q_0.)
+template <typename T>
+__device__ __forceinline__ void class_coeffs(T hx, T hy, T hz, T *c2, T *c4) {
+  const T xx = hx * hx, yy = hy * hy, zz = hz * hz, xy = hx * hy, yz = hy * hz, zx = hz * hx;
+  const T z4 = zz * zz, zzxx = zz * xx, zzyy = zz * yy;
+  c2[0] = zz;
+  c2[1] = xx - zz;
+  c2[2] = yy - zz;
+  c2[3] = T(2) * xy;
+  c2[4] = T(2) * yz;
+  c2[5] = T(2) * zx;
+  c4[0] = z4;
+  c4[1] = T(6) * zzxx - T(2) * z4;
+  c4[2] = T(6) * zzyy - T(2) * z4;
+  c4[3] = T(12) * zz * xy;
+  c4[4] = T(4) * zz * yz;
+  c4[5] = T(4) * zz * zx;
+  c4[6] = xx * xx + z4 - T(6) * zzxx;                        // xxxx
+  c4[7] = yy * yy + z4 - T(6) * zzyy;                        // yyyy
+  c4[8] = T(4) * xx * xy - T(12) * zz * xy;                  // xxxy
+  c4[9] = T(4) * xx * zx - T(4) * zz * zx;                   // xxxz
+  c4[10] = T(4) * yy * xy - T(12) * zz * xy;                 // yyyx
+  c4[11] = T(4) * yy * yz - T(4) * zz * yz;                  // yyyz
+  c4[12] = T(6) * xx * yy + T(2) * z4 - T(6) * (zzxx + zzyy);  // xxyy
+  c4[13] = T(12) * xx * yz - T(4) * zz * yz;                 // xxyz
+  c4[14] = T(12) * yy * zx - T(4) * zz * zx;                 // yyxz
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

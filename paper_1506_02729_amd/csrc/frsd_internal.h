@@ -17,23 +17,25 @@
 namespace frsd {
 
 // ---------------------------------------------------------------------------
-// Moments.  IDs 0..21 are the monopole, the 6 independent components of the
-// rank-2 tensor and the 15 of the rank-4 tensor (Sec. II.B eqs. delta2b,
-// delta4b); ID 22 is the w^2-weighted monopole F_0^w (Sec. III.B, the
-// definition below eq. SNbisp2).
+// Moments.  The line-of-sight moments Q_ab = sum w xhat_a xhat_b and
+// Q_abcd (Sec. II.B eqs. delta2b, delta4b) of a unit vector obey the trace
+// relations sum_a Q_aa = Q_0 and sum_a Q_aabc = Q_bc, so 1 + 5 + 9 of the
+// 1 + 6 + 15 components determine the rest:
+//   Q_zz = Q_0 - Q_xx - Q_yy,
+//   Q_zzxx = Q_xx - Q_xxxx - Q_xxyy,  Q_zzyy = Q_yy - Q_xxyy - Q_yyyy,
+//   Q_zzzz = Q_zz - Q_zzxx - Q_zzyy,  Q_zzxy = Q_xy - Q_xxxy - Q_yyyx,
+//   Q_zzzy = Q_yz - Q_xxyz - Q_yyyz,  Q_zzzx = Q_zx - Q_xxxz - Q_yyxz.
+// Only the 15 kept components are gridded and transformed; the binning
+// folds the eliminated ones into the coefficients of the kept ones
+// (class_coeffs in device.h).  IDs: 0 the monopole; 1-5 xx yy xy yz zx;
+// 6-14 xxxx yyyy xxxy xxxz yyyx yyyz xxyy xxyz yyxz; 15 the w^2-weighted
+// monopole F_0^w (Sec. III.B, the definition below eq. SNbisp2).
 // ---------------------------------------------------------------------------
-constexpr int kMomW = 22;
-constexpr int kMaxMom = 23;
-constexpr int kMaxSlots = 23;
-
-// Component indices (x=0, y=1, z=2) of each moment, -1 padded, and the
-// multiplicity of the independent component in the full contraction.
-struct MomentTable {
-  int8_t idx[kMaxMom][4];
-  int8_t rank[kMaxMom];
-  float mult[kMaxMom];
-};
-const MomentTable &moment_table();
+constexpr int kMomRank2 = 6;   // moments of l_max = 2 (IDs 0-5)
+constexpr int kMomRank4 = 15;  // moments of l_max = 4 (IDs 0-14)
+constexpr int kMomW = 15;
+constexpr int kMaxMom = 16;
+constexpr int kMaxSlots = 16;
 
 // ---------------------------------------------------------------------------
 // FFT plan for one length: radix schedule (factors 8, 4, 2, 3).
@@ -129,7 +131,7 @@ struct frsd_plan {
   int n_out = 0;                      // contraction outputs (ntri * n_ell)
   int n_ell = 0;                      // multipoles in the bispectrum (1, 2 or 3)
   int bk_ell = 0;                     // highest bispectrum multipole (0, 2 or 4)
-  int n_wmom = 0;                     // w^2-weighted moments of the complete l > 0 shot noise (0, 7 or 22)
+  int n_wmom = 0;                     // w^2-weighted moments of the complete l > 0 shot noise (0, 6 or 15)
   frsd::FftLen fft_n, fft_m;
   frsd::Layout L;
   int state = 0;                      // 0 created, 1 initialised, 2 assigned, 3 pk done
@@ -137,6 +139,7 @@ struct frsd_plan {
   bool cache_ready = false;           // init_ws holds a random cache
   bool assigned_cached = false;       // the last assignment used the random cache
   int stream_slots = 0;               // streamed plans: complex slots resident per group
+  bool mesh_live = false;             // the mesh region holds the last assignment's spectra
   double cached_alpha = 0;            // its alpha
   // Constant tables (twiddles, bin lookups, triangle and contraction tables),
   // built on the host once per plan and copied into a workspace at init.

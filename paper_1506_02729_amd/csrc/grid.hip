@@ -6,8 +6,8 @@
 // interlaced twin grid, and accumulates every moment plane of both nodes in
 // registers:
 //   mesh_m(i) = sum_j t0_j T_m(xhat_j) prod_d W_p(u_jd - i_d),
-// with T_m in {1, xhat_a xhat_b, xhat_a xhat_b xhat_c xhat_d} and the w^2
-// plane of F_0^w (weight t0^2).  A workgroup owns a block of 4 x 8 x 16
+// with T_m in {1, xhat_a xhat_b, xhat_a xhat_b xhat_c xhat_d} (the 15 kept
+// components of frsd_internal.h) and the w^2 plane of F_0^w (weight t0^2).  A workgroup owns a block of 4 x 8 x 16
 // nodes; it stages the objects of every cell that can reach the block (the
 // block grown by the kernel support) in LDS, in cell order, and each thread
 // walks the contiguous runs of objects in the RW^3 cells around its node
@@ -90,7 +90,7 @@ __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
 struct GridArgs {
   int N;
-  int n_ell_mom;       // moments of the multipoles: 1, 7 or 22 (ell_max 0, 2, 4)
+  int n_ell_mom;       // moments of the multipoles: 1, 6 or 15 (ell_max 0, 2, 4)
   int has_w;           // w^2 plane present (position n_ell_mom)
   int interlace;
   int wsq;             // 1: every object weighs t0^2 (the w^2-weighted moments of F^w_l)
@@ -100,25 +100,34 @@ struct GridArgs {
   long long plane_stride;
 };
 
-// Add the moment-weighted contribution s of one object to the 23
-// accumulators: q holds the rank-2 monomials of the line of sight in table
-// order (xx yy zz xy yz zx), q4 the rank-4 ones.  Moments below m0 (not
-// written by this pass of a streamed plan) are skipped by rank.
+// Add the moment-weighted contribution s of one object to the 16
+// accumulators (the 15 kept moments of frsd_internal.h and the w^2 plane):
+// q holds the kept rank-2 monomials of the line of sight in ID order (xx yy
+// xy yz zx), q4 the kept rank-4 ones.  Moments below m0 (not written by
+// this pass of a streamed plan) are skipped by rank.
 template <typename T>
 __device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const T *q4, int n_ell_mom, bool has_w,
                                             int m0) {
   if (m0 == 0) acc[0] += s;
   if (n_ell_mom > 1) {
-    if (m0 < 7) {
+    if (m0 < kMomRank2) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) acc[1 + i] += s * q[i];
+      for (int i = 0; i < 5; ++i) acc[1 + i] += s * q[i];
     }
-    if (n_ell_mom > 7) {
+    if (n_ell_mom > kMomRank2) {
 #pragma unroll
-      for (int i = 0; i < 15; ++i) acc[7 + i] += s * q4[i];
+      for (int i = 0; i < 9; ++i) acc[kMomRank2 + i] += s * q4[i];
     }
   }
   if (has_w) acc[kMomW] += s * t0;
+}
+
+// Kept rank-4 monomials (IDs 6-14: xxxx yyyy xxxy xxxz yyyx yyyz xxyy xxyz
+// yyxz) from the kept rank-2 ones: each is xx or yy times a rank-2 monomial.
+template <typename T>
+__device__ __forceinline__ void rank4_from_rank2(const T *q, T *q4) {
+  q4[0] = q[0] * q[0]; q4[1] = q[1] * q[1]; q4[2] = q[0] * q[2]; q4[3] = q[0] * q[4]; q4[4] = q[1] * q[2];
+  q4[5] = q[1] * q[3]; q4[6] = q[0] * q[1]; q4[7] = q[0] * q[3]; q4[8] = q[1] * q[4];
 }
 
 // Node columns within reach of an object: colmask[x N + y] = 1 when some
@@ -155,24 +164,22 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
   if (threadIdx.x == 0) xmask[x] = any ? 1 : 0;
 }
 
-// The same sum with the rank-4 monomials taken as (s q_a) q_b, a < 3: no
-// rank-4 table is held across a ring of nodes.
+// The same sum with the rank-4 monomials taken as (s xx) q_b and (s yy) q_b:
+// no rank-4 table is held across a ring of nodes.
 __device__ __forceinline__ void add_moments_u(float *acc, float s, float t0, const float *q, int n_ell_mom,
                                               bool has_w, int m0) {
   if (m0 == 0) acc[0] += s;
   if (n_ell_mom > 1) {
-    const float u0 = s * q[0], u1 = s * q[1], u2 = s * q[2];
-    if (m0 < 7) {
-      acc[1] += u0; acc[2] += u1; acc[3] += u2;
-      acc[4] += s * q[3]; acc[5] += s * q[4]; acc[6] += s * q[5];
+    const float u0 = s * q[0], u1 = s * q[1];
+    if (m0 < kMomRank2) {
+      acc[1] += u0; acc[2] += u1;
+      acc[3] += s * q[2]; acc[4] += s * q[3]; acc[5] += s * q[4];
     }
-    if (n_ell_mom > 7) {
-      // xxxx yyyy zzzz xxxy xxxz yyyx yyyz zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy
-      acc[7] += u0 * q[0]; acc[8] += u1 * q[1]; acc[9] += u2 * q[2];
-      acc[10] += u0 * q[3]; acc[11] += u0 * q[5]; acc[12] += u1 * q[3];
-      acc[13] += u1 * q[4]; acc[14] += u2 * q[5]; acc[15] += u2 * q[4];
-      acc[16] += u0 * q[1]; acc[17] += u1 * q[2]; acc[18] += u2 * q[0];
-      acc[19] += u0 * q[4]; acc[20] += u1 * q[5]; acc[21] += u2 * q[3];
+    if (n_ell_mom > kMomRank2) {
+      // xxxx yyyy xxxy xxxz yyyx yyyz xxyy xxyz yyxz
+      acc[6] += u0 * q[0]; acc[7] += u1 * q[1]; acc[8] += u0 * q[2];
+      acc[9] += u0 * q[4]; acc[10] += u1 * q[2]; acc[11] += u1 * q[3];
+      acc[12] += u0 * q[1]; acc[13] += u0 * q[3]; acc[14] += u1 * q[4];
     }
   }
   if (has_w) acc[kMomW] += s * t0;
@@ -319,7 +326,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
       if (ga.interlace)
         stw = r.w * (kernel_w<T, P>(dx - T(0.5)) * kernel_w<T, P>(dy - T(0.5)) * kernel_w<T, P>(dz - T(0.5)));
       // line of sight (computed even when only the monopole is gridded)
-      T q[6], q4[15];
+      T q[5], q4[9];
       {
         T px = r.x + bxo, py = r.y + byo, pz = r.z + bzo;
         if (edge) {
@@ -330,13 +337,9 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
         const T r2 = px * px + py * py + pz * pz;
         const T ir = r2 > T(0) ? rsqrt_t(r2) : T(0);
         const T hx = px * ir, hy = py * ir, hz = pz * ir;
-        q[0] = hx * hx; q[1] = hy * hy; q[2] = hz * hz; q[3] = hx * hy; q[4] = hy * hz; q[5] = hz * hx;
+        q[0] = hx * hx; q[1] = hy * hy; q[2] = hx * hy; q[3] = hy * hz; q[4] = hz * hx;
       }
-      // rank-4 moments in table order: xxxx yyyy zzzz xxxy xxxz yyyx yyyz
-      // zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy
-      q4[0] = q[0] * q[0]; q4[1] = q[1] * q[1]; q4[2] = q[2] * q[2]; q4[3] = q[0] * q[3]; q4[4] = q[0] * q[5];
-      q4[5] = q[1] * q[3]; q4[6] = q[1] * q[4]; q4[7] = q[2] * q[5]; q4[8] = q[2] * q[4]; q4[9] = q[0] * q[1];
-      q4[10] = q[1] * q[2]; q4[11] = q[2] * q[0]; q4[12] = q[0] * q[4]; q4[13] = q[1] * q[5]; q4[14] = q[2] * q[3];
+      rank4_from_rank2(q, q4);
       add_moments<T>(am, sm, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
       if (ga.interlace) add_moments<T>(at, stw, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
     }
@@ -577,7 +580,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) 
         const float r2 = px * px + py * py + pz * pz;
         const float ir = r2 > 0.f ? rsqrt_t(r2) : 0.f;
         const float hx = px * ir, hy = py * ir, hz = pz * ir;
-        const float q[6] = {hx * hx, hy * hy, hz * hz, hx * hy, hy * hz, hz * hx};
+        const float q[5] = {hx * hx, hy * hy, hx * hy, hy * hz, hz * hx};
         float wr[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < RING; ++q) wr[q] = r.a.w * kernel_w<float, P>(r.a.x + (float)(HI - q) - SH);

@@ -5,8 +5,9 @@
 // conjugate contributions, so each half-space mode is counted twice).  For
 // every complex slot the thread reads Z(n) and Z(-n), and accumulates the
 // real-coefficient combinations needed for F_0, F_2, F_4 and F_0^w:
-//   F_2 = 3/2 sum_m mult_m khat^m Q_m - 1/2 F_0,
-//   F_4 = 35/8 sum_m mult_m khat^m Q_m - 5/2 F_2 - 7/8 F_0.
+//   R_2 = sum_ab khat_a khat_b Q_ab,  R_4 = sum_abcd khat_a khat_b khat_c khat_d Q_abcd
+// over the kept moments (class_coeffs), F_2 = 3/2 R_2 - 1/2 F_0,
+//   F_4 = 35/8 R_4 - 5/2 F_2 - 7/8 F_0.
 // Because every step after the FFT is linear with real coefficients, the
 // unpacking of the two real planes of a slot (X = [Z(n) + Z(-n)^*] / 2,
 // Y = [Z(n) - Z(-n)^*] / 2i), the interlacing 1/2 [X + exp(-i pi sum n / N) Y]
@@ -76,33 +77,28 @@ __device__ __forceinline__ void wave_run_add(int key, double *v, double *lds_bin
 // (Sec. II.B eq. P4fast).
 template <bool GEOM> struct BinValues { static constexpr int n = GEOM ? 2 : 4; };
 
-// Rank-2 and rank-4 monomials of k-hat times their multiplicities in the
-// full contraction, in moment-table order (xx yy zz xy yz zx; xxxx yyyy zzzz
-// xxxy xxxz yyyx yyyz zzzx zzzy xxyy yyzz zzxx xxyz yyxz zzxy).
-template <typename T>
-__device__ __forceinline__ void khat_monomials(T hx, T hy, T hz, T *mono) {
-  const T q[6] = {hx * hx, hy * hy, hz * hz, hx * hy, hy * hz, hz * hx};
-  mono[0] = T(1);
-  mono[1] = q[0]; mono[2] = q[1]; mono[3] = q[2];
-  mono[4] = T(2) * q[3]; mono[5] = T(2) * q[4]; mono[6] = T(2) * q[5];
-  mono[7] = q[0] * q[0]; mono[8] = q[1] * q[1]; mono[9] = q[2] * q[2];
-  mono[10] = T(4) * q[0] * q[3]; mono[11] = T(4) * q[0] * q[5]; mono[12] = T(4) * q[1] * q[3];
-  mono[13] = T(4) * q[1] * q[4]; mono[14] = T(4) * q[2] * q[5]; mono[15] = T(4) * q[2] * q[4];
-  mono[16] = T(6) * q[0] * q[1]; mono[17] = T(6) * q[1] * q[2]; mono[18] = T(6) * q[2] * q[0];
-  mono[19] = T(12) * q[0] * q[4]; mono[20] = T(12) * q[1] * q[5]; mono[21] = T(12) * q[2] * q[3];
-}
-
 // Add the moment at position p of the moment list (moments 0..n_ell-1 in
-// table order, then the w^2 moment if has_w) with Fourier values z(n), z(-n)
-// to the class sums r[cls][+-]: class 0 the monopole moment, 1 the rank-2
-// sum, 2 the rank-4 sum (each weighted by its monomial), 3 the w^2 moment.
+// ID order, then the w^2 moment if has_w) with Fourier values z(n), z(-n)
+// to the class sums r[cls][+-]: class 0 the monopole, 1 R_2, 2 R_4 (each
+// kept moment with its class_coeffs coefficient), 3 the w^2 moment.
 template <typename C, typename T, int p>
-__device__ __forceinline__ void add_position(int n_ell, int has_w, const T *mono, C zp, C zm, C (&r)[4][2]) {
+__device__ __forceinline__ void add_position(int n_ell, int has_w, const T *c2, const T *c4, C zp, C zm,
+                                             C (&r)[4][2]) {
   if (p < n_ell) {
-    constexpr int cls = p == 0 ? 0 : (p < 7 ? 1 : 2);
-    const T c = mono[p];
-    r[cls][0] = cadd(r[cls][0], cscale(zp, c));
-    r[cls][1] = cadd(r[cls][1], cscale(zm, c));
+    if (p == 0) {
+      r[0][0] = cadd(r[0][0], zp);
+      r[0][1] = cadd(r[0][1], zm);
+    }
+    if (p < kMomRank2 && n_ell > 1) {
+      const T c = c2[p < kMomRank2 ? p : 0];
+      r[1][0] = cadd(r[1][0], cscale(zp, c));
+      r[1][1] = cadd(r[1][1], cscale(zm, c));
+    }
+    if (n_ell > kMomRank2) {
+      const T c = c4[p < kMomRank4 ? p : 0];
+      r[2][0] = cadd(r[2][0], cscale(zp, c));
+      r[2][1] = cadd(r[2][1], cscale(zm, c));
+    }
   } else if (p == n_ell && has_w) {
     r[3][0] = cadd(r[3][0], zp);
     r[3][1] = cadd(r[3][1], zm);
@@ -112,12 +108,13 @@ __device__ __forceinline__ void add_position(int n_ell, int has_w, const T *mono
 // All slots of one mode, unrolled so that every position is a constant.
 template <typename C, typename T, bool IL, int... S>
 __device__ __forceinline__ void add_slots(std::integer_sequence<int, S...>, int n_slot, int n_ell, int has_w,
-                                          const T *mono, const C *zp, const C *zm, C (&rr)[4][2], C (&ri)[4][2]) {
+                                          const T *c2, const T *c4, const C *zp, const C *zm, C (&rr)[4][2],
+                                          C (&ri)[4][2]) {
   if constexpr (IL) {
-    ((S < n_slot ? add_position<C, T, S>(n_ell, has_w, mono, zp[S], zm[S], rr) : void()), ...);
+    ((S < n_slot ? add_position<C, T, S>(n_ell, has_w, c2, c4, zp[S], zm[S], rr) : void()), ...);
   } else {
-    ((S < n_slot ? add_position<C, T, 2 * S>(n_ell, has_w, mono, zp[S], zm[S], rr) : void()), ...);
-    ((S < n_slot ? add_position<C, T, 2 * S + 1>(n_ell, has_w, mono, zp[S], zm[S], ri) : void()), ...);
+    ((S < n_slot ? add_position<C, T, 2 * S>(n_ell, has_w, c2, c4, zp[S], zm[S], rr) : void()), ...);
+    ((S < n_slot ? add_position<C, T, 2 * S + 1>(n_ell, has_w, c2, c4, zp[S], zm[S], ri) : void()), ...);
   }
 }
 
@@ -218,15 +215,15 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         }
       }
       const T ik = (T)(1.0 / sqrt((double)m2));
-      T mono[kMaxMom - 1];
-      khat_monomials<T>((T)ix * ik, (T)iy * ik, (T)iz * ik, mono);
+      T c2[kMomRank2], c4[kMomRank4];
+      class_coeffs<T>((T)ix * ik, (T)iy * ik, (T)iz * ik, c2, c4);
       // class sums [class][n / -n] of the real-part and imaginary-part planes
       C rr[4][2], ri[4][2];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int q = 0; q < 2; ++q) { rr[c][q] = cmake<C>(T(0), T(0)); ri[c][q] = cmake<C>(T(0), T(0)); }
-      add_slots<C, T, IL>(std::make_integer_sequence<int, kMaxSlots>{}, a.n_slot, a.n_ell, a.has_w, mono, zp, zm,
+      add_slots<C, T, IL>(std::make_integer_sequence<int, kMaxSlots>{}, a.n_slot, a.n_ell, a.has_w, c2, c4, zp, zm,
                           rr, ri);
       // multipole combinations (Sec. II.B): F_0 = R0, F_2 = 3/2 R2 - 1/2 R0,
       // F_4 = 35/8 R4 - 15/4 R2 + 3/8 R0, and F_0^w

@@ -19,37 +19,6 @@ int fail(int code, const std::string &msg) {
 void clear_error() { g_err.clear(); }
 const char *last_error() { return g_err.c_str(); }
 
-// Moment components (Sec. II.B eqs. delta2b and delta4b); the multiplicity
-// of a component is the number of distinct orderings of its index tuple.
-const MomentTable &moment_table() {
-  static MomentTable t = [] {
-    MomentTable m{};
-    const int comp[kMaxMom][4] = {
-        {-1, -1, -1, -1},
-        {0, 0, -1, -1}, {1, 1, -1, -1}, {2, 2, -1, -1}, {0, 1, -1, -1}, {1, 2, -1, -1}, {2, 0, -1, -1},
-        {0, 0, 0, 0}, {1, 1, 1, 1}, {2, 2, 2, 2},
-        {0, 0, 0, 1}, {0, 0, 0, 2}, {1, 1, 1, 0}, {1, 1, 1, 2}, {2, 2, 2, 0}, {2, 2, 2, 1},
-        {0, 0, 1, 1}, {1, 1, 2, 2}, {2, 2, 0, 0},
-        {0, 0, 1, 2}, {1, 1, 0, 2}, {2, 2, 0, 1},
-        {-1, -1, -1, -1}};
-    for (int i = 0; i < kMaxMom; ++i) {
-      int rank = 0, cnt[3] = {0, 0, 0};
-      for (int k = 0; k < 4; ++k) {
-        m.idx[i][k] = (int8_t)comp[i][k];
-        if (comp[i][k] >= 0) { ++rank; ++cnt[comp[i][k]]; }
-      }
-      m.rank[i] = (int8_t)rank;
-      double f = 1;
-      for (int k = 2; k <= rank; ++k) f *= k;
-      for (int a = 0; a < 3; ++a)
-        for (int k = 2; k <= cnt[a]; ++k) f /= k;
-      m.mult[i] = (float)f;
-    }
-    return m;
-  }();
-  return t;
-}
-
 bool make_fft_len(int n, FftLen *out) {
   FftLen f{};
   f.n = n;
@@ -185,13 +154,13 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     pl->bk_ell = bk_ell;
     pl->n_ell = bk_ell / 2 + 1;
     pl->n_out = (int)(pl->ntri * pl->n_ell);
-    pl->n_wmom = (p.bk_shot_noise && bk_ell >= 2) ? (bk_ell == 2 ? 7 : 22) : 0;
+    pl->n_wmom = (p.bk_shot_noise && bk_ell >= 2) ? (bk_ell == 2 ? kMomRank2 : kMomRank4) : 0;
   }
 
   // moments in slot order, and their packing into complex meshes
   SlotDesc &sd = pl->slots;
   int nm = 0;
-  const int nmom_ell = p.ell_max == 0 ? 1 : (p.ell_max == 2 ? 7 : 22);
+  const int nmom_ell = p.ell_max == 0 ? 1 : (p.ell_max == 2 ? kMomRank2 : kMomRank4);
   for (int m = 0; m < nmom_ell; ++m) sd.mom_id[nm++] = m;
   if (p.bk_nbins > 0) sd.mom_id[nm++] = kMomW;
   sd.n_mom = nm;
@@ -234,13 +203,16 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.sorted = take(sorted_bytes(nobj, T));
   pl->stream_slots = p.stream_moments ? std::min(p.stream_slots > 0 ? p.stream_slots : kStreamSlots, sd.n_slot) : 0;
   const size_t slots_resident = p.stream_moments ? (size_t)pl->stream_slots : (size_t)sd.n_slot;
+  // the complex meshes and the assignment planes are adjacent: together they
+  // are the scratch region of the bispectrum call (below)
   L.mesh = take(2 * T * NNN * slots_resident);
+  L.planar = take(2 * T * NNN * slots_resident);
+  const size_t scratch_end = off;
   if (p.stream_moments) L.acc = take(stream_acc_bytes(pl, T));
   if (p.random_cache) {
     L.rcache = take(2 * T * NNN * sd.n_slot);
     L.rcache_sums = take(8 * 4);
   }
-  L.planar = take(2 * T * NNN * slots_resident);
   const int nbins_all = p.pk_nbins + p.bk_nbins;
   L.bin_part = take(8 * (size_t)kBinSums * nbins_all * kMaxBinBlocks);
   L.bin_sum = take(8 * (size_t)kBinSums * nbins_all);
@@ -252,14 +224,15 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
     const size_t buf1_bytes = 16 * npair_batch * D * D * M, buf2_bytes = 16 * npair_batch * D * M * M;
     const size_t nfield = (size_t)pl->n_ell * p.bk_nbins;
     const size_t shell_bytes = std::max(T * nfield, (size_t)8 * p.bk_nbins) * M * M * M;
-    // The planar assignment arrays are dead outside the assignment and the
-    // first FFT pass, and the shell intermediates and fields live only inside
-    // one bispectrum call (and plan init); calls on a workspace are ordered
-    // on one stream, so the shell buffers share the planar region when they
-    // fit in it.
-    const size_t planar_bytes = 2 * T * NNN * sd.n_slot;
-    if (align256(buf1_bytes) + align256(buf2_bytes) + align256(shell_bytes) <= planar_bytes) {
-      L.buf1 = L.planar;
+    // The assignment planes are dead after the first FFT pass and the
+    // complex meshes after the binning of frsd_pk_multipoles (the bispectrum
+    // reads the low-k cube); the shell intermediates and fields live only
+    // inside one bispectrum call (and plan init).  Calls on a workspace are
+    // ordered on one stream, so the shell buffers take the mesh and planar
+    // regions when they fit in them (frsd_pk_multipoles then needs a new
+    // frsd_mesh_assign).
+    if (align256(buf1_bytes) + align256(buf2_bytes) + align256(shell_bytes) <= scratch_end - L.mesh) {
+      L.buf1 = L.mesh;
       L.buf2 = L.buf1 + align256(buf1_bytes);
       L.shells = L.buf2 + align256(buf2_bytes);
     } else {

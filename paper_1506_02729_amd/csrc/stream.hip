@@ -1,11 +1,12 @@
 // Streamed power-spectrum multipoles for meshes whose full set of moment
-// meshes does not fit the device (e.g. N = 1024: 22 interlaced complex FP32
-// meshes would take 190 GB, twice that with the assignment planes).
+// meshes does not fit the device (e.g. N = 1024: 15 interlaced complex FP32
+// meshes take 129 GB, twice that with the assignment planes).
 //
 // The moment meshes are gridded, transformed and consumed a group of
 // stream_slots complex slots at a time: after each group's forward FFTs,
 // k_stream_acc adds that group's part of the class sums
-//   R_0 = Q_0,  R_2 = sum_m mult_m khat^m Q_m (rank 2),  R_4 (rank 4)
+//   R_0 = Q_0,  R_2 = sum_ab khat_a khat_b Q_ab,  R_4 (rank 4), over the
+//   kept moments with their class_coeffs coefficients
 // (Sec. II.B eqs. delta2b, delta4b, with Q_m unpacked from the packed slot,
 // interlaced and compensated as in the binning kernel) into accumulators on
 // the half space of kept frequencies.  Everything after the FFT is linear, so
@@ -39,12 +40,8 @@ struct AccArgs {
   int order, interlace, compensate;
   int pos0, npos, n_mom, nslot;  // first moment position of the group, positions in it, all positions, slots
   int first;                     // the first group writes the accumulators instead of adding
-  int8_t idx[kMaxMom][4];        // component indices of every moment position (-1 padded)
-  float mult[kMaxMom];           // multiplicity of each component in the full contraction
   long long acc_stride;          // elements per accumulator
 };
-
-__device__ __forceinline__ int acc_class(int p) { return p == 0 ? 0 : (p < 7 ? 1 : 2); }
 
 // Per-axis interlacing phase exp(-i pi n / N) and inverse window, |n| <= nm.
 __device__ void axis_tables(int nm, int N, int order, int compensate, double *tcos, double *tsin, double *tiw) {
@@ -93,7 +90,8 @@ __global__ __launch_bounds__(kAccThreads) void k_stream_acc(const cplx_t<T> *__r
     const long long gp = ((long long)((ix + N) % N) * N + (iy + N) % N) * N + iz;
     const long long gm = ((long long)((N - ix) % N) * N + (N - iy) % N) * N + (N - iz) % N;
     const double ik = 1.0 / sqrt((double)m2);
-    const double kh[3] = {ix * ik, iy * ik, iz * ik};
+    double c2[kMomRank2], c4[kMomRank4];
+    class_coeffs<double>(ix * ik, iy * ik, iz * ik, c2, c4);
     const int ax = ix < 0 ? -ix : ix, ay = iy < 0 ? -iy : iy;
     double ph_re = 1.0, ph_im = 0.0, sc = 1.0;
     if (a.interlace) {
@@ -107,13 +105,21 @@ __global__ __launch_bounds__(kAccThreads) void k_stream_acc(const cplx_t<T> *__r
     }
     const double win = tiw[ax] * tiw[ay] * tiw[iz];
     double r[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    // moment p into R_0, R_2, R_4 with its class coefficients (plans with
+    // l_max = 4: every moment reaches R_4, the monopole and rank-2 ones R_2)
     auto add = [&](int p, double qr, double qi) {
-      double c = a.mult[p];
-      for (int k = 0; k < 4; ++k)
-        if (a.idx[p][k] >= 0) c *= kh[a.idx[p][k]];
-      const int cl = acc_class(p);
-      r[cl][0] += c * qr;
-      r[cl][1] += c * qi;
+      if (p == 0) {
+        r[0][0] += qr;
+        r[0][1] += qi;
+      }
+      if (p < kMomRank2 && a.n_mom > 1) {
+        r[1][0] += c2[p] * qr;
+        r[1][1] += c2[p] * qi;
+      }
+      if (a.n_mom > kMomRank2) {
+        r[2][0] += c4[p] * qr;
+        r[2][1] += c4[p] * qi;
+      }
     };
     for (int g = 0; g < a.nslot; ++g) {
       const C zp = mesh[g * slot_stride + gp], zm = mesh[g * slot_stride + gm];
@@ -223,11 +229,6 @@ static AccArgs acc_args(const frsd_plan *pl) {
   a.interlace = pl->p.interlace;
   a.compensate = pl->p.compensate;
   a.n_mom = pl->slots.n_mom;
-  const MomentTable &mt = moment_table();
-  for (int p = 0; p < kMaxMom; ++p) {
-    for (int k = 0; k < 4; ++k) a.idx[p][k] = mt.idx[p][k];
-    a.mult[p] = mt.mult[p];
-  }
   const long long side = 2LL * a.nm + 1;
   a.acc_stride = side * side * (a.nm + 1);
   return a;

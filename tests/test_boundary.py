@@ -58,13 +58,13 @@ def test_plan_validation_on_host():
             F.frsd_plan_create(cfg.to_c())
         assert ei.value.code == F.FRSD_EINVAL, change
     # streamed plans: each resident slot adds its complex mesh and two assignment planes
-    # (4 x 4 bytes x N^3 for FP32); slots beyond the 22 of the moments are clamped
+    # (4 x 4 bytes x N^3 for FP32); slots beyond the 15 of the moments are clamped
     base = {**good.__dict__, "stream_moments": True, "ell_max": 4, "interlace": True}
-    sizes = {k: F.workspace_bytes(F.Config(**{**base, "stream_slots": k})) for k in (1, 2, 3, 22, 40)}
+    sizes = {k: F.workspace_bytes(F.Config(**{**base, "stream_slots": k})) for k in (1, 2, 3, 14, 15, 40)}
     assert sizes[2] == F.workspace_bytes(F.Config(**base))
     assert sizes[2] - sizes[1] == pytest.approx(16 * 64**3, abs=1024)
     assert sizes[3] - sizes[2] == pytest.approx(16 * 64**3, abs=1024)
-    assert sizes[40] == sizes[22]
+    assert sizes[40] == sizes[15] > sizes[14]
 
 
 def test_triangle_list_matches_oracle_rule():
@@ -111,11 +111,12 @@ def test_triangle_grid_choice():
     F.frsd_plan_destroy(h)
 
 
-def test_workspace_shares_the_planar_region():
+def test_workspace_shares_the_mesh_and_planar_regions():
     """The shell intermediates and fields (live only inside one bispectrum
-    call) share the planar assignment arrays (live only during the
-    assignment and the first FFT pass): at H512 the FP32 workspace is the
-    rest plus the larger of the two, and order 4 (PCS) plans build too."""
+    call) take the complex meshes and the planar assignment arrays (dead
+    after the binning of frsd_pk_multipoles): at H512 the FP32 workspace with
+    bispectrum bins is the P_ell-only one plus tables, the low-k cube and the
+    contraction partials, and order 4 (PCS) plans build too."""
     from paper_1506_02729_amd import fastrsd as F
     kf = 2 * math.pi / 3500.0
     base = dict(n_grid=512, box=3500.0, observer=(-400.0, 1750.0, 1750.0), precision=32, pk_dk=0.005,
@@ -126,11 +127,11 @@ def test_workspace_shares_the_planar_region():
     h = F.frsd_plan_create(F.Config(**{**base, "bk_nbins": 0}).to_c())
     without_bk = F.frsd_plan_workspace_bytes(h)
     F.frsd_plan_destroy(h)
-    planar = 2 * 4 * 512**3 * 23            # 23 complex slots of real/imaginary planes
+    meshes = 2 * 2 * 4 * 512**3 * 16         # 16 complex slots and their real/imaginary planes
     shells = 4 * 111 * 343**3                # 111 FP32 shell fields on M = 343
-    assert shells < planar
+    assert shells < meshes
     assert with_bk - without_bk < 3e9        # tables, low-k cube and contraction partials only
-    assert with_bk < 52e9
+    assert with_bk < 40e9
     h = F.frsd_plan_create(F.Config(**{**base, "order": 4}).to_c())
     F.frsd_plan_destroy(h)
 
