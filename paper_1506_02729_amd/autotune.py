@@ -29,7 +29,7 @@ CANDIDATES = {
     "tri_wg": (512, 768, 1024, 1536, 2048),
     "row_grid": (1024, 2048, 4096, 8192),
     "bin_blocks": (1024, 2048, 4096),
-    "pair_batch": (2, 4, 8),
+    "pair_batch": (2, 4, 8, 16),
 }
 AFFECTS = {
     "tri_wg": ("triple", "tri_reduce"),

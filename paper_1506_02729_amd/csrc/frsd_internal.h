@@ -104,7 +104,7 @@ constexpr int kPairBatch = 8;   // default shell-field pairs per inverse-FFT bat
 constexpr int kStreamSlots = 2;  // default complex slots gridded and transformed per pass of a streamed plan
 // Tunable launch parameters (frsd_plan_set_tuning); the workspace is sized for
 // the largest values so that a plan can be retuned at any time.
-constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 8;
+constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 16;
 
 // One constant table of a plan: bytes at host_off of the plan's host table
 // image go to workspace offset ws_off.

@@ -104,16 +104,14 @@ struct GridArgs {
 // accumulators (the 15 kept moments of frsd_internal.h and the w^2 plane):
 // q holds the kept rank-2 monomials of the line of sight in ID order (xx yy
 // xy yz zx), q4 the kept rank-4 ones.  Moments below m0 (not written by
-// this pass of a streamed plan) are skipped by rank.
+// this pass of a streamed plan) are accumulated all the same (and not
+// written): per-rank tests here cost the FP64 gather more than they save.
 template <typename T>
-__device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const T *q4, int n_ell_mom, bool has_w,
-                                            int m0) {
-  if (m0 == 0) acc[0] += s;
+__device__ __forceinline__ void add_moments(T *acc, T s, T t0, const T *q, const T *q4, int n_ell_mom, bool has_w) {
+  acc[0] += s;
   if (n_ell_mom > 1) {
-    if (m0 < kMomRank2) {
 #pragma unroll
-      for (int i = 0; i < 5; ++i) acc[1 + i] += s * q[i];
-    }
+    for (int i = 0; i < 5; ++i) acc[1 + i] += s * q[i];
     if (n_ell_mom > kMomRank2) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) acc[kMomRank2 + i] += s * q4[i];
@@ -340,8 +338,8 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
         q[0] = hx * hx; q[1] = hy * hy; q[2] = hx * hy; q[3] = hy * hz; q[4] = hz * hx;
       }
       rank4_from_rank2(q, q4);
-      add_moments<T>(am, sm, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
-      if (ga.interlace) add_moments<T>(at, stw, r.w, q, q4, ga.n_ell_mom, has_w, ga.m0);
+      add_moments<T>(am, sm, r.w, q, q4, ga.n_ell_mom, has_w);
+      if (ga.interlace) add_moments<T>(at, stw, r.w, q, q4, ga.n_ell_mom, has_w);
     }
   }
 
@@ -405,7 +403,7 @@ struct SweepRec {
 };
 
 template <int P, bool TWIN>
-__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_grid_sweep(const int *__restrict__ offs,
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_grid_sweep(const int *__restrict__ offs,
                                                           const Rec4<float> *__restrict__ recs,
                                                           const uint8_t *__restrict__ colmask,
                                                           const uint8_t *__restrict__ colocc, GridArgs ga,

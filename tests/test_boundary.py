@@ -150,7 +150,7 @@ def test_tuning_ranges_and_cache(tmp_path):
     good = {"tri_wg": 512, "row_grid": 2048, "bin_blocks": 4096, "pair_batch": 1}
     F.frsd_plan_set_tuning(h, good)
     assert F.frsd_plan_get_tuning(h) == good
-    for bad in ({"tri_wg": 4096}, {"row_grid": 100}, {"bin_blocks": 8192}, {"pair_batch": 0}, {"pair_batch": 9}):
+    for bad in ({"tri_wg": 4096}, {"row_grid": 100}, {"bin_blocks": 8192}, {"pair_batch": 0}, {"pair_batch": 17}):
         with pytest.raises(F.FrsdError) as ei:
             F.frsd_plan_set_tuning(h, dict(good, **bad))
         assert ei.value.code == F.FRSD_EINVAL
