@@ -147,7 +147,7 @@ def algorithmic_traffic(geom, col, xm, n_obj, n_slot, n_field, tb, n_batch_pairs
     """Algorithmic HBM bytes per launch of the memory-bound kernels: every
     element a pass must read or write counted once (live survey columns and
     slabs only, kept frequencies only), for an FP32 plan (tb = 4).  Shell
-    passes: the launch average over the request's batches of 8 field pairs."""
+    passes: the launch average over the request's batches of n_batch_pairs field pairs."""
     N, M, nmax, m2max = geom["N"], geom["M"], geom["nmax"], geom["m2max"]
     c = 2 * tb
     live_cols = int(col.sum())
@@ -861,7 +861,8 @@ def main():
     n_obj_kern = float(np.mean([len(pool[i % len(pool)][0]["w"]) for i in range(ks)])) + len(ran["w"])
     geom = plan_geometry(cfg, M)
     col, xm = live_masks([pool[0][0]["pos"], ran["pos"]], cfg.n_grid, cfg.box)
-    alg = algorithmic_traffic(geom, col, xm, n_obj_kern, N_SLOT_H512, 3 * cfg.bk_nbins, 4)
+    alg = algorithmic_traffic(geom, col, xm, n_obj_kern, N_SLOT_H512, 3 * cfg.bk_nbins, 4,
+                              n_batch_pairs=F.frsd_plan_get_tuning(plan.handle)["pair_batch"])
     mfma_flops = 6.0 * n_out * M**3      # three bf16 split products of 2 flops per listed output and cell
     kernels = {}
     for k, (n, ms) in kern.items():
