@@ -130,9 +130,9 @@ __device__ __forceinline__ void rank4_from_rank2(const T *q, T *q4) {
 
 // Node columns within reach of an object: colmask[x N + y] = 1 when some
 // cell column (cx, cy) with cx - x and cy - y in [LO, HI] (periodic) holds
-// an object, i.e. offs[(cx N + cy + 1) N] > offs[(cx N + cy) N] for the
-// exclusive scan offs of the cell counts (colocc[cx N + cy]); xmask[x] = 1
-// when any column of slab x is set.  One workgroup per x.
+// an object, i.e. offs[2 (cx N + cy + 1) N] > offs[2 (cx N + cy) N] for the
+// exclusive scan offs of the half-cell counts (colocc[cx N + cy]); xmask[x]
+// = 1 when any column of slab x is set.  One workgroup per x.
 template <int P>
 __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, int N, uint8_t *colmask,
                                                   uint8_t *xmask, uint8_t *colocc) {
@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
   const int x = blockIdx.x;
   int any = 0;
   for (int y = threadIdx.x; y < N; y += 256) {
-    const long long c0 = ((long long)x * N + y) * N;
-    colocc[(long long)x * N + y] = offs[c0 + N] > offs[c0] ? 1 : 0;
+    const long long c0 = 2 * ((long long)x * N + y) * N;
+    colocc[(long long)x * N + y] = offs[c0 + 2 * N] > offs[c0] ? 1 : 0;
     int m = 0;
 #pragma unroll
     for (int dx = LO; dx <= HI; ++dx) {
@@ -151,8 +151,8 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
       for (int dy = LO; dy <= HI; ++dy) {
         int cy = y + dy;
         cy += cy < 0 ? N : (cy >= N ? -N : 0);
-        const long long c0 = ((long long)cx * N + cy) * N;
-        m |= offs[c0 + N] > offs[c0] ? 1 : 0;
+        const long long c0 = 2 * ((long long)cx * N + cy) * N;
+        m |= offs[c0 + 2 * N] > offs[c0] ? 1 : 0;
       }
     }
     colmask[(long long)x * N + y] = (uint8_t)m;
@@ -222,10 +222,10 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
       cx += cx < 0 ? N : (cx >= N ? -N : 0);
       cy += cy < 0 ? N : (cy >= N ? -N : 0);
       cz += cz < 0 ? N : (cz >= N ? -N : 0);
-      const long long idx = ((long long)cx * N + cy) * N + cz;
+      const long long idx = 2 * (((long long)cx * N + cy) * N + cz);  // both halves of the cell
       const int a = offs[idx];
       gsrc[e] = a;
-      cnt[r] = offs[idx + 1] - a;
+      cnt[r] = offs[idx + 2] - a;
       mysum += cnt[r];
     }
   }
@@ -413,8 +413,13 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   constexpr int CY = kSY + RING - 1, CZ = kSZ + RING - 1, NSC = CY * CZ;
   static_assert(NSC <= kSCellsMax && RING <= 4, "slab too large");
   constexpr float SH = TWIN ? 0.5f : 0.0f;  // node offset of the pass
+  // TSC main and CIC twin nodes: the support ends mid-cell in z, where the
+  // kernel weight is zero, so the window's z run skips the far halves of
+  // its first and last cells (the records of a cell are ordered by z half)
+  constexpr bool TRIM = (P == 3 && !TWIN) || (P == 2 && TWIN);
   __shared__ SweepRec st[kSCap];
   __shared__ int cst[kSCellsMax + 1];  // staged start of each slab cell (e = iy * CZ + iz)
+  __shared__ int clo[kSCellsMax];      // records of the cell's lower z half (those come first)
   __shared__ int gsrc[kSCellsMax];     // first sorted record of each slab cell
   __shared__ int wtot[kSThreads / 64];
   __shared__ uint8_t step_live[kSStepsMax];  // slab of the step holds an object in the patch's y range
@@ -479,10 +484,11 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
         int cy = Y0 + LO + iy, cz = Z0 + LO + iz;
         cy += cy < 0 ? N : (cy >= N ? -N : 0);
         cz += cz < 0 ? N : (cz >= N ? -N : 0);
-        const long long idx = ((long long)cw * N + cy) * N + cz;
+        const long long idx = 2 * (((long long)cw * N + cy) * N + cz);
         const int a0 = offs[idx];
         gsrc[e] = a0;
-        cnt[h] = offs[idx + 1] - a0;
+        cnt[h] = offs[idx + 2] - a0;
+        if (TRIM) clo[e] = offs[idx + 1] - a0;
       }
     }
     // thread t holds cells t and t + 256: scan the 512 slots in two halves
@@ -538,11 +544,15 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
       // this thread's window: RING runs (y cells ly..ly+RING-1), each the
       // RING z cells lz..lz+RING-1; one flat stream, uniform trip count per
       // wavefront (finished threads add zero)
+      // (TRIM: from the upper half of the first cell to the lower half of
+      // the last one, the z extent of the kernel's support)
+      auto run_begin = [&](int e) { return TRIM ? cst[e] + clo[e] : cst[e]; };
+      auto run_end = [&](int e) { return TRIM ? cst[e + RING - 1] + clo[e + RING - 1] : cst[e + RING]; };
       int mine = 0;
 #pragma unroll
       for (int j = 0; j < RING; ++j) {
         const int e = (ly + j) * CZ + lz;
-        mine += max(0, min(cst[e + RING], s1) - max(cst[e], s0));
+        mine += max(0, min(run_end(e), s1) - max(run_begin(e), s0));
       }
       int trips = mine;
 #pragma unroll
@@ -552,8 +562,8 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
 #pragma unroll 1
         while (j >= je && wi < RING) {
           const int e = (ly + wi) * CZ + lz;
-          j = max(cst[e], s0) - s0;
-          je = min(cst[e + RING], s1) - s0;
+          j = max(run_begin(e), s0) - s0;
+          je = min(run_end(e), s1) - s0;
           ++wi;
         }
       };

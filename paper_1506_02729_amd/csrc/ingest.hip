@@ -3,11 +3,16 @@
 // N0true; Sec. III.B eq. Noise0).
 //
 // Pass 1 (k_count) validates every object, finds its cell floor(x / h) and
-// takes a rank inside that cell with an atomic increment of the cell count.
-// An exclusive scan of the counts gives each cell's first slot; pass 2
-// (k_scatter) re-reads the catalogue and writes the object's record at
-// offset[cell] + rank, so objects end up grouped by cell in row-major cell
-// order (x slowest, z fastest).
+// the half of the cell in z its fraction lies in, and takes a rank inside
+// that half cell with an atomic increment of its count.  An exclusive scan
+// of the counts gives each half cell's first slot; pass 2 (k_scatter)
+// re-reads the catalogue and writes the object's record at offset + rank,
+// so objects end up grouped by cell in row-major cell order (x slowest, z
+// fastest), and inside a cell those with z fraction below 1/2 first (half
+// cell 2 c_z, then 2 c_z + 1).  The offsets of cell c are offs[2 c] (first
+// record) and offs[2 c + 2] (end); offs[2 c + 1] splits the halves.  The
+// half is decided on the fraction as the record stores it (FP32 or FP64),
+// so the assignment kernels see the same split.
 #include "device.h"
 #include "frsd_internal.h"
 
@@ -27,7 +32,16 @@ __global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
 struct GeomArgs {
   double inv_h, L, ox, oy, oz;
   int N;
+  int rec_f32;  // records hold FP32 fractions
 };
+
+constexpr double kOneMinus = 1.0 - 1e-15;  // largest fraction kept in a cell
+
+// Fraction of u in cell c, clamped to [0, 1).
+__device__ __forceinline__ double cell_fraction(double u, int c) {
+  const double f = u - c;
+  return f < 0 ? 0 : (f > kOneMinus ? kOneMinus : f);
+}
 
 // Cell of an in-box position; u = x / h rounded up to N near the upper edge
 // is folded back into the last cell.
@@ -85,9 +99,11 @@ __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const 
     double x, y, z;
     const bool ok = load_pos(pos, i, g, x, y, z);
     if (ok) {
-      const int cx = cell_coord(x * g.inv_h, g.N), cy = cell_coord(y * g.inv_h, g.N),
-                cz = cell_coord(z * g.inv_h, g.N);
-      const int cell = (cx * g.N + cy) * g.N + cz;
+      const double uz = z * g.inv_h;
+      const int cx = cell_coord(x * g.inv_h, g.N), cy = cell_coord(y * g.inv_h, g.N), cz = cell_coord(uz, g.N);
+      const double fz = cell_fraction(uz, cz);
+      const int hz = g.rec_f32 ? ((float)fz >= 0.5f) : (fz >= 0.5);
+      const int cell = 2 * ((cx * g.N + cy) * g.N + cz) + hz;  // half-cell key, < 2 N^3 <= 2^31
       slot[obj_off + i] = atomicAdd(&cnt[cell], 1);
       cellkey[obj_off + i] = cell;
       const double wi = (double)w[i];
@@ -123,11 +139,7 @@ __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, cons
     const double ux = (double)pos[3 * i] * g.inv_h, uy = (double)pos[3 * i + 1] * g.inv_h,
                  uz = (double)pos[3 * i + 2] * g.inv_h;
     const int cx = cell_coord(ux, g.N), cy = cell_coord(uy, g.N), cz = cell_coord(uz, g.N);
-    const double one_minus = 1.0 - 1e-15;
-    double f0 = ux - cx, f1 = uy - cy, f2 = uz - cz;
-    f0 = f0 < 0 ? 0 : (f0 > one_minus ? one_minus : f0);
-    f1 = f1 < 0 ? 0 : (f1 > one_minus ? one_minus : f1);
-    f2 = f2 < 0 ? 0 : (f2 > one_minus ? one_minus : f2);
+    const double f0 = cell_fraction(ux, cx), f1 = cell_fraction(uy, cy), f2 = cell_fraction(uz, cz);
     const double wi = (double)w[i];
     Rec4<T> r;
     r.x = (T)f0; r.y = (T)f1; r.z = (T)f2;
@@ -310,8 +322,9 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
                     hipStream_t s, const double *dyn) {
   const Layout &L = pl->L;
   const int N = pl->N;
-  const long long ncell = (long long)N * N * N;
-  GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N};
+  const long long ncell = 2LL * N * N * N;  // half cells
+  GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N,
+             sizeof(T) == 4 ? 1 : 0};
 
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0));
   FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject)));

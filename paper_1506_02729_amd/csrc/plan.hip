@@ -193,8 +193,8 @@ extern "C" int frsd_plan_create(const frsd_params *params, frsd_plan **plan_out)
   L.scal = take(8 * 16);
   L.reject = take(8);
   L.dyn = take(8 * 4);
-  L.cnt = take(4 * (NNN + 1));
-  L.scan_blk = take(4 * ((NNN + 1 + 4095) / 4096 + 1));
+  L.cnt = take(4 * (2 * NNN + 1));  // half-cell counts / offsets
+  L.scan_blk = take(4 * ((2 * NNN + 1 + 4095) / 4096 + 1));
   L.colmask = take((size_t)N * N);
   L.xmask = take((size_t)N);
   L.colocc = take((size_t)N * N);
