@@ -200,12 +200,23 @@ void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Exclusive scan of int32 counts, in place (three kernels).
 // ---------------------------------------------------------------------------
+// Four consecutive counts from index i (16-byte aligned), zero past n.
+__device__ __forceinline__ int4 load4(const int *a, long long i, long long n) {
+  if (i + 3 < n) return *reinterpret_cast<const int4 *>(a + i);
+  int4 v = make_int4(0, 0, 0, 0);
+  if (i < n) v.x = a[i];
+  if (i + 1 < n) v.y = a[i + 1];
+  if (i + 2 < n) v.z = a[i + 2];
+  return v;
+}
+
 __global__ __launch_bounds__(256) void k_scan_reduce(const int *a, long long n, int *blk) {
   const long long base = (long long)blockIdx.x * kScanChunk;
   int s = 0;
-  for (int k = threadIdx.x; k < kScanChunk; k += 256) {
-    const long long i = base + k;
-    if (i < n) s += a[i];
+#pragma unroll
+  for (int k = 0; k < kScanChunk / 1024; ++k) {
+    const int4 v = load4(a, base + 4 * (k * 256 + (int)threadIdx.x), n);
+    s += v.x + v.y + v.z + v.w;
   }
   __shared__ int red[256];
   red[threadIdx.x] = s;
@@ -258,9 +269,9 @@ __global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb) {
   }
 }
 
-// One chunk of 4096 counts per block: coalesced through LDS (one pad word
-// per 16 so that each thread's 16 consecutive counts sit in distinct banks),
-// scanned, and written back coalesced.
+// One chunk of 4096 counts per block: read and written as 16-byte vectors
+// through LDS (one pad word per 16 so that each thread's 16 consecutive
+// counts sit in distinct banks), scanned per thread and per block.
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }
 
 __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const int *blk) {
@@ -268,9 +279,13 @@ __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const in
   __shared__ int wtot[4];
   const long long base = (long long)blockIdx.x * kScanChunk;
 #pragma unroll
-  for (int k = 0; k < kScanChunk / 256; ++k) {
-    const int e = k * 256 + threadIdx.x;
-    buf[scan_pad(e)] = base + e < n ? a[base + e] : 0;
+  for (int k = 0; k < kScanChunk / 1024; ++k) {
+    const int e = 4 * (k * 256 + (int)threadIdx.x);
+    const int4 v = load4(a, base + e, n);
+    buf[scan_pad(e)] = v.x;
+    buf[scan_pad(e + 1)] = v.y;
+    buf[scan_pad(e + 2)] = v.z;
+    buf[scan_pad(e + 3)] = v.w;
   }
   __syncthreads();
   int v[16];
@@ -289,9 +304,17 @@ __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const in
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kScanChunk / 256; ++k) {
-    const int e = k * 256 + threadIdx.x;
-    if (base + e < n) a[base + e] = buf[scan_pad(e)];
+  for (int k = 0; k < kScanChunk / 1024; ++k) {
+    const int e = 4 * (k * 256 + (int)threadIdx.x);
+    const long long i = base + e;
+    const int4 v = make_int4(buf[scan_pad(e)], buf[scan_pad(e + 1)], buf[scan_pad(e + 2)], buf[scan_pad(e + 3)]);
+    if (i + 3 < n) {
+      *reinterpret_cast<int4 *>(a + i) = v;
+    } else {
+      if (i < n) a[i] = v.x;
+      if (i + 1 < n) a[i + 1] = v.y;
+      if (i + 2 < n) a[i + 2] = v.z;
+    }
   }
 }
 
