@@ -164,11 +164,11 @@ __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, 
 
 // The same sum with the rank-4 monomials taken as (s xx) q_b and (s yy) q_b:
 // no rank-4 table is held across a ring of nodes.
-__device__ __forceinline__ void add_moments_u(float *acc, float s, float t0, const float *q, int n_ell_mom,
-                                              bool has_w, int m0) {
+template <typename T>
+__device__ __forceinline__ void add_moments_u(T *acc, T s, T t0, const T *q, int n_ell_mom, bool has_w, int m0) {
   if (m0 == 0) acc[0] += s;
   if (n_ell_mom > 1) {
-    const float u0 = s * q[0], u1 = s * q[1];
+    const T u0 = s * q[0], u1 = s * q[1];
     if (m0 < kMomRank2) {
       acc[1] += u0; acc[2] += u1;
       acc[3] += s * q[2]; acc[4] += s * q[3]; acc[5] += s * q[4];
@@ -396,28 +396,28 @@ template <> struct SweepWin<2, true> { static constexpr int LO = -1, HI = 1; };
 template <> struct SweepWin<1, false> { static constexpr int LO = -1, HI = 0; };
 template <> struct SweepWin<1, true> { static constexpr int LO = 0, HI = 0; };
 
-// Staged object: a = (x fraction in cell c, y and z relative to the patch
-// origin, t0).
-struct SweepRec {
-  float4 a;
+// Staged object: x fraction in cell c, y and z relative to the patch origin,
+// t0 (16 bytes in FP32 plans, 32 in FP64 plans).
+template <typename T> struct alignas(4 * sizeof(T)) SweepRec {
+  T x, y, z, w;
 };
 
-template <int P, bool TWIN>
-__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_grid_sweep(const int *__restrict__ offs,
-                                                          const Rec4<float> *__restrict__ recs,
-                                                          const uint8_t *__restrict__ colmask,
-                                                          const uint8_t *__restrict__ colocc, GridArgs ga,
-                                                          float *__restrict__ planar) {
+// FP32 plans run 4 waves per SIMD (128 VGPRs); FP64 plans hold twice the
+// accumulator registers and run 2.
+template <typename T, int P, bool TWIN>
+__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_grid_sweep(
+    const int *__restrict__ offs, const Rec4<T> *__restrict__ recs, const uint8_t *__restrict__ colmask,
+    const uint8_t *__restrict__ colocc, GridArgs ga, T *__restrict__ planar) {
   using Wn = SweepWin<P, TWIN>;
   constexpr int LO = Wn::LO, HI = Wn::HI, RING = HI - LO + 1;
   constexpr int CY = kSY + RING - 1, CZ = kSZ + RING - 1, NSC = CY * CZ;
   static_assert(NSC <= kSCellsMax && RING <= 4, "slab too large");
-  constexpr float SH = TWIN ? 0.5f : 0.0f;  // node offset of the pass
+  constexpr T SH = TWIN ? T(0.5) : T(0);  // node offset of the pass
   // TSC main and CIC twin nodes: the support ends mid-cell in z, where the
   // kernel weight is zero, so the window's z run skips the far halves of
   // its first and last cells (the records of a cell are ordered by z half)
   constexpr bool TRIM = (P == 3 && !TWIN) || (P == 2 && TWIN);
-  __shared__ SweepRec st[kSCap];
+  __shared__ SweepRec<T> st[kSCap];
   __shared__ int cst[kSCellsMax + 1];  // staged start of each slab cell (e = iy * CZ + iz)
   __shared__ int clo[kSCellsMax];      // records of the cell's lower z half (those come first)
   __shared__ int gsrc[kSCellsMax];     // first sorted record of each slab cell
@@ -451,19 +451,19 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
   __syncthreads();
   const bool has_w = ga.has_w != 0;
   const int nmom = ga.n_ell_mom, m0 = ga.m0;
-  const float ny_ = (float)ly + SH, nz_ = (float)lz + SH;  // node position relative to (Y0, Z0)
-  const float nf = (float)N;
-  const float oyr = (float)((double)Y0 - ga.ou[1]), ozr = (float)((double)Z0 - ga.ou[2]);
+  const T ny_ = (T)ly + SH, nz_ = (T)lz + SH;  // node position relative to (Y0, Z0)
+  const T nf = (T)N;
+  const T oyr = (T)((double)Y0 - ga.ou[1]), ozr = (T)((double)Z0 - ga.ou[2]);
   // patches whose slab crosses the periodic boundary in y or z rebuild the
   // true position of the object for the line of sight
   const bool edge = Y0 + LO < 0 || Z0 + LO < 0 || Y0 + kSY - 1 + HI >= N || Z0 + kSZ - 1 + HI >= N;
-  const float loy = (float)(-Y0), loz = (float)(-Z0), hiy = (float)(N - Y0), hiz = (float)(N - Z0);
+  const T loy = (T)(-Y0), loz = (T)(-Z0), hiy = (T)(N - Y0), hiz = (T)(N - Z0);
 
-  float acc[RING][kMaxMom];
+  T acc[RING][kMaxMom];
 #pragma unroll
   for (int r = 0; r < RING; ++r)
 #pragma unroll
-    for (int m = 0; m < kMaxMom; ++m) acc[r][m] = 0.f;
+    for (int m = 0; m < kMaxMom; ++m) acc[r][m] = T(0);
 
   const long long ps = ga.plane_stride;
 
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     constexpr int k = decltype(kc)::value;  // sidx % RING
     const int c = X0 + LO + sidx;            // cell slab (unwrapped)
     const int cw = c < 0 ? c + N : (c >= N ? c - N : c);
-    const float xo = (float)((double)cw - ga.ou[0]);
+    const T xo = (T)((double)cw - ga.ou[0]);
 
     if (step_live[sidx]) {
     // ---- slab cell table and exclusive scan of the counts ----
@@ -533,10 +533,13 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
           const int mid = (lo + hi) >> 1;
           if (cst[mid] <= i) lo = mid; else hi = mid;
         }
-        const Rec4<float> g = recs[gsrc[lo] + (i - cst[lo])];
+        const Rec4<T> g = recs[gsrc[lo] + (i - cst[lo])];
         const int iy = lo / CZ, iz = lo - iy * CZ;
-        SweepRec r;
-        r.a = make_float4(g.x, (float)(LO + iy) + g.y, (float)(LO + iz) + g.z, ga.wsq ? g.w * g.w : g.w);
+        SweepRec<T> r;
+        r.x = g.x;
+        r.y = (T)(LO + iy) + g.y;
+        r.z = (T)(LO + iz) + g.z;
+        r.w = ga.wsq ? g.w * g.w : g.w;
         st[i - s0] = r;
       }
       __syncthreads();
@@ -569,31 +572,31 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
       };
       advance();
       bool nvalid = j < je;
-      SweepRec nr = st[nvalid ? j : 0];
+      SweepRec<T> nr = st[nvalid ? j : 0];
 #pragma unroll 1
       for (int t = 0; t < trips; ++t) {
-        SweepRec r = nr;
-        if (!nvalid) r.a.w = 0.f;
+        SweepRec<T> r = nr;
+        if (!nvalid) r.w = T(0);
         j += nvalid ? 1 : 0;
         advance();
         nvalid = j < je;
         nr = st[nvalid ? j : 0];
-        const float wyz = kernel_w<float, P>(r.a.y - ny_) * kernel_w<float, P>(r.a.z - nz_);
+        const T wyz = kernel_w<T, P>(r.y - ny_) * kernel_w<T, P>(r.z - nz_);
         // line of sight from the true position
-        float px = xo + r.a.x, py = oyr + r.a.y, pz = ozr + r.a.z;
+        T px = xo + r.x, py = oyr + r.y, pz = ozr + r.z;
         if (edge) {
-          py += r.a.y < loy ? nf : (r.a.y >= hiy ? -nf : 0.f);
-          pz += r.a.z < loz ? nf : (r.a.z >= hiz ? -nf : 0.f);
+          py += r.y < loy ? nf : (r.y >= hiy ? -nf : T(0));
+          pz += r.z < loz ? nf : (r.z >= hiz ? -nf : T(0));
         }
-        const float r2 = px * px + py * py + pz * pz;
-        const float ir = r2 > 0.f ? rsqrt_t(r2) : 0.f;
-        const float hx = px * ir, hy = py * ir, hz = pz * ir;
-        const float q[5] = {hx * hx, hy * hy, hx * hy, hy * hz, hz * hx};
-        float wr[4] = {0.f, 0.f, 0.f, 0.f};
+        const T r2 = px * px + py * py + pz * pz;
+        const T ir = r2 > T(0) ? rsqrt_t(r2) : T(0);
+        const T hx = px * ir, hy = py * ir, hz = pz * ir;
+        const T q[5] = {hx * hx, hy * hy, hx * hy, hy * hz, hz * hx};
+        T wr[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int q = 0; q < RING; ++q) wr[q] = r.a.w * kernel_w<float, P>(r.a.x + (float)(HI - q) - SH);
+        for (int q = 0; q < RING; ++q) wr[q] = r.w * kernel_w<T, P>(r.x + (T)(HI - q) - SH);
 #pragma unroll
-        for (int rr = 0; rr < RING; ++rr) add_moments_u(acc[(k + rr) % RING], wyz * wr[rr], r.a.w, q, nmom, has_w, m0);
+        for (int rr = 0; rr < RING; ++rr) add_moments_u<T>(acc[(k + rr) % RING], wyz * wr[rr], r.w, q, nmom, has_w, m0);
       }
     }
     }  // step_live
@@ -601,7 +604,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     // the lowest ring node (c - HI) is complete: written when it belongs to
     // the workgroup (the first RING - 1 steps only warm the ring up), and its
     // slot is cleared for the node entering the ring at the next step
-    float *a = acc[k % RING];
+    T *a = acc[k % RING];
     if (sidx >= RING - 1) {
       const int n = X0 + sidx - (RING - 1);
       if (colmask[(long long)n * N + Y0 + ly]) {
@@ -617,11 +620,11 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(4))) 
           else __builtin_nontemporal_store(a[id], &planar[(long long)pos * ps + g]);
         }
         const int nw = nmom + (has_w ? 1 : 0) - ga.m0;
-        if (!TWIN && !ga.interlace && (nw & 1)) planar[(long long)nw * ps + g] = 0.f;
+        if (!TWIN && !ga.interlace && (nw & 1)) planar[(long long)nw * ps + g] = T(0);
       }
     }
 #pragma unroll
-    for (int m = 0; m < kMaxMom; ++m) a[m] = 0.f;
+    for (int m = 0; m < kMaxMom; ++m) a[m] = T(0);
     __syncthreads();  // slab buffers are rewritten by the next step
   };
 
@@ -654,20 +657,20 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
     FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
                                                  ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
                                                  ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
-  if constexpr (std::is_same<T, float>::value && P <= 3) {
+  if constexpr (P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
       const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
-      FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<P, false>), dim3(nblk), dim3(kSThreads), 0, s,
-                                               ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<float>>(ws, L.sorted),
+      FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk), dim3(kSThreads), 0, s,
+                                               ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
                                                ws_ptr<const uint8_t>(ws, L.colmask), ws_ptr<const uint8_t>(ws, L.colocc),
-                                               ga, ws_ptr<float>(ws, L.planar)));
+                                               ga, ws_ptr<T>(ws, L.planar)));
       if (ga.interlace)
-        FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<P, true>), dim3(nblk), dim3(kSThreads), 0, s,
+        FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<T, P, true>), dim3(nblk), dim3(kSThreads), 0, s,
                                                       ws_ptr<const int>(ws, L.cnt),
-                                                      ws_ptr<const Rec4<float>>(ws, L.sorted),
+                                                      ws_ptr<const Rec4<T>>(ws, L.sorted),
                                                       ws_ptr<const uint8_t>(ws, L.colmask),
                                                       ws_ptr<const uint8_t>(ws, L.colocc), ga,
-                                                      ws_ptr<float>(ws, L.planar)));
+                                                      ws_ptr<T>(ws, L.planar)));
       FRSD_LAUNCH_CHECK();
       return FRSD_OK;
     }

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
 #pragma unroll
     for (int q = 0; q < kXPf; ++q) {
       const int e = threadIdx.x + q * kXThreads;
-      const int fl = e >> 5, k = 2 * (e & 31);
+      const int fl = e / (kXKC / 2), k = 2 * (e % (kXKC / 2));
       float2 v = make_float2(0.f, 0.f);
       if (e < npe) {
         const float *src = f + (long long)fl * a.ncell + c0 + k;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kXThreads) void k_triple_mfma(const float *__restri
     for (int q = 0; q < kXPf; ++q) {
       const int e = threadIdx.x + q * kXThreads;
       if (e < npe) {
-        const int fl = e >> 5, k = 2 * (e & 31);
+        const int fl = e / (kXKC / 2), k = 2 * (e % (kXKC / 2));
         const int col = cmap[fl];
         if (col != 0xff) {
           bf16x2_t h, l;
