@@ -12,8 +12,9 @@
 // block grown by the kernel support) in LDS, in cell order, and each thread
 // walks the contiguous runs of objects in the RW^3 cells around its node
 // (RW = 4 for TSC: floor cells i-2..i+1 reach the main node i and i-1..i+1
-// the twin node i+1/2; RW = 5 for PCS: i-2..i+1 and i-2..i+2).  FP32 plans
-// of orders 1-3 use the x-sweep form below instead.  The line of sight of an object is rebuilt from its
+// the twin node i+1/2; RW = 5 for PCS: i-2..i+1 and i-2..i+2).  Plans of
+// orders 1-3 with N a multiple of 64 use the x-sweep form below instead.
+// The line of sight of an object is rebuilt from its
 // position and the observer (the true position, not the periodic image,
 // for blocks at the box faces).
 //
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 }
 
 // ---------------------------------------------------------------------------
-// x-sweep assignment (FP32 plans, N a multiple of 64).
+// x-sweep assignment (orders 1-3, N a multiple of 64; FP32 and FP64 plans).
 //
 // A workgroup owns a 4 (y) x 32 (z) patch of node columns and sweeps it
 // along x over 64 nodes.  At each cell slab x = c it stages the objects of
