@@ -227,20 +227,22 @@ def test_sparse_survey_region(gpu_lib, precision, order, interlace):
     _check_bk(out, refb, prm, precision, plan)
 
 
-@pytest.mark.parametrize("order,interlace", [(1, True), (2, True), (3, True), (1, False), (3, False),
-                                             (4, True), (4, False)])
-def test_fp32_assignment_orders_64(gpu_lib, order, interlace):
-    """FP32 plans on N = 64 (a multiple of 64: the x-sweep assignment for
-    orders 1-3, the gather for PCS) for every order with and without
-    interlacing, against the FP64 oracle."""
-    _log(f"case: pk+bk 64^3 FP32 order={order} interlace={interlace}")
+@pytest.mark.parametrize("precision,order,interlace", [(32, 1, True), (32, 2, True), (32, 3, True), (32, 1, False),
+                                                       (32, 3, False), (32, 4, True), (32, 4, False),
+                                                       (64, 1, True), (64, 2, True), (64, 3, True), (64, 2, False)])
+def test_fp32_assignment_orders_64(gpu_lib, precision, order, interlace):
+    """Plans on N = 64 (a multiple of 64: the x-sweep assignment for orders
+    1-3, FP32 and FP64 instantiations, with the half-cell trimming of the
+    TSC main and CIC twin windows; the gather for PCS) for every order with
+    and without interlacing, against the FP64 oracle."""
+    _log(f"case: pk+bk 64^3 precision={precision} order={order} interlace={interlace}")
     gal, ran, alpha, prm = _bk_case(41 + order, N=64, order=order, interlace=interlace, n_gal=4000, n_ran=20000)
     fields = est.multipole_fields(gal, ran, alpha, prm, with_w=True)
     refp = est.pk_multipoles(gal, ran, alpha, prm, fields=fields)
     refb = est.bk_multipoles(gal, ran, alpha, prm, fields=fields)
-    out, plan = _run_gpu(gpu_lib, prm, 32, gal, ran, alpha)
-    _check_pk(out, refp, prm, 32)
-    _check_bk(out, refb, prm, 32, plan)
+    out, plan = _run_gpu(gpu_lib, prm, precision, gal, ran, alpha)
+    _check_pk(out, refp, prm, precision)
+    _check_bk(out, refb, prm, precision, plan)
 
 
 def test_ell_max_two_and_float32_inputs(gpu_lib):
