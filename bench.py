@@ -554,6 +554,114 @@ def p4_study(args, F, torch, synth, dev, log):
                                   "sigma4_sq_mean": float(np.mean((v4b / v4)[sel]))}}
 
 
+def batch_study(args, F, torch, synth, dev, log):
+    """Small meshes of a covariance run (many mocks over one survey, Sec.
+    III.C): lognormal mocks of 2e5 galaxies (8 distinct, seeds 6000 + i,
+    cycled) against one cached catalogue of 1e7 randoms, TSC interlaced,
+    P_ell l = 0, 2, 4 in bins of 0.005 to min(0.225, 0.95 k_Nyquist), on
+    64^3, 128^3 and 256^3 meshes (FP32).  Mocks resident in HBM, outputs left
+    on the device; per mesh size the throughput of --batch-mocks mocks served
+    (a) one at a time on one plan and stream (frsd_mesh_assign_cached +
+    frsd_pk_multipoles), (b) on 3 plans with a stream each, round robin, and
+    (c) in batches of 8 and 16 requests (frsd_pk_batch, one stream: one
+    forward FFT and one binning launch per batch).  Each batched result is
+    compared with the one-at-a-time result of the same mock."""
+    box = 3500.0
+    n_ran = 10_000_000
+    n_mock = 8
+    t0 = time.perf_counter()
+    gal0, ran, alpha0, observer, _ = synth.lognormal_mock(n_mesh=256, box=box, n_gal=2.0e5, n_ran=n_ran, seed=6000)
+    mocks = [(gal0, alpha0)]
+    for i in range(1, n_mock):
+        g, _, a, _, _ = synth.lognormal_mock(n_mesh=256, box=box, n_gal=2.0e5, n_ran=n_ran, seed=6000 + i,
+                                             ran_seed=6500, make_randoms=False)
+        mocks.append((g, a))
+    log(f"batch study: {n_mock} mocks in {time.perf_counter() - t0:.0f} s")
+    r_dev = F.device_catalog(ran, dev)
+    dev_mocks = [(F.device_catalog(g, dev), a) for g, a in mocks]
+    K = args.batch_mocks
+    results = {}
+    for N in (64, 128, 256):
+        k_ny = math.pi * N / box
+        nb = int(min(0.225, 0.95 * k_ny) / 0.005)
+        cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
+                       precision=32, pk_kmin=0.0, pk_dk=0.005, pk_nbins=nb, max_objects=max(int(3e5), n_ran),
+                       random_cache=True)
+        streams = [torch.cuda.Stream(dev) for _ in range(3)]
+        plans = [F.Plan(cfg, device=dev, stream=streams[0]) for _ in range(16)]
+        side = [F.Plan(cfg, device=dev, stream=streams[k]) for k in (1, 2)]
+        for pl in plans + side:
+            pl.random_cache(r_dev)
+        torch.cuda.synchronize()
+
+        def one_at_a_time(n):
+            for i in range(n):
+                g, a = dev_mocks[i % n_mock]
+                plans[0].mesh_assign_cached(g, a)
+                plans[0].pk()
+
+        def round_robin(n):
+            rr = [plans[0]] + side
+            for i in range(n):
+                g, a = dev_mocks[i % n_mock]
+                rr[i % 3].mesh_assign_cached(g, a)
+                rr[i % 3].pk()
+
+        def batched(n, b):
+            for i0 in range(0, n, b):
+                idx = [(i0 + j) % n_mock for j in range(b)]
+                F.pk_batch(plans[:b], [dev_mocks[i][0] for i in idx], None, [dev_mocks[i][1] for i in idx])
+
+        def timed(fn, *a):
+            fn(*a)  # warm-up pass
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn(*a)
+            torch.cuda.synchronize()
+            return K / (time.perf_counter() - t)
+
+        row = {"pk_nbins": nb, "workspace_gb_per_plan": plans[0].ws_bytes / 1e9,
+               "one_at_a_time": timed(one_at_a_time, K), "three_streams": timed(round_robin, K)}
+        for b in (8, 16):
+            row[f"batch{b}"] = timed(batched, K, b)
+        # per-kernel device time per mock (library HIP events, untimed passes of 16 mocks)
+        for name, fn, a in (("one_at_a_time", one_at_a_time, (16,)), ("batch16", batched, (16, 16))):
+            F.frsd_profile(True)
+            F.frsd_profile_report()
+            fn(*a)
+            torch.cuda.synchronize()
+            rep = F.frsd_profile_report()
+            F.frsd_profile(False)
+            row[f"kernel_ms_per_mock_{name}"] = {k: round(v[1] / 16, 4) for k, v in sorted(rep.items())}
+        # batched results against one-at-a-time results of the same mocks
+        ref = []
+        for i in range(n_mock):
+            g, a = dev_mocks[i]
+            ref.append(plans[0].run_cached(g, a, bispectrum=False))
+        outs = F.run_batch(plans[:n_mock], [m[0] for m in dev_mocks], None, [m[1] for m in dev_mocks])
+        diff = 0.0
+        for i in range(n_mock):
+            for key in ("p0", "p2", "p4"):
+                diff = max(diff, float(np.max(np.abs(outs[i][key] - ref[i][key])) / np.max(np.abs(ref[i][key]))))
+        row["max_rel_diff_batch_vs_one_at_a_time"] = diff
+        for pl in plans + side:
+            assert pl.status() == 0
+        log(f"batch study N={N}: " + ", ".join(f"{k} {v:.4g}" for k, v in row.items() if not isinstance(v, dict)))
+        for k, v in row.items():
+            if isinstance(v, dict):
+                log(f"  {k}: " + ", ".join(f"{n} {t:.3f}" for n, t in v.items()))
+        results[str(N)] = row
+        del plans, side
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return {"metric": "small-mesh covariance throughput (mocks/s): one at a time vs 3 streams vs batched requests",
+            "unit": "mocks/s", "mocks_timed": K,
+            "config": {"workload": "lognormal mocks 2e5 galaxies (8 distinct, seeds 6000+i, cycled) against one "
+                                   "cached 1e7-random catalogue, 3500 Mpc/h box, TSC interlaced, P_ell l=0,2,4 in bins "
+                                   "of 0.005 to min(0.225, 0.95 k_Ny), FP32"},
+            "data": "synthetic", "results": results}
+
+
 SERVE_SIZES = (256, 384, 512)
 
 
@@ -759,6 +867,9 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the served covariance run")
     ap.add_argument("--p4-study", type=int, default=0,
                     help="run only the P_4 vs P_4b bias and variance study over this many synthetic mocks")
+    ap.add_argument("--batch-study", action="store_true",
+                    help="run only the small-mesh study: one at a time vs 3 streams vs batched requests")
+    ap.add_argument("--batch-mocks", type=int, default=64, help="batch study: mocks per timed pass")
     ap.add_argument("--large-mesh", action="store_true",
                     help="run only the 1024^3 streamed precision sweep (FP32 vs FP64 vs the stored oracle)")
     ap.add_argument("--mean-gap", type=float, default=0.5, help="served run: mean inter-arrival time (s)")
@@ -790,6 +901,9 @@ def main():
         return
     if args.large_mesh:
         print(json.dumps(large_mesh(args, F, torch, synth, dev, log)), flush=True)
+        return
+    if args.batch_study:
+        print(json.dumps(batch_study(args, F, torch, synth, dev, log)), flush=True)
         return
     if args.p4_study > 0:
         print(json.dumps(p4_study(args, F, torch, synth, dev, log)), flush=True)

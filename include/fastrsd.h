@@ -57,6 +57,7 @@ enum {
 
 enum { FRSD_F32 = 32, FRSD_F64 = 64 };
 enum { FRSD_DEVICE = 0, FRSD_HOST = 1 };  /* where an array lives */
+#define FRSD_MAX_BATCH 16  /* requests of one frsd_pk_batch call */
 
 typedef struct frsd_plan frsd_plan;
 
@@ -214,6 +215,29 @@ int frsd_mesh_assign_cached(frsd_plan *plan, void *ws, const frsd_catalog *gal, 
  * and no frsd_bk_multipoles since then (FRSD_ESTATE otherwise).  Also
  * extracts the low-k multipole fields that frsd_bk_multipoles uses. */
 int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *out, void *stream);
+
+/* Steps a1-a6 for a batch of n requests of one shape, the many-mock case of
+ * the paper's covariance use (Sec. III.C): plans[r] and workspaces[r] are n
+ * plans created with equal frsd_params, each initialised on its own
+ * workspace (distinct).  Per request the steps of frsd_mesh_assign(gal[r],
+ * ran[r], alpha[r]) up to the assignment planes (launches of their own,
+ * sized by its catalogues); then ONE forward FFT over all n requests' moment
+ * meshes and ONE binning over all n (Sec. III.A eqs. (mapFFT),
+ * (P0_impl)-(P4_impl)), so that small meshes share launches that fill the
+ * device; then P_ell into out[r].  ran == NULL: every plan holds a random
+ * cache (frsd_random_cache) and the galaxies are assigned against it, as
+ * frsd_mesh_assign_cached.  gal, ran, alpha and out are host arrays of n
+ * entries.  Results equal those of n calls of frsd_mesh_assign (or
+ * frsd_mesh_assign_cached) and frsd_pk_multipoles up to rounding order, and
+ * leave every plan in the same state as that sequence (frsd_bk_multipoles
+ * and frsd_status may follow per plan).  FRSD_EINVAL: n outside
+ * 1..FRSD_MAX_BATCH, a null pointer, plans whose parameters differ, a
+ * streamed plan, a workspace given twice; FRSD_ESTATE: a workspace not
+ * initialised by its plan, or without a random cache when ran is NULL;
+ * FRSD_ENOMEM: a catalogue beyond max_objects.  Validation covers every
+ * request before any device work.  Asynchronous on `stream`. */
+int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, int32_t n, const frsd_catalog *gal,
+                  const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, void *stream);
 
 /* Number of listed triangles and the list itself (host array of 3*ntri
  * int32: b1 >= b2 >= b3 with lo(b1) < hi(b2) + hi(b3), lexicographic). */

@@ -238,3 +238,72 @@ extern "C" int frsd_status(frsd_plan *plan, void *ws, int64_t *n_rejected, void 
   if (v) return fail(FRSD_EDOM, "objects outside [0, L)^3 or at the observer were rejected");
   return FRSD_OK;
 }
+
+// Plans of one shape: equal parameters, hence equal workspace layouts.
+static bool same_params(const frsd_params &a, const frsd_params &b) {
+  bool eq = a.n_grid == b.n_grid && a.order == b.order && a.interlace == b.interlace &&
+            a.compensate == b.compensate && a.ell_max == b.ell_max && a.precision == b.precision &&
+            a.box == b.box && a.pk_kmin == b.pk_kmin && a.pk_dk == b.pk_dk && a.pk_nbins == b.pk_nbins &&
+            a.bk_kmin == b.bk_kmin && a.bk_dk == b.bk_dk && a.bk_nbins == b.bk_nbins && a.bk_grid == b.bk_grid &&
+            a.max_objects == b.max_objects && a.bk_ell_max == b.bk_ell_max && a.bk_shot_noise == b.bk_shot_noise &&
+            a.bk_zero_area == b.bk_zero_area && a.random_cache == b.random_cache &&
+            a.stream_moments == b.stream_moments && a.stream_slots == b.stream_slots;
+  for (int d = 0; d < 3; ++d) eq = eq && a.observer[d] == b.observer[d];
+  return eq;
+}
+
+extern "C" int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, int32_t n, const frsd_catalog *gal,
+                             const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, void *stream) {
+  clear_error();
+  if (n < 1 || n > kMaxBatch) return fail(FRSD_EINVAL, "batch size must be 1..FRSD_MAX_BATCH");
+  if (!plans || !workspaces || !gal || !alpha || !out) return fail(FRSD_EINVAL, "null argument");
+  const bool cached = ran == nullptr;
+  int rc;
+  for (int r = 0; r < n; ++r) {
+    if ((rc = check_ws(plans[r], workspaces[r]))) return rc;
+    if (!same_params(plans[r]->p, plans[0]->p) || std::memcmp(&plans[r]->L, &plans[0]->L, sizeof(Layout)) != 0)
+      return fail(FRSD_EINVAL, "the plans of a batch must have equal parameters");
+    for (int q = 0; q < r; ++q)
+      if (workspaces[q] == workspaces[r] || plans[q] == plans[r])
+        return fail(FRSD_EINVAL, "a plan or workspace appears twice in the batch");
+  }
+  frsd_plan *pl0 = plans[0];
+  if (pl0->p.stream_moments) return fail(FRSD_EINVAL, "streamed plans are not batched");
+  for (int r = 0; r < n; ++r) {
+    frsd_plan *pl = plans[r];
+    if (pl->state < 1 || pl->init_ws != workspaces[r])
+      return fail(FRSD_ESTATE, "workspace not initialised by frsd_plan_init");
+    if (cached && !pl->cache_ready) return fail(FRSD_ESTATE, "a batch without randoms needs frsd_random_cache on every workspace");
+    if ((rc = check_catalog(&gal[r], false, "galaxies"))) return rc;
+    if (!cached && (rc = check_catalog(&ran[r], true, "randoms"))) return rc;
+    if (!std::isfinite(alpha[r])) return fail(FRSD_EINVAL, "alpha must be finite");
+    const int64_t nobj = gal[r].n + (cached ? 0 : ran[r].n);
+    if (nobj > pl->p.max_objects) return fail(FRSD_ENOMEM, "a catalogue exceeds max_objects of the plan");
+    if (nobj > (int64_t)0x7fffffff) return fail(FRSD_EINVAL, "more than 2^31-1 objects");
+    const frsd_pk_out &o = out[r];
+    if (!o.n_modes || !o.k_eff || !o.p0 || !o.p2 || !o.p4 || !o.s00 || !o.s20 || !o.s40 || !o.scalars)
+      return fail(FRSD_EINVAL, "null output array");
+  }
+  frsd_catalog gd[kMaxBatch], rd[kMaxBatch];
+  frsd_pk_out od[kMaxBatch];
+  for (int r = 0; r < n; ++r) {
+    if ((rc = device_view(&gal[r], &gd[r])) || (rc = device_view(&out[r], &od[r]))) return rc;
+    if (!cached && (rc = device_view(&ran[r], &rd[r]))) return rc;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f64 = pl0->p.precision == FRSD_F64;
+  rc = f64 ? run_mesh_assign_batch<double>(plans, workspaces, n, gd, cached ? nullptr : rd, alpha, s)
+           : run_mesh_assign_batch<float>(plans, workspaces, n, gd, cached ? nullptr : rd, alpha, s);
+  if (rc) return rc;
+  for (int r = 0; r < n; ++r) {
+    plans[r]->state = 2;
+    plans[r]->mesh_live = true;
+    plans[r]->assigned_cached = cached;
+    if (cached) plans[r]->cached_alpha = alpha[r];
+  }
+  rc = f64 ? run_pk_batch<double>(plans, workspaces, n, od, s, cached)
+           : run_pk_batch<float>(plans, workspaces, n, od, s, cached);
+  if (rc) return rc;
+  for (int r = 0; r < n; ++r) plans[r]->state = 3;
+  return FRSD_OK;
+}

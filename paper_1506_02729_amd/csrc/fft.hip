@@ -71,14 +71,16 @@ __device__ __forceinline__ void column_block(int b, int P, int N, const Keep &k,
 // Run-time length kernel (lengths without a compiled kernel).  AXIS 2
 // reads the planar real arrays `planar` (re, im of mesh b at arrays 2b,
 // 2b+1) and writes `data`; AXIS 1 and 0 work in place on `data`.
-// Grid: AXIS 2 (N^2 / P rows, batch); AXIS 1 (x * (nba + nbb) + column
-// block, batch); AXIS 0 (kept y * (nba + nbb) + column block, batch).
+// Grid: AXIS 2 (N^2 / P rows, mesh); AXIS 1 (x * (nba + nbb) + column
+// block, mesh); AXIS 0 (kept y * (nba + nbb) + column block, mesh), with
+// mesh = request * n_mesh + mesh of the request.
 template <typename T, int AXIS>
 __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *data, const T *planar, int N, int P,
                                                            StageList st, const cplx_t<T> *tw_g,
                                                            long long batch_stride, Keep keep,
                                                            const uint8_t *__restrict__ colmask,
-                                                           const uint8_t *__restrict__ xmask) {
+                                                           const uint8_t *__restrict__ xmask, Batch bt,
+                                                           int n_mesh) {
   using C = cplx_t<T>;
   constexpr int NT = FftTune<T>::threads;
   extern __shared__ unsigned char smem_raw[];
@@ -86,7 +88,11 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
   C *lds = tw + N;
   const int ld = N + 1;
 
-  C *mesh = data + (long long)blockIdx.y * batch_stride;
+  const int req = (int)blockIdx.y / n_mesh, mi = (int)blockIdx.y - req * n_mesh;
+  const long long dr = bt.delta[req];
+  colmask = shifted(colmask, dr);
+  xmask = shifted(xmask, dr);
+  C *mesh = shifted(data, dr) + (long long)mi * batch_stride;
   const long long NN = (long long)N * N;
 
   if (AXIS == 2) {
@@ -97,7 +103,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
     if (!__syncthreads_or(any)) return;  // every row of the block is empty
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
     const int tot = npen * N;
-    const T *re = planar + 2 * (long long)blockIdx.y * batch_stride + q0 * N;
+    const T *re = shifted(planar, dr) + 2 * (long long)mi * batch_stride + q0 * N;
     const T *im = re + batch_stride;
     for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
@@ -152,14 +158,15 @@ template <typename T, int LEN> constexpr int p_row() {
 template <typename T, int LEN> constexpr int p_col() { return fit_pencils<cplx_t<T>, LEN, FwdTune<T>::p_col>(); }
 
 // Row pass (z), persistent: a fixed grid of workgroups walks the groups of
-// P_ROW rows, slot by slot, and moves on at once from groups whose rows are
-// all empty, so the empty part of the box costs no workgroup launches.
+// P_ROW rows, mesh by mesh (every request's n_mesh meshes), and moves on at
+// once from groups whose rows are all empty, so the empty part of the box
+// costs no workgroup launches.
 
 template <typename T, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data, const T *planar,
                                                                 const cplx_t<T> *tw_g, long long batch_stride,
                                                                 Keep keep, const uint8_t *__restrict__ colmask,
-                                                                int n_batch) {
+                                                                int n_mesh, Batch bt) {
   using C = cplx_t<T>;
   constexpr int P = p_row<T, LEN>(), NT = FwdTune<T>::nt_row;
   constexpr long long NN = (long long)LEN * LEN;
@@ -169,20 +176,24 @@ __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data,
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *lds = tw + LEN;
   for (int i = threadIdx.x; i < LEN; i += NT) tw[i] = tw_g[i];
-  for (long long it = blockIdx.x; it < NG * n_batch; it += gridDim.x) {
-    const long long grp = it / n_batch;
-    const int slot = (int)(it - grp * n_batch);
+  const int n_all = n_mesh * bt.n;
+  for (long long it = blockIdx.x; it < NG * n_all; it += gridDim.x) {
+    const long long grp = it / n_all;
+    const int slot = (int)(it - grp * n_all);
+    const int req = slot / n_mesh, mi = slot - req * n_mesh;
+    const long long dr = bt.delta[req];
+    const uint8_t *cm = shifted(colmask, dr);
     const long long q0 = grp * P;
     const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
     int any = 0;
     for (int p = threadIdx.x; p < P; p += NT) {
-      live[p] = p < npen ? colmask[q0 + p] : 0;
+      live[p] = p < npen ? cm[q0 + p] : 0;
       any |= live[p];
     }
     if (!__syncthreads_or(any)) continue;  // (the barrier also publishes tw and live)
-    const T *re = planar + 2 * (long long)slot * batch_stride + q0 * LEN;
+    const T *re = shifted(planar, dr) + 2 * (long long)mi * batch_stride + q0 * LEN;
     const T *im = re + batch_stride;
-    C *dst = data + (long long)slot * batch_stride + q0 * LEN;
+    C *dst = shifted(data, dr) + (long long)mi * batch_stride + q0 * LEN;
     fft_pencils<C, LEN, P, NT, false, false>(
         lds, tw, npen,
         [&](int p, int e) {
@@ -195,14 +206,21 @@ __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data,
   }
 }
 
+// Column passes (y, x): grid (column blocks, mesh), mesh = request *
+// n_mesh + mesh of the request.
 template <typename T, int AXIS, int LEN>
 __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data, const cplx_t<T> *tw_g,
                                                                 long long batch_stride, Keep keep,
                                                                 const uint8_t *__restrict__ colmask,
-                                                                const uint8_t *__restrict__ xmask) {
+                                                                const uint8_t *__restrict__ xmask, Batch bt,
+                                                                int n_mesh) {
   using C = cplx_t<T>;
   constexpr int P = p_col<T, LEN>(), NT = FwdTune<T>::nt_col;
   constexpr long long NN = (long long)LEN * LEN;
+  const int req = (int)blockIdx.y / n_mesh, mi = (int)blockIdx.y - req * n_mesh;
+  const long long dr = bt.delta[req];
+  colmask = shifted(colmask, dr);
+  xmask = shifted(xmask, dr);
   const int nzb = keep.nba + keep.nbb;
   const int outer_i = blockIdx.x / nzb;
   int z0, npen;
@@ -230,7 +248,7 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   }
   __syncthreads();
   constexpr long long es = (AXIS == 1) ? LEN : NN;
-  C *col = data + (long long)blockIdx.y * batch_stride +
+  C *col = shifted(data, dr) + (long long)mi * batch_stride +
            ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
   // in place: every load happens in the first stage, every store in the last
   // (y pass: columns (n_y = e, n_z) outside the disc are not written; x
@@ -271,7 +289,8 @@ static Keep make_keep(int N, int P, int nmax) {
 
 template <typename T, int LEN>
 static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid) {
+                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid,
+                            const Batch &bt) {
   using C = cplx_t<T>;
   constexpr int PR = p_row<T, LEN>(), PC = p_col<T, LEN>();
   constexpr long long NN = (long long)LEN * LEN;
@@ -283,21 +302,21 @@ static int fft3d_forward_ct(const void *tw, const void *planar, void *mesh, int 
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 1, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_col<T, 0, LEN>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh_col));
   const long long bs = NN * LEN;
-  const dim3 gz((unsigned)row_grid), gy((unsigned)LEN * nzb, n_batch),
-      gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
+  const unsigned nm = (unsigned)(n_batch * bt.n);
+  const dim3 gz((unsigned)row_grid), gy((unsigned)LEN * nzb, nm), gx((unsigned)(k.ka + k.kb) * nzb, nm);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_row<T, LEN>), gz, dim3(FwdTune<T>::nt_row), sh_row, s, (C *)mesh,
-                                            (const T *)planar, (const C *)tw, bs, k, colmask, n_batch));
+                                            (const T *)planar, (const C *)tw, bs, k, colmask, n_batch, bt));
   FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_col<T, 1, LEN>), gy, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
-                                            (const C *)tw, bs, k, colmask, xmask));
+                                            (const C *)tw, bs, k, colmask, xmask, bt, n_batch));
   FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_col<T, 0, LEN>), gx, dim3(FwdTune<T>::nt_col), sh_col, s, (C *)mesh,
-                                            (const C *)tw, bs, k, colmask, xmask));
+                                            (const C *)tw, bs, k, colmask, xmask, bt, n_batch));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
 static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax,
-                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s) {
+                            const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, const Batch &bt) {
   using C = cplx_t<T>;
   const int N = f.n;
   const int P = FftTune<T>::pn / N;
@@ -310,33 +329,36 @@ static int fft3d_forward_rt(const FftLen &f, const void *tw, const void *planar,
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
   FRSD_HIP(hipFuncSetAttribute((const void *)k_fft_axis<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  const dim3 gz((unsigned)((NN + P - 1) / P), n_batch), gy((unsigned)N * nzb, n_batch),
-      gx((unsigned)(k.ka + k.kb) * nzb, n_batch);
+  const unsigned nm = (unsigned)(n_batch * bt.n);
+  const dim3 gz((unsigned)((NN + P - 1) / P), nm), gy((unsigned)N * nzb, nm), gx((unsigned)(k.ka + k.kb) * nzb, nm);
   FRSD_TIMED("fft_z", s, hipLaunchKernelGGL((k_fft_axis<T, 2>), gz, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask, bt,
+                                            n_batch));
   FRSD_TIMED("fft_y", s, hipLaunchKernelGGL((k_fft_axis<T, 1>), gy, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask, bt,
+                                            n_batch));
   FRSD_TIMED("fft_x", s, hipLaunchKernelGGL((k_fft_axis<T, 0>), gx, dim3(FftTune<T>::threads), shmem, s, (C *)mesh,
-                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask));
+                                            (const T *)planar, N, P, st, (const C *)tw, bs, k, colmask, xmask, bt,
+                                            n_batch));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid) {
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid, const Batch &bt) {
   switch (f.n) {
 #define FRSD_CASE(L) \
-  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, m2max, colmask, xmask, s, row_grid);
+  case L: return fft3d_forward_ct<T, L>(tw, planar, mesh, n_batch, nmax, m2max, colmask, xmask, s, row_grid, bt);
     FRSD_FFT_LENGTHS(FRSD_CASE)
 #undef FRSD_CASE
-    default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, colmask, xmask, s);
+    default: return fft3d_forward_rt<T>(f, tw, planar, mesh, n_batch, nmax, colmask, xmask, s, bt);
   }
 }
 
 template int fft3d_forward<float>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
-                                  const uint8_t *, hipStream_t, int);
+                                  const uint8_t *, hipStream_t, int, const Batch &);
 template int fft3d_forward<double>(const FftLen &, const void *, const void *, void *, int, int, int, const uint8_t *,
-                                   const uint8_t *, hipStream_t, int);
+                                   const uint8_t *, hipStream_t, int, const Batch &);
 
 }  // namespace frsd

@@ -106,6 +106,39 @@ constexpr int kStreamSlots = 2;  // default complex slots gridded and transforme
 // the largest values so that a plan can be retuned at any time.
 constexpr int kMaxTriWg = 2048, kMaxRowGrid = 16384, kMaxBinBlocks = 4096, kMaxPairBatch = 16;
 
+// Request batches (frsd_pk_batch): the forward FFT and the binning of up to
+// kMaxBatch requests run as one launch each.  The requests' plans have one
+// shape and so one workspace layout: a kernel takes request 0's pointers and
+// adds delta[r], the byte distance from request 0's workspace to request r's,
+// to those of the regions that belong to a request (constant tables are read
+// from request 0's workspace).  A single request is a batch of one.
+constexpr int kMaxBatch = FRSD_MAX_BATCH;
+struct Batch {
+  long long delta[kMaxBatch];
+  int n;
+};
+inline Batch batch_one() {
+  Batch b{};
+  b.n = 1;
+  return b;
+}
+inline Batch batch_of(void *const *ws, int n) {
+  Batch b{};
+  b.n = n;
+  for (int r = 0; r < n; ++r) b.delta[r] = static_cast<char *>(ws[r]) - static_cast<char *>(ws[0]);
+  return b;
+}
+// p moved by d bytes (a null p stays null: optional regions)
+template <typename P>
+__host__ __device__ __forceinline__ P *shifted(P *p, long long d) {
+  return p ? reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + d) : p;
+}
+// the same for a pointer that is never null
+template <typename P>
+__host__ __device__ __forceinline__ P *moved(P *p, long long d) {
+  return reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + d);
+}
+
 // One constant table of a plan: bytes at host_off of the plan's host table
 // image go to workspace offset ws_off.
 struct TabSeg {
@@ -213,6 +246,15 @@ int run_mesh_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal,
 // cached: the meshes hold galaxies alone, combined here with the random cache
 template <typename T>
 int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached);
+// Batches of n plans of one shape (frsd_pk_batch): per request the ingest,
+// sort and assignment, then one forward FFT over every request's meshes
+// (ran null: galaxies against each plan's random cache); one binning over
+// every request's meshes, then each request's P_ell
+template <typename T>
+int run_mesh_assign_batch(frsd_plan *const *pl, void *const *ws, int n, const frsd_catalog *gal,
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s);
+template <typename T>
+int run_pk_batch(frsd_plan *const *pl, void *const *ws, int n, const frsd_pk_out *out, hipStream_t s, bool cached);
 // streamed plans (stream.hip): moment groups accumulated into R_0, R_2, R_4
 template <typename T>
 int run_stream_assign(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
@@ -246,10 +288,13 @@ int upload_tables(frsd_plan *pl, void *ws, hipStream_t s, bool pageable);
 // (re of mesh s = array 2s, im = array 2s+1); output interleaved complex.
 // Node columns (x, y) with colmask 0 and x slabs with xmask 0 are zero in
 // every mesh: they are read as zero, never from memory.  Only modes with
-// |n|^2 <= m2max are guaranteed in the output.
+// |n|^2 <= m2max are guaranteed in the output.  With a batch of several
+// requests, planar, mesh and the masks are request 0's (each request's
+// n_batch meshes, masks from its own workspace).
 template <typename T>
 int fft3d_forward(const FftLen &f, const void *tw, const void *planar, void *mesh, int n_batch, int nmax, int m2max,
-                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid);
+                  const uint8_t *colmask, const uint8_t *xmask, hipStream_t s, int row_grid,
+                  const Batch &batch = batch_one());
 
 // Triple-product contraction on the matrix cores (triple_mfma.hip).
 bool triple_mfma_supported(const frsd_plan *pl);

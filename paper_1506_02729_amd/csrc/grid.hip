@@ -133,11 +133,17 @@ __device__ __forceinline__ void rank4_from_rank2(const T *q, T *q4) {
 // cell column (cx, cy) with cx - x and cy - y in [LO, HI] (periodic) holds
 // an object, i.e. offs[2 (cx N + cy + 1) N] > offs[2 (cx N + cy) N] for the
 // exclusive scan offs of the half-cell counts (colocc[cx N + cy]); xmask[x]
-// = 1 when any column of slab x is set.  One workgroup per x.
+// = 1 when any column of slab x is set.  One workgroup per (x, request of
+// the batch); every pointer is request 0's.
 template <int P>
 __global__ __launch_bounds__(256) void k_col_mask(const int *__restrict__ offs, int N, uint8_t *colmask,
-                                                  uint8_t *xmask, uint8_t *colocc) {
+                                                  uint8_t *xmask, uint8_t *colocc, Batch bt) {
   constexpr int LO = Win<P>::LO, HI = Win<P>::HI;
+  const long long dr = bt.delta[blockIdx.y];
+  offs = shifted(offs, dr);
+  colmask = shifted(colmask, dr);
+  xmask = shifted(xmask, dr);
+  colocc = shifted(colocc, dr);
   const int x = blockIdx.x;
   int any = 0;
   for (int y = threadIdx.x; y < N; y += 256) {
@@ -184,10 +190,18 @@ __device__ __forceinline__ void add_moments_u(T *acc, T s, T t0, const T *q, int
   if (has_w) acc[kMomW] += s * t0;
 }
 
+// Grid (blocks, request of the batch); every pointer is request 0's.
 template <typename T, int P>
 __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs, const Rec4<T> *__restrict__ recs,
                                                      const uint8_t *__restrict__ colmask, GridArgs ga,
-                                                     T *__restrict__ planar) {
+                                                     T *__restrict__ planar, Batch bt) {
+  {
+    const long long dr = bt.delta[blockIdx.y];
+    offs = shifted(offs, dr);
+    recs = shifted(recs, dr);
+    colmask = shifted(colmask, dr);
+    planar = shifted(planar, dr);
+  }
   constexpr int LO = Win<P>::LO, RW = Win<P>::HI - Win<P>::LO + 1;
   constexpr int CY = kBY + RW - 1, CZ = kBZ + RW - 1;
   constexpr int NCELL = (kBX + RW - 1) * CY * CZ;
@@ -404,11 +418,20 @@ template <typename T> struct alignas(4 * sizeof(T)) SweepRec {
 };
 
 // FP32 plans run 4 waves per SIMD (128 VGPRs); FP64 plans hold twice the
-// accumulator registers and run 2.
+// accumulator registers and run 2.  Grid (patches, request of the batch);
+// every pointer is request 0's.
 template <typename T, int P, bool TWIN>
 __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_grid_sweep(
     const int *__restrict__ offs, const Rec4<T> *__restrict__ recs, const uint8_t *__restrict__ colmask,
-    const uint8_t *__restrict__ colocc, GridArgs ga, T *__restrict__ planar) {
+    const uint8_t *__restrict__ colocc, GridArgs ga, T *__restrict__ planar, Batch bt) {
+  {
+    const long long dr = bt.delta[blockIdx.y];
+    offs = moved(offs, dr);
+    recs = moved(recs, dr);
+    colmask = moved(colmask, dr);
+    colocc = moved(colocc, dr);
+    planar = moved(planar, dr);
+  }
   using Wn = SweepWin<P, TWIN>;
   constexpr int LO = Wn::LO, HI = Wn::HI, RING = HI - LO + 1;
   constexpr int CY = kSY + RING - 1, CZ = kSZ + RING - 1, NSC = CY * CZ;
@@ -642,7 +665,8 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(sizeo
 // wsq: weights t0^2 instead of t0 (a second pass after the first, whose
 // occupancy masks it reuses).
 template <typename T, int P>
-static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0) {
+static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0,
+                       const Batch &bt) {
   const Layout &L = pl->L;
   const int N = pl->N;
   GridArgs ga{};
@@ -655,23 +679,23 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
   for (int d = 0; d < 3; ++d) ga.ou[d] = pl->p.observer[d] / pl->h;
   ga.plane_stride = (long long)N * N * N;
   if (!wsq && m0 == 0)
-    FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N), dim3(256), 0, s,
+    FRSD_TIMED("col_mask", s, hipLaunchKernelGGL(k_col_mask<P>, dim3((unsigned)N, bt.n), dim3(256), 0, s,
                                                  ws_ptr<const int>(ws, L.cnt), N, ws_ptr<uint8_t>(ws, L.colmask),
-                                                 ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc)));
+                                                 ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc), bt));
   if constexpr (P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
       const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
-      FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk), dim3(kSThreads), 0, s,
+      FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk, bt.n), dim3(kSThreads), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
                                                ws_ptr<const uint8_t>(ws, L.colmask), ws_ptr<const uint8_t>(ws, L.colocc),
-                                               ga, ws_ptr<T>(ws, L.planar)));
+                                               ga, ws_ptr<T>(ws, L.planar), bt));
       if (ga.interlace)
-        FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<T, P, true>), dim3(nblk), dim3(kSThreads), 0, s,
-                                                      ws_ptr<const int>(ws, L.cnt),
+        FRSD_TIMED("grid_twin", s, hipLaunchKernelGGL((k_grid_sweep<T, P, true>), dim3(nblk, bt.n), dim3(kSThreads), 0,
+                                                      s, ws_ptr<const int>(ws, L.cnt),
                                                       ws_ptr<const Rec4<T>>(ws, L.sorted),
                                                       ws_ptr<const uint8_t>(ws, L.colmask),
                                                       ws_ptr<const uint8_t>(ws, L.colocc), ga,
-                                                      ws_ptr<T>(ws, L.planar)));
+                                                      ws_ptr<T>(ws, L.planar), bt));
       FRSD_LAUNCH_CHECK();
       return FRSD_OK;
     }
@@ -679,20 +703,21 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
   auto kern = k_grid<T, P>;
   FRSD_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kGStageBytes));
   const unsigned nblk = (unsigned)((N / kBX) * (N / kBY) * (N / kBZ));
-  FRSD_TIMED("grid", s, hipLaunchKernelGGL(kern, dim3(nblk), dim3(kGThreads), kGStageBytes, s,
+  FRSD_TIMED("grid", s, hipLaunchKernelGGL(kern, dim3(nblk, bt.n), dim3(kGThreads), kGStageBytes, s,
                                            ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
-                                           ws_ptr<const uint8_t>(ws, L.colmask), ga, ws_ptr<T>(ws, L.planar)));
+                                           ws_ptr<const uint8_t>(ws, L.colmask), ga, ws_ptr<T>(ws, L.planar), bt));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 template <typename T>
-static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0 = 0) {
+static int grid_order(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, int has_w, int wsq, int m0 = 0,
+                      const Batch &bt = batch_one()) {
   switch (pl->p.order) {
-    case 1: return launch_grid<T, 1>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
-    case 2: return launch_grid<T, 2>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
-    case 3: return launch_grid<T, 3>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
-    default: return launch_grid<T, 4>(pl, ws, s, n_ell_mom, has_w, wsq, m0);
+    case 1: return launch_grid<T, 1>(pl, ws, s, n_ell_mom, has_w, wsq, m0, bt);
+    case 2: return launch_grid<T, 2>(pl, ws, s, n_ell_mom, has_w, wsq, m0, bt);
+    case 3: return launch_grid<T, 3>(pl, ws, s, n_ell_mom, has_w, wsq, m0, bt);
+    default: return launch_grid<T, 4>(pl, ws, s, n_ell_mom, has_w, wsq, m0, bt);
   }
 }
 
@@ -704,23 +729,35 @@ int run_grid_group(frsd_plan *pl, void *ws, int m0, int m1, hipStream_t s) {
 template int run_grid_group<float>(frsd_plan *, void *, int, int, hipStream_t);
 template int run_grid_group<double>(frsd_plan *, void *, int, int, hipStream_t);
 
-// Assignment and forward transforms of the sorted records into the complex
-// meshes at mesh_off (the mesh region, or the random cache).
+// Assignment of the sorted records into every moment plane of the plan
+// (of every request of the batch; ws: request 0's workspace).
 template <typename T>
-static int grid_and_transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStream_t s) {
+static int grid_all(frsd_plan *pl, void *ws, hipStream_t s, const Batch &bt = batch_one()) {
   const SlotDesc &sd = pl->slots;
   int n_ell_mom = 0, has_w = 0;
   for (int m = 0; m < sd.n_mom; ++m) {
     if (sd.mom_id[m] == kMomW) has_w = 1;
     else ++n_ell_mom;
   }
-  int rc = grid_order<T>(pl, ws, s, n_ell_mom, has_w, 0);
-  if (rc) return rc;
+  return grid_order<T>(pl, ws, s, n_ell_mom, has_w, 0, 0, bt);
+}
+
+// Forward transforms of the assignment planes into the complex meshes at
+// mesh_off (the mesh region, or the random cache) of the batch's requests
+// (ws: request 0's workspace).
+template <typename T>
+static int transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStream_t s, const Batch &bt = batch_one()) {
   return fft3d_forward<T>(pl->fft_n, ws_ptr<void>(ws, pl->L.tw_fwd), ws_ptr<const void>(ws, pl->L.planar),
                           ws_ptr<void>(ws, mesh_off), pl->slots.n_slot, pl->nmax,
                           std::max(pl->pk_lut_len, pl->p.bk_nbins > 0 ? pl->bk_lut_len : 0) - 1,
                           ws_ptr<const uint8_t>(ws, pl->L.colmask), ws_ptr<const uint8_t>(ws, pl->L.xmask), s,
-                          pl->tune.row_grid);
+                          pl->tune.row_grid, bt);
+}
+
+template <typename T>
+static int grid_and_transform(frsd_plan *pl, void *ws, size_t mesh_off, hipStream_t s) {
+  const int rc = grid_all<T>(pl, ws, s);
+  return rc ? rc : transform<T>(pl, ws, mesh_off, s);
 }
 
 template <typename T>
@@ -755,6 +792,29 @@ int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, dou
   return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
 }
 
+// A batch of requests on plans of one shape: each request's ingest and sort
+// (launches sized by its own catalogues), then one occupancy-mask launch,
+// one assignment launch per grid (main, twin) and one forward FFT per pass
+// over every request.  ran null: the galaxies against each plan's random
+// cache.
+template <typename T>
+int run_mesh_assign_batch(frsd_plan *const *pls, void *const *wss, int n, const frsd_catalog *gal,
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s) {
+  const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
+  for (int r = 0; r < n; ++r) {
+    const int rc = ingest_and_sort<T>(pls[r], wss[r], &gal[r], ran ? &ran[r] : &none, alpha[r], s, nullptr);
+    if (rc) return rc;
+    if (!ran) scal_cached(pls[r], wss[r], alpha[r], s);
+  }
+  const Batch bt = batch_of(wss, n);
+  const int rc = grid_all<T>(pls[0], wss[0], s, bt);
+  return rc ? rc : transform<T>(pls[0], wss[0], pls[0]->L.mesh, s, bt);
+}
+
+template int run_mesh_assign_batch<float>(frsd_plan *const *, void *const *, int, const frsd_catalog *,
+                                          const frsd_catalog *, const double *, hipStream_t);
+template int run_mesh_assign_batch<double>(frsd_plan *const *, void *const *, int, const frsd_catalog *,
+                                           const frsd_catalog *, const double *, hipStream_t);
 template int run_random_cache<float>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
 template int run_random_cache<double>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
 template int run_mesh_assign_cached<float>(frsd_plan *, void *, const frsd_catalog *, double, hipStream_t);

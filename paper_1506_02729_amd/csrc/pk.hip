@@ -35,10 +35,18 @@ struct BinArgs {
   int n_slot, n_ell, has_w;
   double kf;
   // random cache: slot s is Z_gal + cx[s] X_ran + i cy[s] Y_ran, with X_ran and
-  // Y_ran the real-plane spectra of the cached slot (cx = cy: one factor)
+  // Y_ran the real-plane spectra of the cached slot (cx = cy: one factor);
+  // the factor of a plane is 0 (empty), -alpha (kind 1: the moments of eqs.
+  // F0, Qab) or +alpha^2 (kind 2: the w^2 weights of F_0^w), alpha[r] that
+  // of request r of the batch
   int cached;
-  double cx[kMaxSlots], cy[kMaxSlots];
+  int8_t kx[kMaxSlots], ky[kMaxSlots];
+  double alpha[kMaxBatch];
 };
+
+__device__ __forceinline__ double cache_factor(int kind, double al) {
+  return kind == 1 ? -al : (kind == 2 ? al * al : 0.0);
+}
 
 // Sum v[NV] over every run of equal keys among consecutive lanes (a
 // segmented inclusive scan), and let the last lane of each run whose key is
@@ -124,13 +132,21 @@ __device__ __forceinline__ void add_slots(std::integer_sequence<int, S...>, int 
 // whose combinations are F^w_0, F^w_2, F^w_4; only bispectrum bins are
 // summed, Q_lw = sum Re[F_0 (F^w_l)^*] for l = 2, 4, with F_0 read from the
 // low-k cube written by the first pass.
+// Grid (blocks, request): mesh, lowk, part and rcache are request 0's and
+// move by the request's workspace distance.
 template <typename T, bool GEOM, bool IL, bool WP = false>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict__ mesh, long long slot_stride,
                                                       BinArgs a, const int16_t *__restrict__ pk_lut,
                                                       const int16_t *__restrict__ bk_lut, cplx_t<T> *lowk,
-                                                      double *part, const cplx_t<T> *__restrict__ rcache) {
+                                                      double *part, const cplx_t<T> *__restrict__ rcache, Batch bt) {
   using C = cplx_t<T>;
   constexpr int NV = BinValues<GEOM>::n;
+  const long long dr = bt.delta[blockIdx.y];
+  mesh = shifted(mesh, dr);
+  lowk = shifted(lowk, dr);
+  part = shifted(part, dr);
+  rcache = shifted(rcache, dr);
+  const double al = a.alpha[blockIdx.y];
   __shared__ double bins[kMaxBinsAll * NV];
   // per-axis factors for |n| <= nmax: interlacing phase exp(-i pi n / N)
   // (cos, sin) and the inverse window 1 / sinc(pi n / N)^p
@@ -208,7 +224,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
         for (int sl = 0; sl < kMaxSlots; ++sl) {
           if (sl < a.n_slot) {
             const C rp = rcache[sl * slot_stride + gp], rm = rcache[sl * slot_stride + gm];
-            const T ca = (T)(0.5 * (a.cx[sl] + a.cy[sl])), cb = (T)(0.5 * (a.cx[sl] - a.cy[sl]));
+            const double fx = cache_factor(a.kx[sl], al), fy = cache_factor(a.ky[sl], al);
+            const T ca = (T)(0.5 * (fx + fy)), cb = (T)(0.5 * (fx - fy));
             zp[sl] = cadd(zp[sl], cadd(cscale(rp, ca), cscale(cmake<C>(rm.x, -rm.y), cb)));
             zm[sl] = cadd(zm[sl], cadd(cscale(rm, ca), cscale(cmake<C>(rp.x, -rp.y), cb)));
           }
@@ -314,9 +331,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const cplx_t<T> *__restrict
 // (geometry): slots 0-1; mode 0 (data): slots 2-5 (P_ell bins: S00 S20 S40
 // S22) or 5-7 (bispectrum bins: S0w S2w S4w; their fourth quantity is not
 // kept); mode 2 (w^2-weighted pass): slots 2-3 of the bispectrum bins (Q2w,
-// Q4w).
+// Q4w).  Grid (wavefront groups, request), as k_bin.
 __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk, int nv, int nall, int pk_nb,
-                                                    int mode, double *sum) {
+                                                    int mode, double *sum, Batch bt) {
+  part = shifted(part, bt.delta[blockIdx.y]);
+  sum = shifted(sum, bt.delta[blockIdx.y]);
   const int i = blockIdx.x * 4 + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i >= nall * nv) return;  // whole wavefronts
   double s = 0;
@@ -396,52 +415,67 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
                                                ws_ptr<const int16_t>(ws, L.pk_lut),
                                                p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                                (float2 *)nullptr, ws_ptr<double>(ws, L.bin_part),
-                                               (const float2 *)nullptr));
+                                               (const float2 *)nullptr, batch_one()));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
-                                                 p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum)));  // geometry
+                                                 p.pk_nbins, 1, ws_ptr<double>(ws, L.bin_sum), batch_one()));  // geometry
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }
 
 int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
 
+// Binning of n requests of one shape in one launch (grid y = request), then
+// each request's P_ell.  cached: every request's meshes hold galaxies alone,
+// combined with its plan's random cache for its own alpha.
 template <typename T>
-int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached) {
+int run_pk_batch(frsd_plan *const *pls, void *const *wss, int n, const frsd_pk_out *out, hipStream_t s,
+                 bool cached) {
+  frsd_plan *pl = pls[0];
+  void *ws = wss[0];
   const Layout &L = pl->L;
   const frsd_params &p = pl->p;
   const int nall = p.pk_nbins + p.bk_nbins;
   if (nall > kMaxBinsAll) return fail(FRSD_EINVAL, "too many bins (pk + bk > 512)");
+  if (n < 1 || n > kMaxBatch) return fail(FRSD_EINVAL, "batch size out of range");
   BinArgs a = bin_args(pl);
   if (a.nmax >= kBinTab) return fail(FRSD_EINVAL, "k range too large for the binning tables");
   if (cached) {
-    // factor of each moment position: -alpha (the moments of eqs. F0, Qab),
-    // +alpha^2 (the w^2 weights of F_0^w)
     const SlotDesc &sd = pl->slots;
-    const double al = pl->cached_alpha;
-    auto coef = [&](int pos) { return pos < 0 || pos >= sd.n_mom ? 0.0 : (sd.mom_id[pos] == kMomW ? al * al : -al); };
+    auto kind = [&](int pos) -> int8_t { return pos < 0 || pos >= sd.n_mom ? 0 : (sd.mom_id[pos] == kMomW ? 2 : 1); };
     a.cached = 1;
     for (int sl = 0; sl < sd.n_slot; ++sl) {
-      a.cx[sl] = coef(sd.re_mom[sl]);
-      a.cy[sl] = coef(sd.im_mom[sl]);
+      a.kx[sl] = kind(sd.re_mom[sl]);
+      a.ky[sl] = kind(sd.im_mom[sl]);
     }
+    for (int r = 0; r < n; ++r) a.alpha[r] = pls[r]->cached_alpha;
   }
   if (!slot_layout_ok(pl->slots, a, p.interlace != 0)) return fail(FRSD_EINVAL, "unexpected slot layout");
+  const Batch bt = batch_of(wss, n);
   using C = cplx_t<T>;
   const long long NNN = (long long)pl->N * pl->N * pl->N;
   constexpr int NV = BinValues<false>::n;
   auto kern = p.interlace ? k_bin<T, false, true> : k_bin<T, false, false>;
-  FRSD_TIMED("bin", s, hipLaunchKernelGGL(kern, dim3(pl->tune.bin_blocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
-                                          NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
+  FRSD_TIMED("bin", s, hipLaunchKernelGGL(kern, dim3(pl->tune.bin_blocks, n), dim3(kBinThreads), 0, s,
+                                          ws_ptr<const C>(ws, L.mesh), NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                           p.bk_nbins > 0 ? ws_ptr<const int16_t>(ws, L.bk_lut) : nullptr,
                                           p.bk_nbins > 0 ? ws_ptr<C>(ws, L.lowk) : nullptr,
                                           ws_ptr<double>(ws, L.bin_part),
-                                          a.cached ? ws_ptr<const C>(ws, L.rcache) : nullptr));
-  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
+                                          a.cached ? ws_ptr<const C>(ws, L.rcache) : nullptr, bt));
+  FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4, n), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
-                                                 p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum)));
+                                                 p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum), bt));
   FRSD_LAUNCH_CHECK();
-  return run_pk_final(pl, ws, out, s);
+  for (int r = 0; r < n; ++r) {
+    const int rc = run_pk_final(pls[r], wss[r], &out[r], s);
+    if (rc) return rc;
+  }
+  return FRSD_OK;
+}
+
+template <typename T>
+int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool cached) {
+  return run_pk_batch<T>(&pl, &ws, 1, out, s, cached);
 }
 
 // P_ell from the bin sums (slots 0-5 of every P_ell bin) and the scalars.
@@ -457,6 +491,8 @@ int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s)
 
 template int run_pk<float>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t, bool);
 template int run_pk<double>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t, bool);
+template int run_pk_batch<float>(frsd_plan *const *, void *const *, int, const frsd_pk_out *, hipStream_t, bool);
+template int run_pk_batch<double>(frsd_plan *const *, void *const *, int, const frsd_pk_out *, hipStream_t, bool);
 
 // Q_lw = sum_b Re[F_0 (F^w_l)^*] (l = 2, 4) of every bispectrum bin from the
 // w^2-weighted moment meshes of run_w_moments (the q_2, q_3 terms of Sec. III.B
@@ -478,10 +514,10 @@ int run_bin_w(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_TIMED("bin_w", s, hipLaunchKernelGGL(kern, dim3(pl->tune.bin_blocks), dim3(kBinThreads), 0, s, ws_ptr<const C>(ws, L.mesh),
                                             NNN, a, ws_ptr<const int16_t>(ws, L.pk_lut),
                                             ws_ptr<const int16_t>(ws, L.bk_lut), ws_ptr<C>(ws, L.lowk),
-                                            ws_ptr<double>(ws, L.bin_part), (const C *)nullptr));
+                                            ws_ptr<double>(ws, L.bin_part), (const C *)nullptr, batch_one()));
   FRSD_TIMED("bin_reduce", s, hipLaunchKernelGGL(k_bin_reduce, dim3((nall * NV + 3) / 4), dim3(256), 0, s,
                                                  ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
-                                                 p.pk_nbins, 2, ws_ptr<double>(ws, L.bin_sum)));
+                                                 p.pk_nbins, 2, ws_ptr<double>(ws, L.bin_sum), batch_one()));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
 }

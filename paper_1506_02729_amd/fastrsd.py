@@ -57,6 +57,7 @@ class frsd_tuning(ctypes.Structure):
 
 
 FRSD_DEVICE, FRSD_HOST = 0, 1
+FRSD_MAX_BATCH = 16
 
 
 class frsd_catalog(ctypes.Structure):
@@ -89,6 +90,7 @@ _proto = {
     "frsd_random_cache": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), _P]),
     "frsd_mesh_assign_cached": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_catalog), ctypes.c_double, _P]),
     "frsd_pk_multipoles": (ctypes.c_int, [_P, _P, ctypes.POINTER(frsd_pk_out), _P]),
+    "frsd_pk_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P]),
     "frsd_bk_ntriangles": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "frsd_bk_grid": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "frsd_bk_triangles": (ctypes.c_int, [_P, _P]),
@@ -169,6 +171,22 @@ def frsd_mesh_assign_cached(plan, ws_ptr, gal: frsd_catalog, alpha: float, strea
 
 def frsd_pk_multipoles(plan, ws_ptr, out: frsd_pk_out, stream) -> None:
     _check(_lib.frsd_pk_multipoles(plan, ws_ptr, ctypes.byref(out), stream))
+
+
+def frsd_pk_batch(plans, ws_ptrs, gals, rans, alphas, outs, stream) -> None:
+    """plans, ws_ptrs: handles and workspace addresses; gals, outs: lists of
+    frsd_catalog / frsd_pk_out; rans: list of frsd_catalog, or None for
+    galaxies against each plan's random cache; alphas: list of floats."""
+    n = len(plans)
+    if not (len(ws_ptrs) == len(gals) == len(alphas) == len(outs) == n) or (rans is not None and len(rans) != n):
+        raise ValueError("every per-request list of a batch must have one entry per plan")
+    p_arr = (_P * n)(*plans)
+    w_arr = (_P * n)(*ws_ptrs)
+    g_arr = (frsd_catalog * n)(*gals)
+    r_arr = (frsd_catalog * n)(*rans) if rans is not None else None
+    a_arr = (ctypes.c_double * n)(*[float(a) for a in alphas])
+    o_arr = (frsd_pk_out * n)(*outs)
+    _check(_lib.frsd_pk_batch(p_arr, w_arr, n, g_arr, r_arr, a_arr, o_arr, stream))
 
 
 def frsd_bk_ntriangles(plan) -> int:
@@ -405,12 +423,15 @@ class Plan:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
         return {k: v.cpu().numpy().copy() for k, v in out.items()}
 
-    def pk(self) -> dict:
+    def _pk_out(self) -> frsd_pk_out:
         o = frsd_pk_out()
         for name in PK_ARRAYS:
             setattr(o, name, self.pk_buf[name].data_ptr())
         o.where = FRSD_HOST if self.host_outputs else FRSD_DEVICE
-        frsd_pk_multipoles(self.handle, self.ws_ptr, o, self.stream.cuda_stream)
+        return o
+
+    def pk(self) -> dict:
+        frsd_pk_multipoles(self.handle, self.ws_ptr, self._pk_out(), self.stream.cuda_stream)
         return self.pk_buf
 
     def bk(self) -> dict:
@@ -450,6 +471,36 @@ class Plan:
         if rej:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
         return {k: v.cpu().numpy().copy() for k, v in out.items()}
+
+
+def pk_batch(plans: list, gals: list, rans: list | None, alphas: list) -> list:
+    """One frsd_pk_batch call: request r (gals[r], rans[r], alphas[r]) on
+    plans[r]; rans None: galaxies against each plan's random cache.  The plans
+    share one configuration and one stream.  Returns each plan's pk_buf
+    (device tensors, valid once the stream has run the batch)."""
+    if not plans:
+        return []
+    stream = plans[0].stream
+    if any(p.stream != stream for p in plans):
+        raise ValueError("the plans of a batch must share one stream")
+    for r, p in enumerate(plans):  # keep the catalogues alive while queued
+        p._gal = gals[r]
+        if rans is not None:
+            p._ran = rans[r]
+    frsd_pk_batch([p.handle for p in plans], [p.ws_ptr for p in plans], [_c_catalog(g) for g in gals],
+                  None if rans is None else [_c_catalog(c) for c in rans], alphas,
+                  [p._pk_out() for p in plans], stream.cuda_stream)
+    return [p.pk_buf for p in plans]
+
+
+def run_batch(plans: list, gals: list, rans: list | None, alphas: list) -> list:
+    """pk_batch, then synchronises and returns host NumPy copies per request."""
+    bufs = pk_batch(plans, gals, rans, alphas)
+    for p in plans:
+        rej = p.status()
+        if rej:
+            raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
+    return [{k: v.cpu().numpy().copy() for k, v in b.items()} for b in bufs]
 
 
 class Graph:

@@ -199,3 +199,47 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
         for field, _ in cls._fields_:
             assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_batch_validation_on_host():
+    """frsd_pk_batch checks every request before any device work: batch size,
+    plans of one shape, distinct plans and workspaces, initialised workspaces."""
+    from paper_1506_02729_amd import fastrsd as F
+    kf = 2 * math.pi / 500.0
+    base = dict(n_grid=64, box=500.0, observer=(-300, -300, -300), order=2, pk_dk=2 * kf, pk_nbins=16,
+                max_objects=1000)
+    hs = [F.frsd_plan_create(F.Config(**base).to_c()) for _ in range(3)]
+    other = F.frsd_plan_create(F.Config(**{**base, "order": 3}).to_c())
+    ws = [256 * (k + 1) for k in range(4)]  # aligned placeholders: never dereferenced
+    gal = F.frsd_catalog()
+    out = F.frsd_pk_out()
+
+    def call(plans, wss):
+        n = len(plans)
+        F.frsd_pk_batch(plans, wss, [gal] * n, None, [1.0] * n, [out] * n, None)
+
+    def call_empty():
+        F._check(F._lib.frsd_pk_batch((F._P * 1)(hs[0]), (F._P * 1)(ws[0]), 0, (F.frsd_catalog * 1)(gal), None,
+                                      (ctypes.c_double * 1)(1.0), (F.frsd_pk_out * 1)(out), None))
+
+    try:
+        cases = [
+            (call_empty, F.FRSD_EINVAL),                                       # empty batch
+            (lambda: call(hs[:2] + [other], ws[:3]), F.FRSD_EINVAL),           # plans of two shapes
+            (lambda: call([hs[0], hs[1]], [ws[0], ws[0]]), F.FRSD_EINVAL),    # one workspace twice
+            (lambda: call([hs[0], hs[0]], ws[:2]), F.FRSD_EINVAL),            # one plan twice
+            (lambda: call(hs, [ws[0], ws[1] + 8, ws[2]]), F.FRSD_EINVAL),     # misaligned workspace
+            (lambda: call(hs, ws[:3]), F.FRSD_ESTATE),                         # not initialised
+        ]
+        for fn, code in cases:
+            with pytest.raises(F.FrsdError) as ei:
+                fn()
+            assert ei.value.code == code, F.frsd_last_error()
+        big = [gal] * (F.FRSD_MAX_BATCH + 1)
+        with pytest.raises(F.FrsdError) as ei:
+            F.frsd_pk_batch([hs[0]] * len(big), [ws[0]] * len(big), big, None, [1.0] * len(big),
+                            [out] * len(big), None)
+        assert ei.value.code == F.FRSD_EINVAL
+    finally:
+        for h in hs + [other]:
+            F.frsd_plan_destroy(h)
