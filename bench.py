@@ -564,8 +564,9 @@ def batch_study(args, F, torch, synth, dev, log):
     (a) one at a time on one plan and stream (frsd_mesh_assign_cached +
     frsd_pk_multipoles), (b) on 3 plans with a stream each, round robin, and
     (c) in batches of 8 and 16 requests (frsd_pk_batch, one stream: one
-    forward FFT and one binning launch per batch).  Each batched result is
-    compared with the one-at-a-time result of the same mock."""
+    launch per kernel per batch), and (d) in batches of 8 alternating between
+    two streams.  Each batched result is compared with the one-at-a-time
+    result of the same mock, per multipole."""
     box = 3500.0
     n_ran = 10_000_000
     n_mock = 8
@@ -581,7 +582,7 @@ def batch_study(args, F, torch, synth, dev, log):
     dev_mocks = [(F.device_catalog(g, dev), a) for g, a in mocks]
     K = args.batch_mocks
     results = {}
-    for N in (64, 128, 256):
+    for N in (int(v) for v in args.batch_n.split(",")):
         k_ny = math.pi * N / box
         nb = int(min(0.225, 0.95 * k_ny) / 0.005)
         cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
@@ -589,10 +590,14 @@ def batch_study(args, F, torch, synth, dev, log):
                        random_cache=True)
         streams = [torch.cuda.Stream(dev) for _ in range(3)]
         plans = [F.Plan(cfg, device=dev, stream=streams[0]) for _ in range(16)]
-        side = [F.Plan(cfg, device=dev, stream=streams[k]) for k in (1, 2)]
-        for pl in plans + side:
+        n_more = 0 if args.batch_profile else 1
+        side = [F.Plan(cfg, device=dev, stream=streams[k]) for k in (1, 2)][:2 * n_more]
+        second = [F.Plan(cfg, device=dev, stream=streams[1]) for _ in range(8 * n_more)]  # batches on a second stream
+        for pl in plans + side + second:
             pl.random_cache(r_dev)
         torch.cuda.synchronize()
+        if args.batch_profile:
+            time.sleep(0.5)  # a gap in a kernel trace between the caches and the batches
 
         def one_at_a_time(n):
             for i in range(n):
@@ -612,6 +617,12 @@ def batch_study(args, F, torch, synth, dev, log):
                 idx = [(i0 + j) % n_mock for j in range(b)]
                 F.pk_batch(plans[:b], [dev_mocks[i][0] for i in idx], None, [dev_mocks[i][1] for i in idx])
 
+        def batched_two_streams(n):
+            for q, i0 in enumerate(range(0, n, 8)):
+                idx = [(i0 + j) % n_mock for j in range(8)]
+                F.pk_batch(plans[:8] if q % 2 == 0 else second, [dev_mocks[i][0] for i in idx], None,
+                           [dev_mocks[i][1] for i in idx])
+
         def timed(fn, *a):
             fn(*a)  # warm-up pass
             torch.cuda.synchronize()
@@ -620,10 +631,16 @@ def batch_study(args, F, torch, synth, dev, log):
             torch.cuda.synchronize()
             return K / (time.perf_counter() - t)
 
+        if args.batch_profile:  # batches of 16 only (a profiler run)
+            results[str(N)] = {"batch16": timed(batched, K, 16)}
+            log(f"batch study N={N}: batch16 {results[str(N)]['batch16']:.4g} mocks/s")
+            del plans, side, second
+            continue
         row = {"pk_nbins": nb, "workspace_gb_per_plan": plans[0].ws_bytes / 1e9,
                "one_at_a_time": timed(one_at_a_time, K), "three_streams": timed(round_robin, K)}
         for b in (8, 16):
             row[f"batch{b}"] = timed(batched, K, b)
+        row["batch8_two_streams"] = timed(batched_two_streams, K)
         # per-kernel device time per mock (library HIP events, untimed passes of 16 mocks)
         for name, fn, a in (("one_at_a_time", one_at_a_time, (16,)), ("batch16", batched, (16, 16))):
             F.frsd_profile(True)
@@ -639,19 +656,17 @@ def batch_study(args, F, torch, synth, dev, log):
             g, a = dev_mocks[i]
             ref.append(plans[0].run_cached(g, a, bispectrum=False))
         outs = F.run_batch(plans[:n_mock], [m[0] for m in dev_mocks], None, [m[1] for m in dev_mocks])
-        diff = 0.0
-        for i in range(n_mock):
-            for key in ("p0", "p2", "p4"):
-                diff = max(diff, float(np.max(np.abs(outs[i][key] - ref[i][key])) / np.max(np.abs(ref[i][key]))))
-        row["max_rel_diff_batch_vs_one_at_a_time"] = diff
-        for pl in plans + side:
+        for key in ("p0", "p2", "p4"):
+            row[f"{key}_max_diff_batch_vs_one_at_a_time"] = max(
+                float(np.max(np.abs(outs[i][key] - ref[i][key])) / np.max(np.abs(ref[i][key]))) for i in range(n_mock))
+        for pl in plans + side + second:
             assert pl.status() == 0
         log(f"batch study N={N}: " + ", ".join(f"{k} {v:.4g}" for k, v in row.items() if not isinstance(v, dict)))
         for k, v in row.items():
             if isinstance(v, dict):
                 log(f"  {k}: " + ", ".join(f"{n} {t:.3f}" for n, t in v.items()))
         results[str(N)] = row
-        del plans, side
+        del plans, side, second
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     return {"metric": "small-mesh covariance throughput (mocks/s): one at a time vs 3 streams vs batched requests",
@@ -870,6 +885,8 @@ def main():
     ap.add_argument("--batch-study", action="store_true",
                     help="run only the small-mesh study: one at a time vs 3 streams vs batched requests")
     ap.add_argument("--batch-mocks", type=int, default=64, help="batch study: mocks per timed pass")
+    ap.add_argument("--batch-n", default="64,128,256", help="batch study: mesh sides")
+    ap.add_argument("--batch-profile", action="store_true", help="batch study: batches of 16 only")
     ap.add_argument("--large-mesh", action="store_true",
                     help="run only the 1024^3 streamed precision sweep (FP32 vs FP64 vs the stored oracle)")
     ap.add_argument("--mean-gap", type=float, default=0.5, help="served run: mean inter-arrival time (s)")

@@ -49,8 +49,12 @@ constexpr int kGStageBytes = 65536;         // staged object records (two workgr
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
                     hipStream_t s, const double *dyn);
+template <typename T>
+int ingest_and_sort_batch(frsd_plan *pl, void *const *wss, int nreq, const frsd_catalog *gal,
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s);
 void scal_keep(frsd_plan *pl, void *ws, hipStream_t s);
 void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s);
+void scal_cached_batch(frsd_plan *pl, void *const *wss, int nreq, const double *alpha, hipStream_t s);
 
 // Floor cells that reach the main node i (at i) or the twin node (at i + 1/2),
 // relative to i: [LO, HI].
@@ -792,22 +796,18 @@ int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, dou
   return grid_and_transform<T>(pl, ws, pl->L.mesh, s);
 }
 
-// A batch of requests on plans of one shape: each request's ingest and sort
-// (launches sized by its own catalogues), then one occupancy-mask launch,
-// one assignment launch per grid (main, twin) and one forward FFT per pass
-// over every request.  ran null: the galaxies against each plan's random
-// cache.
+// A batch of requests on plans of one shape: the ingest and sort, the
+// occupancy masks, the assignment (main and twin grids) and each forward
+// FFT pass run as one launch over every request.  ran null: the galaxies
+// against each plan's random cache.
 template <typename T>
 int run_mesh_assign_batch(frsd_plan *const *pls, void *const *wss, int n, const frsd_catalog *gal,
                           const frsd_catalog *ran, const double *alpha, hipStream_t s) {
-  const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
-  for (int r = 0; r < n; ++r) {
-    const int rc = ingest_and_sort<T>(pls[r], wss[r], &gal[r], ran ? &ran[r] : &none, alpha[r], s, nullptr);
-    if (rc) return rc;
-    if (!ran) scal_cached(pls[r], wss[r], alpha[r], s);
-  }
+  int rc = ingest_and_sort_batch<T>(pls[0], wss, n, gal, ran, alpha, s);
+  if (rc) return rc;
+  if (!ran) scal_cached_batch(pls[0], wss, n, alpha, s);
   const Batch bt = batch_of(wss, n);
-  const int rc = grid_all<T>(pls[0], wss[0], s, bt);
+  rc = grid_all<T>(pls[0], wss[0], s, bt);
   return rc ? rc : transform<T>(pls[0], wss[0], pls[0]->L.mesh, s, bt);
 }
 

@@ -13,6 +13,10 @@
 // record) and offs[2 c + 2] (end); offs[2 c + 1] splits the halves.  The
 // half is decided on the fraction as the record stores it (FP32 or FP64),
 // so the assignment kernels see the same split.
+//
+// Every kernel here serves a batch of requests on plans of one shape (grid y
+// = request): workspace pointers are request 0's and move by the request's
+// workspace distance; catalogue arrays, sizes and alpha come per request.
 #include "device.h"
 #include "frsd_internal.h"
 
@@ -21,13 +25,25 @@ namespace frsd {
 constexpr int kIngestThreads = 256;
 constexpr int kScanChunk = 4096;   // elements per scan block (256 threads x 16)
 
-__global__ void k_fill_i32(int *p, long long n, int v) {
+__global__ void k_fill_i32(int *p, long long n, int v, Batch bt) {
+  p = moved(p, bt.delta[blockIdx.y]);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
 }
 
-__global__ void k_zero_u64(unsigned long long *p) { p[threadIdx.x] = 0ull; }
+__global__ void k_zero_u64(unsigned long long *p, Batch bt) { moved(p, bt.delta[blockIdx.y])[threadIdx.x] = 0ull; }
+
+// The catalogues of one role (galaxies or randoms) of the requests of a
+// batch, and each request's alpha.
+struct CatArgs {
+  const void *pos[kMaxBatch], *w[kMaxBatch], *nbar[kMaxBatch];
+  long long n[kMaxBatch];
+  long long off[kMaxBatch];  // first object slot (the randoms follow the galaxies)
+};
+struct Alphas {
+  double v[kMaxBatch];
+};
 
 struct GeomArgs {
   double inv_h, L, ox, oy, oz;
@@ -87,11 +103,21 @@ __device__ __forceinline__ void dyn_sizes(const double *dyn, int is_ran, long lo
 }
 
 template <typename TIN>
-__global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const TIN *w, const TIN *nbar,
-                                                           long long n, int is_ran, long long obj_off,
-                                                           GeomArgs g, int *cnt, int *slot, int *cellkey,
-                                                           double *part, unsigned long long *reject,
-                                                           const double *dyn) {
+__global__ __launch_bounds__(kIngestThreads) void k_count(CatArgs c, int is_ran, GeomArgs g, int *cnt, int *slot,
+                                                           int *cellkey, double *part,
+                                                           unsigned long long *reject, const double *dyn,
+                                                           Batch bt) {
+  const int r = blockIdx.y;
+  const long long dr = bt.delta[r];
+  cnt = moved(cnt, dr);
+  slot = moved(slot, dr);
+  cellkey = moved(cellkey, dr);
+  part = moved(part, dr);
+  reject = moved(reject, dr);
+  dyn = shifted(dyn, dr);
+  const TIN *pos = static_cast<const TIN *>(c.pos[r]), *w = static_cast<const TIN *>(c.w[r]),
+            *nbar = static_cast<const TIN *>(c.nbar[r]);
+  long long n = c.n[r], obj_off = c.off[r];
   dyn_sizes(dyn, is_ran, n, obj_off);
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -125,10 +151,19 @@ __global__ __launch_bounds__(kIngestThreads) void k_count(const TIN *pos, const 
 
 // Pass 2: write the record of each accepted object at its sorted slot.
 template <typename TIN, typename T>
-__global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, const TIN *w, long long n, int is_ran,
-                                                             long long obj_off, double alpha, GeomArgs g,
+__global__ __launch_bounds__(kIngestThreads) void k_scatter(CatArgs c, int is_ran, Alphas al, GeomArgs g,
                                                              const int *offs, const int *slot, const int *cellkey,
-                                                             Rec4<T> *rec, const double *dyn) {
+                                                             Rec4<T> *rec, const double *dyn, Batch bt) {
+  const int r = blockIdx.y;
+  const long long dr = bt.delta[r];
+  offs = moved(offs, dr);
+  slot = moved(slot, dr);
+  cellkey = moved(cellkey, dr);
+  rec = moved(rec, dr);
+  dyn = shifted(dyn, dr);
+  const TIN *pos = static_cast<const TIN *>(c.pos[r]), *w = static_cast<const TIN *>(c.w[r]);
+  long long n = c.n[r], obj_off = c.off[r];
+  double alpha = al.v[r];
   dyn_sizes(dyn, is_ran, n, obj_off);
   if (dyn) alpha = dyn[2];
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -152,8 +187,13 @@ __global__ __launch_bounds__(kIngestThreads) void k_scatter(const TIN *pos, cons
 // I33 = alpha S_r[nbar^2 w^3], W3 = S_g[w^3] - alpha^3 S_r[w^3].
 // One wavefront per partial column (6 columns, 384 threads), then the
 // scalars.
-__global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk, double alpha, double *scal,
-                                                    const double *dyn) {
+__global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk, Alphas al, double *scal,
+                                                    const double *dyn, Batch bt) {
+  const long long dr = bt.delta[blockIdx.x];
+  part = moved(part, dr);
+  scal = moved(scal, dr);
+  dyn = shifted(dyn, dr);
+  double alpha = al.v[blockIdx.x];
   if (dyn) alpha = dyn[2];
   __shared__ double col[6];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -177,8 +217,12 @@ __global__ __launch_bounds__(384) void k_scal_final(const double *part, int nblk
 __global__ void k_scal_keep(const double *scal, double *keep) {
   if (threadIdx.x < 4) keep[threadIdx.x] = scal[6 + threadIdx.x];
 }
-__global__ void k_scal_cached(const double *keep, double alpha, double *scal) {
+// one workgroup per request of the batch
+__global__ void k_scal_cached(const double *keep, Alphas al, double *scal, Batch bt) {
   if (threadIdx.x != 0) return;
+  keep = moved(keep, bt.delta[blockIdx.x]);
+  scal = moved(scal, bt.delta[blockIdx.x]);
+  const double alpha = al.v[blockIdx.x];
   const double g0 = scal[4], g1 = scal[5];
   scal[0] = alpha * keep[0];
   scal[1] = g0 + alpha * alpha * keep[2];
@@ -191,11 +235,14 @@ void scal_keep(frsd_plan *pl, void *ws, hipStream_t s) {
   FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_keep, dim3(1), dim3(64), 0, s, ws_ptr<const double>(ws, pl->L.scal),
                                               ws_ptr<double>(ws, pl->L.rcache_sums)));
 }
-void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s) {
-  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_cached, dim3(1), dim3(64), 0, s,
-                                              ws_ptr<const double>(ws, pl->L.rcache_sums), alpha,
-                                              ws_ptr<double>(ws, pl->L.scal)));
+void scal_cached_batch(frsd_plan *pl, void *const *wss, int nreq, const double *alpha, hipStream_t s) {
+  Alphas al{};
+  for (int r = 0; r < nreq; ++r) al.v[r] = alpha[r];
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_cached, dim3(nreq), dim3(64), 0, s,
+                                              ws_ptr<const double>(wss[0], pl->L.rcache_sums), al,
+                                              ws_ptr<double>(wss[0], pl->L.scal), batch_of(wss, nreq)));
 }
+void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s) { scal_cached_batch(pl, &ws, 1, &alpha, s); }
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of int32 counts, in place (three kernels).
@@ -210,7 +257,9 @@ __device__ __forceinline__ int4 load4(const int *a, long long i, long long n) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const int *a, long long n, int *blk) {
+__global__ __launch_bounds__(256) void k_scan_reduce(const int *a, long long n, int *blk, Batch bt) {
+  a = moved(a, bt.delta[blockIdx.y]);
+  blk = moved(blk, bt.delta[blockIdx.y]);
   const long long base = (long long)blockIdx.x * kScanChunk;
   int s = 0;
 #pragma unroll
@@ -254,7 +303,8 @@ __device__ __forceinline__ int block_exscan256_fast(int v, int *wtot, int &total
 }
 
 // Block partials: thread t owns a contiguous run of them.
-__global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb) {
+__global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb, Batch bt) {
+  blk = moved(blk, bt.delta[blockIdx.x]);
   __shared__ int wtot[4];
   const int per = (nb + 255) / 256;
   const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
@@ -274,7 +324,9 @@ __global__ __launch_bounds__(256) void k_scan_top(int *blk, int nb) {
 // counts sit in distinct banks), scanned per thread and per block.
 __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 4); }
 
-__global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const int *blk) {
+__global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const int *blk, Batch bt) {
+  a = moved(a, bt.delta[blockIdx.y]);
+  blk = moved(blk, bt.delta[blockIdx.y]);
   __shared__ int buf[kScanChunk + kScanChunk / 16];
   __shared__ int wtot[4];
   const long long base = (long long)blockIdx.x * kScanChunk;
@@ -319,66 +371,119 @@ __global__ __launch_bounds__(256) void k_scan_down(int *a, long long n, const in
 }
 
 // ---------------------------------------------------------------------------
-template <typename TIN>
-static void launch_count(const frsd_catalog *c, int is_ran, long long off, const GeomArgs &g, void *ws,
-                         const frsd_plan *pl, hipStream_t s, const double *dyn) {
-  const Layout &L = pl->L;
-  FRSD_TIMED("count", s, hipLaunchKernelGGL((k_count<TIN>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s, (const TIN *)c->pos,
-                     (const TIN *)c->w, (const TIN *)c->nbar, (long long)c->n, is_ran, off, g,
-                     ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<double>(ws, L.scal_part),
-                     ws_ptr<unsigned long long>(ws, L.reject), dyn));
+// Catalogues of role k (0 galaxies, 1 randoms) of every request: one dtype
+// per launch.  Empty catalogues take any dtype.
+static bool role_dtype(const frsd_catalog *const *cat, int nreq, int *dtype) {
+  *dtype = FRSD_F64;
+  bool seen = false;
+  for (int r = 0; r < nreq; ++r) {
+    if (cat[r]->n == 0) continue;
+    if (seen && cat[r]->dtype != *dtype) return false;
+    *dtype = cat[r]->dtype;
+    seen = true;
+  }
+  return true;
 }
 
-template <typename TIN, typename T>
-static void launch_scatter(const frsd_catalog *c, int is_ran, long long off, double alpha, const GeomArgs &g,
-                           void *ws, const frsd_plan *pl, hipStream_t s, const double *dyn) {
+template <typename T>
+static int ingest_launches(frsd_plan *pl, void *const *wss, int nreq, const frsd_catalog *const *gal,
+                           const frsd_catalog *const *ran, const double *alpha, hipStream_t s, const double *dyn,
+                           int dt_gal, int dt_ran) {
   const Layout &L = pl->L;
-  FRSD_TIMED("scatter", s, hipLaunchKernelGGL((k_scatter<TIN, T>), dim3(kIngestBlocks), dim3(kIngestThreads), 0, s,
-                     (const TIN *)c->pos, (const TIN *)c->w, (long long)c->n, is_ran, off, alpha, g,
-                     ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot), ws_ptr<int>(ws, L.cellkey),
-                     ws_ptr<Rec4<T>>(ws, L.sorted), dyn));
+  void *ws = wss[0];
+  const Batch bt = batch_of(wss, nreq);
+  const int N = pl->N;
+  const long long ncell = 2LL * N * N * N;  // half cells
+  const GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N,
+                   sizeof(T) == 4 ? 1 : 0};
+  CatArgs cat[2] = {};
+  Alphas al{};
+  for (int r = 0; r < nreq; ++r) {
+    const frsd_catalog *c2[2] = {gal[r], ran[r]};
+    for (int k = 0; k < 2; ++k) {
+      cat[k].pos[r] = c2[k]->pos;
+      cat[k].w[r] = c2[k]->w;
+      cat[k].nbar[r] = c2[k]->nbar;
+      cat[k].n[r] = c2[k]->n;
+      cat[k].off[r] = k == 0 ? 0 : gal[r]->n;
+    }
+    al.v[r] = alpha[r];
+  }
+  const int dts[2] = {dt_gal, dt_ran};
+  const unsigned nr = (unsigned)nreq;
+
+  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048, nr), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt),
+                                           ncell + 1, 0, bt));
+  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1, nr), dim3(1), 0, s,
+                                           ws_ptr<unsigned long long>(ws, L.reject), bt));
+  for (int k = 0; k < 2; ++k) {
+    auto kern = dts[k] == FRSD_F64 ? (void (*)(CatArgs, int, GeomArgs, int *, int *, int *, double *,
+                                              unsigned long long *, const double *, Batch))k_count<double>
+                                   : k_count<float>;
+    FRSD_TIMED("count", s, hipLaunchKernelGGL(kern, dim3(kIngestBlocks, nr), dim3(kIngestThreads), 0, s, cat[k], k,
+                                              g, ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot),
+                                              ws_ptr<int>(ws, L.cellkey), ws_ptr<double>(ws, L.scal_part),
+                                              ws_ptr<unsigned long long>(ws, L.reject), dyn, bt));
+  }
+  FRSD_LAUNCH_CHECK();
+  const long long n = ncell + 1;
+  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_reduce, dim3(nb, nr), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n,
+                                           ws_ptr<int>(ws, L.scan_blk), bt));
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_top, dim3(nr), dim3(256), 0, s, ws_ptr<int>(ws, L.scan_blk), nb, bt));
+  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_down, dim3(nb, nr), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n,
+                                           ws_ptr<int>(ws, L.scan_blk), bt));
+  for (int k = 0; k < 2; ++k) {
+    auto kern = dts[k] == FRSD_F64 ? (void (*)(CatArgs, int, Alphas, GeomArgs, const int *, const int *,
+                                              const int *, Rec4<T> *, const double *, Batch))k_scatter<double, T>
+                                   : k_scatter<float, T>;
+    FRSD_TIMED("scatter", s, hipLaunchKernelGGL(kern, dim3(kIngestBlocks, nr), dim3(kIngestThreads), 0, s, cat[k], k,
+                                                al, g, ws_ptr<int>(ws, L.cnt), ws_ptr<int>(ws, L.slot),
+                                                ws_ptr<int>(ws, L.cellkey), ws_ptr<Rec4<T>>(ws, L.sorted), dyn, bt));
+  }
+  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(nr), dim3(384), 0, s,
+                                              ws_ptr<double>(ws, L.scal_part), kIngestBlocks, al,
+                                              ws_ptr<double>(ws, L.scal), dyn, bt));
+  FRSD_LAUNCH_CHECK();
+  return FRSD_OK;
+}
+
+// Steps a1-a2 for the requests of a batch (ran null: no randoms); requests
+// whose catalogues of one role differ in dtype go one at a time.
+template <typename T>
+int ingest_and_sort_batch(frsd_plan *pl, void *const *wss, int nreq, const frsd_catalog *gal,
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s) {
+  const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
+  const frsd_catalog *gp[kMaxBatch], *rp[kMaxBatch];
+  for (int r = 0; r < nreq; ++r) {
+    gp[r] = &gal[r];
+    rp[r] = ran ? &ran[r] : &none;
+  }
+  int dg, dr;
+  if (role_dtype(gp, nreq, &dg) && role_dtype(rp, nreq, &dr))
+    return ingest_launches<T>(pl, wss, nreq, gp, rp, alpha, s, nullptr, dg, dr);
+  for (int r = 0; r < nreq; ++r) {
+    const int dgr = gp[r]->n ? gp[r]->dtype : FRSD_F64, drr = rp[r]->n ? rp[r]->dtype : FRSD_F64;
+    const int rc = ingest_launches<T>(pl, &wss[r], 1, &gp[r], &rp[r], &alpha[r], s, nullptr, dgr, drr);
+    if (rc) return rc;
+  }
+  return FRSD_OK;
 }
 
 template <typename T>
 int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd_catalog *ran, double alpha,
                     hipStream_t s, const double *dyn) {
-  const Layout &L = pl->L;
-  const int N = pl->N;
-  const long long ncell = 2LL * N * N * N;  // half cells
-  GeomArgs g{1.0 / pl->h, pl->p.box, pl->p.observer[0], pl->p.observer[1], pl->p.observer[2], N,
-             sizeof(T) == 4 ? 1 : 0};
-
-  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_fill_i32, dim3(2048), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), ncell + 1, 0));
-  FRSD_TIMED("fill", s, hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, ws_ptr<unsigned long long>(ws, L.reject)));
-  const frsd_catalog *cats[2] = {gal, ran};
-  long long off = 0;
-  for (int k = 0; k < 2; ++k) {
-    if (cats[k]->dtype == FRSD_F64) launch_count<double>(cats[k], k, off, g, ws, pl, s, dyn);
-    else launch_count<float>(cats[k], k, off, g, ws, pl, s, dyn);
-    off += cats[k]->n;
-  }
-  FRSD_LAUNCH_CHECK();
-  const long long n = ncell + 1;
-  const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
-  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk)));
-  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, ws_ptr<int>(ws, L.scan_blk), nb));
-  FRSD_TIMED("scan", s, hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(256), 0, s, ws_ptr<int>(ws, L.cnt), n, ws_ptr<int>(ws, L.scan_blk)));
-  off = 0;
-  for (int k = 0; k < 2; ++k) {
-    if (cats[k]->dtype == FRSD_F64) launch_scatter<double, T>(cats[k], k, off, alpha, g, ws, pl, s, dyn);
-    else launch_scatter<float, T>(cats[k], k, off, alpha, g, ws, pl, s, dyn);
-    off += cats[k]->n;
-  }
-  FRSD_TIMED("scalars", s, hipLaunchKernelGGL(k_scal_final, dim3(1), dim3(384), 0, s, ws_ptr<double>(ws, L.scal_part), kIngestBlocks, alpha,
-                     ws_ptr<double>(ws, L.scal), dyn));
-  FRSD_LAUNCH_CHECK();
-  return FRSD_OK;
+  const int dg = gal->n ? gal->dtype : FRSD_F64, dr = ran->n ? ran->dtype : FRSD_F64;
+  return ingest_launches<T>(pl, &ws, 1, &gal, &ran, &alpha, s, dyn, dg, dr);
 }
 
 template int ingest_and_sort<float>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
                                     hipStream_t, const double *);
 template int ingest_and_sort<double>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
                                      hipStream_t, const double *);
+template int ingest_and_sort_batch<float>(frsd_plan *, void *const *, int, const frsd_catalog *,
+                                          const frsd_catalog *, const double *, hipStream_t);
+template int ingest_and_sort_batch<double>(frsd_plan *, void *const *, int, const frsd_catalog *,
+                                           const frsd_catalog *, const double *, hipStream_t);
 
 }  // namespace frsd

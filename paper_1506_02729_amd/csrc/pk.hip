@@ -349,9 +349,20 @@ __global__ __launch_bounds__(256) void k_bin_reduce(const double *part, int nblk
   }
 }
 
-__global__ void k_pk_final(const double *sum, const double *scal, int nb, int ell_max, int64_t *n_modes, double *k_eff,
-                           double *p0, double *p2, double *p4, double *s00, double *s20, double *s40,
-                           double *scal_out, double *p4b, double *s22) {
+// Output arrays of every request of a batch (device views).
+struct PkOuts {
+  frsd_pk_out o[kMaxBatch];
+};
+
+// Grid (bin blocks, request of the batch); sum and scal are request 0's.
+__global__ void k_pk_final(const double *sum, const double *scal, int nb, int ell_max, PkOuts outs, Batch bt) {
+  const int r = blockIdx.y;
+  sum = moved(sum, bt.delta[r]);
+  scal = moved(scal, bt.delta[r]);
+  const frsd_pk_out &o = outs.o[r];
+  int64_t *n_modes = o.n_modes;
+  double *k_eff = o.k_eff, *p0 = o.p0, *p2 = o.p2, *p4 = o.p4, *s00 = o.s00, *s20 = o.s20, *s40 = o.s40,
+         *scal_out = o.scalars, *p4b = o.p4b, *s22 = o.s22;
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const double I22 = scal[0], N0 = scal[1];
   if (b == 0 && scal_out)
@@ -423,7 +434,7 @@ int run_bin_geometry(frsd_plan *pl, void *ws, hipStream_t s) {
   return FRSD_OK;
 }
 
-int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s);
+int run_pk_final(frsd_plan *pl, void *const *wss, int n, const frsd_pk_out *out, hipStream_t s);
 
 // Binning of n requests of one shape in one launch (grid y = request), then
 // each request's P_ell.  cached: every request's meshes hold galaxies alone,
@@ -466,11 +477,7 @@ int run_pk_batch(frsd_plan *const *pls, void *const *wss, int n, const frsd_pk_o
                                                  ws_ptr<const double>(ws, L.bin_part), pl->tune.bin_blocks, NV, nall,
                                                  p.pk_nbins, 0, ws_ptr<double>(ws, L.bin_sum), bt));
   FRSD_LAUNCH_CHECK();
-  for (int r = 0; r < n; ++r) {
-    const int rc = run_pk_final(pls[r], wss[r], &out[r], s);
-    if (rc) return rc;
-  }
-  return FRSD_OK;
+  return run_pk_final(pl, wss, n, out, s);
 }
 
 template <typename T>
@@ -478,15 +485,22 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool 
   return run_pk_batch<T>(&pl, &ws, 1, out, s, cached);
 }
 
-// P_ell from the bin sums (slots 0-5 of every P_ell bin) and the scalars.
-int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
+// P_ell from the bin sums (slots 0-5 of every P_ell bin) and the scalars,
+// for the n requests of a batch (out: their device views).
+int run_pk_final(frsd_plan *pl, void *const *wss, int n, const frsd_pk_out *out, hipStream_t s) {
   const Layout &L = pl->L;
   const frsd_params &p = pl->p;
-  FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256), dim3(256), 0, s, ws_ptr<const double>(ws, L.bin_sum),
-                     ws_ptr<const double>(ws, L.scal), p.pk_nbins, p.ell_max, out->n_modes, out->k_eff, out->p0, out->p2,
-                     out->p4, out->s00, out->s20, out->s40, out->scalars, out->p4b, out->s22));
+  PkOuts po{};
+  for (int r = 0; r < n; ++r) po.o[r] = out[r];
+  FRSD_TIMED("pk_final", s, hipLaunchKernelGGL(k_pk_final, dim3((p.pk_nbins + 255) / 256, n), dim3(256), 0, s,
+                                               ws_ptr<const double>(wss[0], L.bin_sum),
+                                               ws_ptr<const double>(wss[0], L.scal), p.pk_nbins, p.ell_max, po,
+                                               batch_of(wss, n)));
   FRSD_LAUNCH_CHECK();
   return FRSD_OK;
+}
+int run_pk_final(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s) {
+  return run_pk_final(pl, &ws, 1, out, s);
 }
 
 template int run_pk<float>(frsd_plan *, void *, const frsd_pk_out *, hipStream_t, bool);

@@ -147,3 +147,28 @@ def test_largest_batch(gpu_lib):
     # plan 3 holds request 8's meshes: P_ell again from them
     again = {k: v.cpu().numpy().copy() for k, v in plans[3].pk().items()}
     _same(again, outs2[0], CLOSE[64])
+
+
+def test_batch_catalogue_dtypes(gpu_lib):
+    """FP32 catalogues in a batch (the ingest reads them as they are), and a
+    batch mixing FP32 and FP64 catalogues (ingested one request at a time),
+    on FP64 plans; the oracle gets the same FP32-rounded catalogues."""
+    import torch
+    dev = torch.device("cuda:0")
+    _log("case: batch catalogue dtypes N=48 FP64")
+    reqs, prm = _requests(3, 48, seed=980)
+
+    def rounded(c):
+        return {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in c.items()}
+
+    cap = max(len(g["w"]) + len(r["w"]) for g, r, _ in reqs)
+    cfg = _cfg(gpu_lib, prm, 64, cap)
+    plans = [gpu_lib.Plan(cfg, device=dev) for _ in reqs]
+    for dts in ((torch.float32,) * 3, (torch.float32, torch.float64, torch.float32)):
+        gals = [gpu_lib.device_catalog(g, dev, dt) for (g, _, _), dt in zip(reqs, dts)]
+        rans = [gpu_lib.device_catalog(r, dev, dt) for (_, r, _), dt in zip(reqs, dts)]
+        outs = gpu_lib.run_batch(plans, gals, rans, [a for _, _, a in reqs])
+        for k, ((g, r, a), dt) in enumerate(zip(reqs, dts)):
+            if dt == torch.float32:
+                g, r = rounded(g), rounded(r)
+            _check_pk(outs[k], est.pk_multipoles(g, r, a, prm), prm, 64)
