@@ -88,11 +88,11 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
   C *lds = tw + N;
   const int ld = N + 1;
 
-  const int req = (int)blockIdx.y / n_mesh, mi = (int)blockIdx.y - req * n_mesh;
-  const long long dr = bt.delta[req];
-  colmask = shifted(colmask, dr);
-  xmask = shifted(xmask, dr);
-  C *mesh = shifted(data, dr) + (long long)mi * batch_stride;
+  const int req = bt.n > 1 ? (int)blockIdx.y / n_mesh : 0, mi = (int)blockIdx.y - req * n_mesh;
+  const long long dr = bt.n > 1 ? bt.delta[req] : 0;
+  colmask = moved(colmask, dr);
+  xmask = moved(xmask, dr);
+  C *mesh = moved(data, dr) + (long long)mi * batch_stride;
   const long long NN = (long long)N * N;
 
   if (AXIS == 2) {
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(FftTune<T>::threads) void k_fft_axis(cplx_t<T> *dat
     if (!__syncthreads_or(any)) return;  // every row of the block is empty
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = tw_g[i];
     const int tot = npen * N;
-    const T *re = shifted(planar, dr) + 2 * (long long)mi * batch_stride + q0 * N;
+    const T *re = moved(planar, dr) + 2 * (long long)mi * batch_stride + q0 * N;
     const T *im = re + batch_stride;
     for (int f = threadIdx.x; f < tot; f += NT) {
       const int p = f / N, e = f - p * N;
@@ -181,8 +181,9 @@ __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data,
     const long long grp = it / n_all;
     const int slot = (int)(it - grp * n_all);
     const int req = slot / n_mesh, mi = slot - req * n_mesh;
-    const long long dr = bt.delta[req];
-    const uint8_t *cm = shifted(colmask, dr);
+    // (a single request loads no distance: nothing waits on it before the mask loads)
+    const long long dr = bt.n > 1 ? bt.delta[req] : 0;
+    const uint8_t *cm = moved(colmask, dr);
     const long long q0 = grp * P;
     const int npen = (int)((q0 + P <= NN) ? P : (NN - q0));
     int any = 0;
@@ -191,9 +192,9 @@ __global__ __launch_bounds__(FwdTune<T>::nt_row) void k_fft_row(cplx_t<T> *data,
       any |= live[p];
     }
     if (!__syncthreads_or(any)) continue;  // (the barrier also publishes tw and live)
-    const T *re = shifted(planar, dr) + 2 * (long long)mi * batch_stride + q0 * LEN;
+    const T *re = moved(planar, dr) + 2 * (long long)mi * batch_stride + q0 * LEN;
     const T *im = re + batch_stride;
-    C *dst = shifted(data, dr) + (long long)mi * batch_stride + q0 * LEN;
+    C *dst = moved(data, dr) + (long long)mi * batch_stride + q0 * LEN;
     fft_pencils<C, LEN, P, NT, false, false>(
         lds, tw, npen,
         [&](int p, int e) {
@@ -217,10 +218,10 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   using C = cplx_t<T>;
   constexpr int P = p_col<T, LEN>(), NT = FwdTune<T>::nt_col;
   constexpr long long NN = (long long)LEN * LEN;
-  const int req = (int)blockIdx.y / n_mesh, mi = (int)blockIdx.y - req * n_mesh;
-  const long long dr = bt.delta[req];
-  colmask = shifted(colmask, dr);
-  xmask = shifted(xmask, dr);
+  const int req = bt.n > 1 ? (int)blockIdx.y / n_mesh : 0, mi = (int)blockIdx.y - req * n_mesh;
+  const long long dr = bt.n > 1 ? bt.delta[req] : 0;
+  colmask = moved(colmask, dr);
+  xmask = moved(xmask, dr);
   const int nzb = keep.nba + keep.nbb;
   const int outer_i = blockIdx.x / nzb;
   int z0, npen;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(FwdTune<T>::nt_col) void k_fft_col(cplx_t<T> *data,
   }
   __syncthreads();
   constexpr long long es = (AXIS == 1) ? LEN : NN;
-  C *col = shifted(data, dr) + (long long)mi * batch_stride +
+  C *col = moved(data, dr) + (long long)mi * batch_stride +
            ((AXIS == 1) ? (long long)outer * NN : (long long)outer * LEN) + z0;
   // in place: every load happens in the first stage, every store in the last
   // (y pass: columns (n_y = e, n_z) outside the disc are not written; x

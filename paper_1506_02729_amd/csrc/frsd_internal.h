@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fastrsd.h"
@@ -128,15 +129,18 @@ inline Batch batch_of(void *const *ws, int n) {
   for (int r = 0; r < n; ++r) b.delta[r] = static_cast<char *>(ws[r]) - static_cast<char *>(ws[0]);
   return b;
 }
-// p moved by d bytes (a null p stays null: optional regions)
-template <typename P>
-__host__ __device__ __forceinline__ P *shifted(P *p, long long d) {
-  return p ? reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + d) : p;
-}
-// the same for a pointer that is never null
+// p moved by d bytes.  Byte-pointer arithmetic, not an integer round trip:
+// the compiler then still knows a kernel argument moved this way points to
+// global memory and keeps global (not flat) loads and stores.
 template <typename P>
 __host__ __device__ __forceinline__ P *moved(P *p, long long d) {
-  return reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + d);
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P *>(reinterpret_cast<B *>(p) + d);
+}
+// the same for an optional region (a null p stays null)
+template <typename P>
+__host__ __device__ __forceinline__ P *shifted(P *p, long long d) {
+  return p ? moved(p, d) : p;
 }
 
 // One constant table of a plan: bytes at host_off of the plan's host table

@@ -103,6 +103,7 @@ struct GridArgs {
                        // m0..n_ell_mom-1 per pass; planes are numbered from m0)
   double ou[3];        // observer in grid units
   long long plane_stride;
+  int sx;              // x-sweep: nodes along x per workgroup (64, 32 or 16)
 };
 
 // Add the moment-weighted contribution s of one object to the 16
@@ -452,18 +453,18 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(sizeo
   __shared__ int wtot[kSThreads / 64];
   __shared__ uint8_t step_live[kSStepsMax];  // slab of the step holds an object in the patch's y range
 
-  const int N = ga.N;
+  const int N = ga.N, SX = ga.sx;
   const int nyb = N / kSY, nzb = N / kSZ;
   const int bz = blockIdx.x % nzb, by = (blockIdx.x / nzb) % nyb, bx = blockIdx.x / (nzb * nyb);
-  const int X0 = bx * kSX, Y0 = by * kSY, Z0 = bz * kSZ;
+  const int X0 = bx * SX, Y0 = by * kSY, Z0 = bz * kSZ;
   const int ly = threadIdx.x / kSZ, lz = threadIdx.x % kSZ;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  constexpr int NSTEP = kSX + RING - 1;
+  const int NSTEP = SX + RING - 1;  // <= kSStepsMax
   for (int i = threadIdx.x; i < NSTEP; i += kSThreads) step_live[i] = 0;
   {  // patches with no node in reach of an object write nothing
     int live = 0;
-    for (int t = threadIdx.x; t < kSX * kSY; t += kSThreads)
+    for (int t = threadIdx.x; t < SX * kSY; t += kSThreads)
       live |= colmask[(long long)(X0 + t / kSY) * N + (Y0 + t % kSY)];
     if (!__syncthreads_or(live)) return;
   }
@@ -688,7 +689,11 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
                                                  ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc), bt));
   if constexpr (P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
-      const unsigned nblk = (unsigned)((N / kSX) * (N / kSY) * (N / kSZ));
+      // shorter x runs for small meshes, so that the launch (all requests of
+      // a batch) still has >= 2048 workgroups where it can
+      ga.sx = kSX;
+      while (ga.sx > 16 && (long long)(N / ga.sx) * (N / kSY) * (N / kSZ) * bt.n < 2048) ga.sx /= 2;
+      const unsigned nblk = (unsigned)((N / ga.sx) * (N / kSY) * (N / kSZ));
       FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk, bt.n), dim3(kSThreads), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
                                                ws_ptr<const uint8_t>(ws, L.colmask), ws_ptr<const uint8_t>(ws, L.colocc),

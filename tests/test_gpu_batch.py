@@ -55,18 +55,19 @@ def _same(a, b, close, keys=KEYS):
     np.testing.assert_allclose(a["scalars"], b["scalars"], rtol=1e-12)
 
 
-@pytest.mark.parametrize("precision,N,interlace,ell_max,nbk", [
-    (32, 64, True, 4, 5),    # compiled FFT length, x-sweep assignment, bispectrum after the batch
-    (64, 64, True, 4, 5),
-    (32, 48, False, 2, 0),   # slots pairing two planes, P_ell only
-    (64, 80, True, 4, 0),    # run-time FFT length (pencil kernels)
-    (32, 80, False, 4, 0),
+@pytest.mark.parametrize("precision,N,interlace,ell_max,nbk,n_req", [
+    (32, 64, True, 4, 5, 3),    # compiled FFT length, x-sweep (16-node runs), bispectrum after the batch
+    (64, 64, True, 4, 5, 3),
+    (32, 128, True, 4, 0, 4),   # x-sweep with 32-node runs (4 x 256 workgroups)
+    (32, 48, False, 2, 0, 3),   # slots pairing two planes, P_ell only
+    (64, 80, True, 4, 0, 3),    # run-time FFT length (pencil kernels)
+    (32, 80, False, 4, 0, 3),
 ])
-def test_batch_matches_alone_and_oracle(gpu_lib, precision, N, interlace, ell_max, nbk):
+def test_batch_matches_alone_and_oracle(gpu_lib, precision, N, interlace, ell_max, nbk, n_req):
     import torch
     dev = torch.device("cuda:0")
-    _log(f"case: batch of 3 N={N} interlace={interlace} ell_max={ell_max} nbk={nbk} precision={precision}")
-    reqs, prm = _requests(3, N, interlace, ell_max, nbk)
+    _log(f"case: batch of {n_req} N={N} interlace={interlace} ell_max={ell_max} nbk={nbk} precision={precision}")
+    reqs, prm = _requests(n_req, N, interlace, ell_max, nbk)
     cap = max(len(g["w"]) + len(r["w"]) for g, r, _ in reqs)
     cfg = _cfg(gpu_lib, prm, precision, cap)
     plans = [gpu_lib.Plan(cfg, device=dev) for _ in reqs]
