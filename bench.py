@@ -22,8 +22,10 @@ product is priced in bf16 MFMA flops against 2.5 PF/s.
 
 The "serving" object is the served covariance run (Poisson arrivals of
 uneven mocks on 256^3, 384^3 and 512^3 meshes, admission by HBM footprint,
-p50/p99 latency, the plain FP64 path one request at a time beside it), and
-"cpu_baseline" the FP64 oracle on this host's cores.
+p50/p99 latency, the plain FP64 path one request at a time beside it),
+"small_mesh_batches" the covariance mocks of --batch-study on 64^3 and 128^3
+meshes (one at a time, three streams, and request batches of frsd_pk_batch),
+and "cpu_baseline" the FP64 oracle on this host's cores.
 
 Prints one JSON line (see the "metric" key).  --gpus N > 1 is refused: the
 build targets one GPU.
@@ -886,6 +888,7 @@ def main():
                     help="run only the small-mesh study: one at a time vs 3 streams vs batched requests")
     ap.add_argument("--batch-mocks", type=int, default=64, help="batch study: mocks per timed pass")
     ap.add_argument("--batch-n", default="64,128,256", help="batch study: mesh sides")
+    ap.add_argument("--no-batch-study", action="store_true", help="skip the small-mesh batch study of the default run")
     ap.add_argument("--batch-profile", action="store_true", help="batch study: batches of 16 only")
     ap.add_argument("--large-mesh", action="store_true",
                     help="run only the 1024^3 streamed precision sweep (FP32 vs FP64 vs the stored oracle)")
@@ -1078,6 +1081,13 @@ def main():
         serve = serving(args, F, torch, synth, dev, log)
         torch.cuda.empty_cache()
 
+    batches = None
+    if not args.no_batch_study:
+        # request batches on small meshes (the study of --batch-study at 64^3 and 128^3)
+        bargs = argparse.Namespace(**{**vars(args), "batch_n": "64,128", "batch_profile": False})
+        batches = batch_study(bargs, F, torch, synth, dev, log)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, pool[0][0], ran, pool[0][1], observer, M)
@@ -1108,6 +1118,7 @@ def main():
         "fp64_plain": fp64,
         "served_with_random_cache": cached,
         "serving": serve,
+        "small_mesh_batches": batches,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
