@@ -297,6 +297,22 @@ int frsd_graph_create(frsd_plan *plan, void *ws, const frsd_catalog *gal, const 
 int frsd_graph_launch(frsd_graph *graph, int64_t n_gal, int64_t n_ran, double alpha, void *stream);
 void frsd_graph_destroy(frsd_graph *graph);
 
+/* A batch of requests captured as one graph: the launches of frsd_pk_batch
+ * (same arguments and checks; ran non-NULL: no random cache) recorded on
+ * `stream` (non-null) for these catalogue buffers, whose sizes are
+ * capacities, and outputs.  frsd_graph_launch_batch replays it with request
+ * r taking the first n_gal[r] / n_ran[r] objects of its buffers and alpha[r]
+ * (host arrays of the captured batch size; the sizes and alpha are written
+ * into each workspace by a kernel before the replay).  FRSD_ENOMEM for sizes
+ * beyond the capacities, FRSD_EINVAL for frsd_graph_launch on a batch
+ * graph; frsd_graph_launch_batch also replays a graph of one request.
+ * Destroyed with frsd_graph_destroy. */
+int frsd_graph_create_batch(frsd_plan *const *plans, void *const *workspaces, int32_t n, const frsd_catalog *gal,
+                            const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, void *stream,
+                            frsd_graph **graph);
+int frsd_graph_launch_batch(frsd_graph *graph, const int64_t *n_gal, const int64_t *n_ran, const double *alpha,
+                            void *stream);
+
 /* Synchronises `stream` and reports the number of objects rejected by the
  * last frsd_mesh_assign (outside [0, L)^3 or at the observer).  Returns
  * FRSD_EDOM when that number is non-zero. */

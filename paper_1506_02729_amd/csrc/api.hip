@@ -252,9 +252,11 @@ static bool same_params(const frsd_params &a, const frsd_params &b) {
   return eq;
 }
 
-extern "C" int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, int32_t n, const frsd_catalog *gal,
-                             const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, void *stream) {
-  clear_error();
+// Validation of a batch (every request before any device work) and the
+// device views of its catalogues and outputs (ran null: no randoms).
+int frsd::batch_views(frsd_plan *const *plans, void *const *workspaces, int n, const frsd_catalog *gal,
+                      const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, frsd_catalog *gd,
+                      frsd_catalog *rd, frsd_pk_out *od) {
   if (n < 1 || n > kMaxBatch) return fail(FRSD_EINVAL, "batch size must be 1..FRSD_MAX_BATCH");
   if (!plans || !workspaces || !gal || !alpha || !out) return fail(FRSD_EINVAL, "null argument");
   const bool cached = ran == nullptr;
@@ -267,13 +269,13 @@ extern "C" int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, i
       if (workspaces[q] == workspaces[r] || plans[q] == plans[r])
         return fail(FRSD_EINVAL, "a plan or workspace appears twice in the batch");
   }
-  frsd_plan *pl0 = plans[0];
-  if (pl0->p.stream_moments) return fail(FRSD_EINVAL, "streamed plans are not batched");
+  if (plans[0]->p.stream_moments) return fail(FRSD_EINVAL, "streamed plans are not batched");
   for (int r = 0; r < n; ++r) {
     frsd_plan *pl = plans[r];
     if (pl->state < 1 || pl->init_ws != workspaces[r])
       return fail(FRSD_ESTATE, "workspace not initialised by frsd_plan_init");
-    if (cached && !pl->cache_ready) return fail(FRSD_ESTATE, "a batch without randoms needs frsd_random_cache on every workspace");
+    if (cached && !pl->cache_ready)
+      return fail(FRSD_ESTATE, "a batch without randoms needs frsd_random_cache on every workspace");
     if ((rc = check_catalog(&gal[r], false, "galaxies"))) return rc;
     if (!cached && (rc = check_catalog(&ran[r], true, "randoms"))) return rc;
     if (!std::isfinite(alpha[r])) return fail(FRSD_EINVAL, "alpha must be finite");
@@ -284,14 +286,23 @@ extern "C" int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, i
     if (!o.n_modes || !o.k_eff || !o.p0 || !o.p2 || !o.p4 || !o.s00 || !o.s20 || !o.s40 || !o.scalars)
       return fail(FRSD_EINVAL, "null output array");
   }
-  frsd_catalog gd[kMaxBatch], rd[kMaxBatch];
-  frsd_pk_out od[kMaxBatch];
   for (int r = 0; r < n; ++r) {
     if ((rc = device_view(&gal[r], &gd[r])) || (rc = device_view(&out[r], &od[r]))) return rc;
     if (!cached && (rc = device_view(&ran[r], &rd[r]))) return rc;
   }
+  return FRSD_OK;
+}
+
+extern "C" int frsd_pk_batch(frsd_plan *const *plans, void *const *workspaces, int32_t n, const frsd_catalog *gal,
+                             const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, void *stream) {
+  clear_error();
+  frsd_catalog gd[kMaxBatch], rd[kMaxBatch];
+  frsd_pk_out od[kMaxBatch];
+  int rc = batch_views(plans, workspaces, n, gal, ran, alpha, out, gd, rd, od);
+  if (rc) return rc;
+  const bool cached = ran == nullptr;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool f64 = pl0->p.precision == FRSD_F64;
+  const bool f64 = plans[0]->p.precision == FRSD_F64;
   rc = f64 ? run_mesh_assign_batch<double>(plans, workspaces, n, gd, cached ? nullptr : rd, alpha, s)
            : run_mesh_assign_batch<float>(plans, workspaces, n, gd, cached ? nullptr : rd, alpha, s);
   if (rc) return rc;

@@ -254,9 +254,16 @@ int run_pk(frsd_plan *pl, void *ws, const frsd_pk_out *out, hipStream_t s, bool 
 // sort and assignment, then one forward FFT over every request's meshes
 // (ran null: galaxies against each plan's random cache); one binning over
 // every request's meshes, then each request's P_ell
+// (dyn: request 0's {N_g, N_r, alpha}, each request's read from its own
+// workspace, for graph replays)
 template <typename T>
 int run_mesh_assign_batch(frsd_plan *const *pl, void *const *ws, int n, const frsd_catalog *gal,
-                          const frsd_catalog *ran, const double *alpha, hipStream_t s);
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s, const double *dyn = nullptr);
+// Checks a batch (FRSD_E* before any device work) and fills the device views
+// gd, rd (ran non-null) and od of its n requests.
+int batch_views(frsd_plan *const *plans, void *const *workspaces, int n, const frsd_catalog *gal,
+                const frsd_catalog *ran, const double *alpha, const frsd_pk_out *out, frsd_catalog *gd,
+                frsd_catalog *rd, frsd_pk_out *od);
 template <typename T>
 int run_pk_batch(frsd_plan *const *pl, void *const *ws, int n, const frsd_pk_out *out, hipStream_t s, bool cached);
 // streamed plans (stream.hip): moment groups accumulated into R_0, R_2, R_4

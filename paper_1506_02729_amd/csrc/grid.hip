@@ -51,7 +51,7 @@ int ingest_and_sort(frsd_plan *pl, void *ws, const frsd_catalog *gal, const frsd
                     hipStream_t s, const double *dyn);
 template <typename T>
 int ingest_and_sort_batch(frsd_plan *pl, void *const *wss, int nreq, const frsd_catalog *gal,
-                          const frsd_catalog *ran, const double *alpha, hipStream_t s);
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s, const double *dyn);
 void scal_keep(frsd_plan *pl, void *ws, hipStream_t s);
 void scal_cached(frsd_plan *pl, void *ws, double alpha, hipStream_t s);
 void scal_cached_batch(frsd_plan *pl, void *const *wss, int nreq, const double *alpha, hipStream_t s);
@@ -807,8 +807,8 @@ int run_mesh_assign_cached(frsd_plan *pl, void *ws, const frsd_catalog *gal, dou
 // against each plan's random cache.
 template <typename T>
 int run_mesh_assign_batch(frsd_plan *const *pls, void *const *wss, int n, const frsd_catalog *gal,
-                          const frsd_catalog *ran, const double *alpha, hipStream_t s) {
-  int rc = ingest_and_sort_batch<T>(pls[0], wss, n, gal, ran, alpha, s);
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s, const double *dyn) {
+  int rc = ingest_and_sort_batch<T>(pls[0], wss, n, gal, ran, alpha, s, dyn);
   if (rc) return rc;
   if (!ran) scal_cached_batch(pls[0], wss, n, alpha, s);
   const Batch bt = batch_of(wss, n);
@@ -817,9 +817,9 @@ int run_mesh_assign_batch(frsd_plan *const *pls, void *const *wss, int n, const 
 }
 
 template int run_mesh_assign_batch<float>(frsd_plan *const *, void *const *, int, const frsd_catalog *,
-                                          const frsd_catalog *, const double *, hipStream_t);
+                                          const frsd_catalog *, const double *, hipStream_t, const double *);
 template int run_mesh_assign_batch<double>(frsd_plan *const *, void *const *, int, const frsd_catalog *,
-                                           const frsd_catalog *, const double *, hipStream_t);
+                                           const frsd_catalog *, const double *, hipStream_t, const double *);
 template int run_random_cache<float>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
 template int run_random_cache<double>(frsd_plan *, void *, const frsd_catalog *, hipStream_t);
 template int run_mesh_assign_cached<float>(frsd_plan *, void *, const frsd_catalog *, double, hipStream_t);

@@ -449,10 +449,11 @@ static int ingest_launches(frsd_plan *pl, void *const *wss, int nreq, const frsd
 }
 
 // Steps a1-a2 for the requests of a batch (ran null: no randoms); requests
-// whose catalogues of one role differ in dtype go one at a time.
+// whose catalogues of one role differ in dtype go one at a time.  dyn (may
+// be null): request 0's {N_g, N_r, alpha}, each request's in its workspace.
 template <typename T>
 int ingest_and_sort_batch(frsd_plan *pl, void *const *wss, int nreq, const frsd_catalog *gal,
-                          const frsd_catalog *ran, const double *alpha, hipStream_t s) {
+                          const frsd_catalog *ran, const double *alpha, hipStream_t s, const double *dyn) {
   const frsd_catalog none{nullptr, nullptr, nullptr, 0, FRSD_F64};
   const frsd_catalog *gp[kMaxBatch], *rp[kMaxBatch];
   for (int r = 0; r < nreq; ++r) {
@@ -461,10 +462,11 @@ int ingest_and_sort_batch(frsd_plan *pl, void *const *wss, int nreq, const frsd_
   }
   int dg, dr;
   if (role_dtype(gp, nreq, &dg) && role_dtype(rp, nreq, &dr))
-    return ingest_launches<T>(pl, wss, nreq, gp, rp, alpha, s, nullptr, dg, dr);
+    return ingest_launches<T>(pl, wss, nreq, gp, rp, alpha, s, dyn, dg, dr);
   for (int r = 0; r < nreq; ++r) {
     const int dgr = gp[r]->n ? gp[r]->dtype : FRSD_F64, drr = rp[r]->n ? rp[r]->dtype : FRSD_F64;
-    const int rc = ingest_launches<T>(pl, &wss[r], 1, &gp[r], &rp[r], &alpha[r], s, nullptr, dgr, drr);
+    const double *dyn_r = dyn ? ws_ptr<const double>(wss[r], pl->L.dyn) : nullptr;
+    const int rc = ingest_launches<T>(pl, &wss[r], 1, &gp[r], &rp[r], &alpha[r], s, dyn_r, dgr, drr);
     if (rc) return rc;
   }
   return FRSD_OK;
@@ -482,8 +484,8 @@ template int ingest_and_sort<float>(frsd_plan *, void *, const frsd_catalog *, c
 template int ingest_and_sort<double>(frsd_plan *, void *, const frsd_catalog *, const frsd_catalog *, double,
                                      hipStream_t, const double *);
 template int ingest_and_sort_batch<float>(frsd_plan *, void *const *, int, const frsd_catalog *,
-                                          const frsd_catalog *, const double *, hipStream_t);
+                                          const frsd_catalog *, const double *, hipStream_t, const double *);
 template int ingest_and_sort_batch<double>(frsd_plan *, void *const *, int, const frsd_catalog *,
-                                           const frsd_catalog *, const double *, hipStream_t);
+                                           const frsd_catalog *, const double *, hipStream_t, const double *);
 
 }  // namespace frsd

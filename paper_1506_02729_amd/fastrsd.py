@@ -102,6 +102,8 @@ _proto = {
                                          _P, ctypes.POINTER(_P)]),
     "frsd_graph_launch": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, _P]),
     "frsd_graph_destroy": (None, [_P]),
+    "frsd_graph_create_batch": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "frsd_graph_launch_batch": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "frsd_status": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]),
     "frsd_profile": (ctypes.c_int, [ctypes.c_int]),
     "frsd_profile_report": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -232,6 +234,22 @@ def frsd_graph_launch(graph: int, n_gal: int, n_ran: int, alpha: float, stream) 
 
 def frsd_graph_destroy(graph: int) -> None:
     _lib.frsd_graph_destroy(graph)
+
+
+def frsd_graph_create_batch(plans, ws_ptrs, gals, rans, alphas, outs, stream) -> int:
+    n = len(plans)
+    h = _P()
+    _check(_lib.frsd_graph_create_batch((_P * n)(*plans), (_P * n)(*ws_ptrs), n, (frsd_catalog * n)(*gals),
+                                        (frsd_catalog * n)(*rans), (ctypes.c_double * n)(*[float(a) for a in alphas]),
+                                        (frsd_pk_out * n)(*outs), stream, ctypes.byref(h)))
+    return h.value
+
+
+def frsd_graph_launch_batch(graph: int, n_gal, n_ran, alphas, stream) -> None:
+    n = len(n_gal)
+    _check(_lib.frsd_graph_launch_batch(graph, (ctypes.c_int64 * n)(*[int(v) for v in n_gal]),
+                                        (ctypes.c_int64 * n)(*[int(v) for v in n_ran]),
+                                        (ctypes.c_double * n)(*[float(a) for a in alphas]), stream))
 
 
 def frsd_status(plan, ws_ptr, stream) -> int:
@@ -501,6 +519,35 @@ def run_batch(plans: list, gals: list, rans: list | None, alphas: list) -> list:
         if rej:
             raise FrsdError(FRSD_EDOM, f"{rej} objects outside the box or at the observer")
     return [{k: v.cpu().numpy().copy() for k, v in b.items()} for b in bufs]
+
+
+def capture_batch(plans: list, gals: list, rans: list, alphas: list) -> "BatchGraph":
+    """Capture one frsd_pk_batch of these requests (catalogue buffers of
+    capacity size, randoms required) on the plans' common stream."""
+    stream = plans[0].stream
+    if any(p.stream != stream for p in plans):
+        raise ValueError("the plans of a batch must share one stream")
+    h = frsd_graph_create_batch([p.handle for p in plans], [p.ws_ptr for p in plans], [_c_catalog(g) for g in gals],
+                                [_c_catalog(c) for c in rans], alphas, [p._pk_out() for p in plans],
+                                stream.cuda_stream)
+    return BatchGraph(plans, h, (gals, rans))
+
+
+class BatchGraph:
+    """A batch captured by capture_batch; launch() replays it with request r
+    taking the first n_gal[r] / n_ran[r] objects of its buffers."""
+
+    def __init__(self, plans, handle: int, keep):
+        self.plans, self.handle, self._keep = plans, handle, keep
+
+    def launch(self, n_gal, n_ran, alphas) -> None:
+        frsd_graph_launch_batch(self.handle, n_gal, n_ran, alphas, self.plans[0].stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            frsd_graph_destroy(h)
+            self.handle = None
 
 
 class Graph:

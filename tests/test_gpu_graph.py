@@ -87,3 +87,62 @@ def test_graph_replays_match_eager_requests(gpu_lib, precision):
         graph.launch(len(gal["w"]) + 1, len(ran["w"]), alpha)
     assert ei.value.code == F.FRSD_ENOMEM
     del graph
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_batch_graph_replays_match_eager_batches(gpu_lib, precision):
+    """A batch of three 48^3 requests captured as one graph
+    (frsd_graph_create_batch), replayed with other sizes, contents and alpha
+    per request (frsd_graph_launch_batch), with eager batches and
+    synchronisations between the replays: each replay against the eager
+    batch on the same data and against the oracle."""
+    import torch
+    F = gpu_lib
+    dev = torch.device("cuda:0")
+    _log(f"case: graph capture of a batch of three 48^3 requests, precision={precision}")
+    sets = []
+    for k in range(3):
+        g, r, a, prm = _bk_case(170 + k, N=48, nbk=1, n_gal=2500 + 400 * k, n_ran=12000 + 1500 * k)
+        g2, r2, _, _ = _bk_case(180 + k, N=48, nbk=1, n_gal=1600 + 300 * k, n_ran=8000 + 900 * k)
+        sets.append(((g, r, a), (g2, r2, len(g2["w"]) / len(r2["w"]))))
+    prm.bk_nbins = 0
+    cap = max(len(s[0][0]["w"]) + len(s[0][1]["w"]) for s in sets)
+    cfg = _cfg(F, prm, precision, cap)
+    stream = torch.cuda.Stream(dev)
+    plans = [F.Plan(cfg, device=dev, stream=stream) for _ in sets]
+    eager = [F.Plan(cfg, device=dev, stream=stream) for _ in sets]
+
+    def buffers(c):
+        return {k: torch.zeros((len(c["w"]), 3) if k == "pos" else len(c["w"]), dtype=torch.float64, device=dev)
+                for k in ("pos", "w", "nbar")}
+
+    gbufs = [buffers(s[0][0]) for s in sets]
+    rbufs = [buffers(s[0][1]) for s in sets]
+    for k, s in enumerate(sets):
+        _fill(gbufs[k], s[0][0], torch)
+        _fill(rbufs[k], s[0][1], torch)
+    torch.cuda.synchronize()
+    graph = F.capture_batch(plans, gbufs, rbufs, [s[0][2] for s in sets])
+    close = 1e-5 if precision == 32 else 1e-10
+    for rep, which in enumerate((0, 1, 0, 1)):
+        reqs = [s[which] for s in sets]
+        _log(f"  replay {rep}: " + ", ".join(f"{len(g['w'])} + {len(r['w'])}" for g, r, _ in reqs))
+        for k, (g, r, _) in enumerate(reqs):
+            _fill(gbufs[k], g, torch)
+            _fill(rbufs[k], r, torch)
+        torch.cuda.synchronize()
+        graph.launch([len(g["w"]) for g, _, _ in reqs], [len(r["w"]) for _, r, _ in reqs], [a for _, _, a in reqs])
+        torch.cuda.synchronize()
+        got = [{k: v.cpu().numpy().copy() for k, v in p.pk_buf.items()} for p in plans]
+        ref = F.run_batch(eager, [F.device_catalog(g, dev) for g, _, _ in reqs],
+                          [F.device_catalog(r, dev) for _, r, _ in reqs], [a for _, _, a in reqs])
+        for k, (g, r, a) in enumerate(reqs):
+            np.testing.assert_array_equal(got[k]["n_modes"], ref[k]["n_modes"])
+            np.testing.assert_allclose(got[k]["scalars"], ref[k]["scalars"], rtol=1e-12)
+            for key in ("p0", "p2", "p4", "p4b", "s00"):
+                scale = np.max(np.abs(ref[k][key]))
+                assert np.max(np.abs(got[k][key] - ref[k][key])) <= close * scale, (rep, k, key)
+            if rep < 2:
+                _check_pk(got[k], est.pk_multipoles(g, r, a, prm), prm, precision)
+    with pytest.raises(F.FrsdError):
+        F.frsd_graph_launch(graph.handle, 10, 10, 0.1, stream.cuda_stream)  # a batch graph needs the batch call
