@@ -671,12 +671,93 @@ def batch_study(args, F, torch, synth, dev, log):
         del plans, side, second
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    served = None
+    if not args.batch_profile and args.batch_requests > 0:
+        served = batch_serving(args, F, torch, dev, log, dev_mocks, r_dev, observer, box, n_ran)
     return {"metric": "small-mesh covariance throughput (mocks/s): one at a time vs 3 streams vs batched requests",
             "unit": "mocks/s", "mocks_timed": K,
             "config": {"workload": "lognormal mocks 2e5 galaxies (8 distinct, seeds 6000+i, cycled) against one "
                                    "cached 1e7-random catalogue, 3500 Mpc/h box, TSC interlaced, P_ell l=0,2,4 in bins "
                                    "of 0.005 to min(0.225, 0.95 k_Ny), FP32"},
-            "data": "synthetic", "results": results}
+            "data": "synthetic", "results": results, "served": served}
+
+
+def batch_serving(args, F, torch, dev, log, dev_mocks, r_dev, observer, box, n_ran):
+    """Continuous batching of small meshes: Poisson arrivals (--batch-rates
+    per second: one rate for 64^3, one for 128^3) of --batch-requests
+    covariance mocks (the batch study's, cycled), served two ways.  Per request:
+    three plans with a stream each; a queued request takes the first free
+    plan (frsd_mesh_assign_cached + frsd_pk_multipoles).  Batched: two groups
+    of 8 plans with a stream each; a free group takes every queued request
+    (up to 8) as one frsd_pk_batch, so requests that arrive while a batch runs
+    form the next one.  Outputs go to page-locked host arrays; latency runs
+    from arrival to the completion event of the request's launch."""
+    out = {}
+    R = args.batch_requests
+    for N, rate in zip((64, 128), (float(v) for v in args.batch_rates.split(","))):
+        nb = int(min(0.225, 0.95 * math.pi * N / box) / 0.005)
+        cfg = F.Config(n_grid=N, box=box, observer=observer, order=3, interlace=True, compensate=True, ell_max=4,
+                       precision=32, pk_kmin=0.0, pk_dk=0.005, pk_nbins=nb, max_objects=max(int(3e5), n_ran),
+                       random_cache=True)
+        rng = np.random.Generator(np.random.PCG64(7000 + N))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, R))
+        row = {}
+        for mode in ("per_request", "batched"):
+            if mode == "per_request":
+                groups = [[F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev), host_outputs=True)] for _ in range(3)]
+            else:
+                groups = []
+                for _ in range(2):
+                    st = torch.cuda.Stream(dev)
+                    groups.append([F.Plan(cfg, device=dev, stream=st, host_outputs=True) for _ in range(8)])
+            for grp in groups:
+                for pl in grp:
+                    pl.random_cache(r_dev)
+            torch.cuda.synchronize()
+            busy = [None] * len(groups)  # (event, request ids) in flight per group
+            done = np.zeros(R)
+            sizes = []
+            nxt = 0
+            queue = []
+            t0 = time.perf_counter()
+            finished = 0
+            while finished < R:
+                now = time.perf_counter() - t0
+                while nxt < R and arrivals[nxt] <= now:
+                    queue.append(nxt)
+                    nxt += 1
+                for gi, grp in enumerate(groups):
+                    if busy[gi] is not None and busy[gi][0].query():
+                        tdone = time.perf_counter() - t0
+                        for i in busy[gi][1]:
+                            done[i] = tdone
+                        finished += len(busy[gi][1])
+                        busy[gi] = None
+                    if busy[gi] is None and queue:
+                        take, queue = queue[:len(grp)], queue[len(grp):]
+                        if mode == "per_request":
+                            g, a = dev_mocks[take[0] % len(dev_mocks)]
+                            grp[0].mesh_assign_cached(g, a)
+                            grp[0].pk()
+                        else:
+                            F.pk_batch(grp[:len(take)], [dev_mocks[i % len(dev_mocks)][0] for i in take], None,
+                                       [dev_mocks[i % len(dev_mocks)][1] for i in take])
+                        ev = torch.cuda.Event()
+                        ev.record(grp[0].stream)
+                        busy[gi] = (ev, take)
+                        sizes.append(len(take))
+            lat = 1e3 * (done - arrivals)
+            row[mode] = {"mocks_per_s": R / (done.max() - arrivals[0]), "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean(sizes)),
+                         "launch_groups": len(groups)}
+            log(f"batch serving N={N} {mode}: " + ", ".join(f"{k} {v:.4g}" for k, v in row[mode].items()))
+            for grp in groups:
+                for pl in grp:
+                    assert pl.status() == 0
+            del groups
+            torch.cuda.empty_cache()
+        out[str(N)] = {"pk_nbins": nb, "arrival_rate_per_s": rate, **row}
+    return {"requests": R, "results": out}
 
 
 SERVE_SIZES = (256, 384, 512)
@@ -889,6 +970,9 @@ def main():
     ap.add_argument("--batch-mocks", type=int, default=64, help="batch study: mocks per timed pass")
     ap.add_argument("--batch-n", default="64,128,256", help="batch study: mesh sides")
     ap.add_argument("--no-batch-study", action="store_true", help="skip the small-mesh batch study of the default run")
+    ap.add_argument("--batch-rates", default="2000,2600",
+                    help="batch study: Poisson arrival rates of the served run at 64^3 and 128^3 (1/s)")
+    ap.add_argument("--batch-requests", type=int, default=1024, help="batch study: requests of the served run (0: skip)")
     ap.add_argument("--batch-profile", action="store_true", help="batch study: batches of 16 only")
     ap.add_argument("--large-mesh", action="store_true",
                     help="run only the 1024^3 streamed precision sweep (FP32 vs FP64 vs the stored oracle)")
