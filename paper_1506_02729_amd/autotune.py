@@ -2,8 +2,9 @@
 
 The tunable parameters are those of ``frsd_tuning`` (include/fastrsd.h):
 the workgroup count of the matrix-core contraction, of the persistent
-forward z pass and of the binning kernel, and the number of shell-field
-pairs per inverse-FFT launch.  None changes a result beyond rounding order.
+forward z pass and of the binning kernel, the number of shell-field pairs
+per inverse-FFT launch, and the x run of the x-sweep assignment's
+workgroup tiles.  None changes a result beyond rounding order.
 The radix schedules of the FFT lengths are fixed at compile time (one
 schedule per length), so the tuner chooses launch tiles only.
 
@@ -30,12 +31,14 @@ CANDIDATES = {
     "row_grid": (1024, 2048, 4096, 8192),
     "bin_blocks": (1024, 2048, 4096),
     "pair_batch": (2, 4, 8, 16),
+    "sweep_x": (16, 32, 64),
 }
 AFFECTS = {
     "tri_wg": ("triple", "tri_reduce"),
     "row_grid": ("fft_z",),
     "bin_blocks": ("bin", "bin_reduce"),
     "pair_batch": ("shell_z", "shell_y", "shell_x"),
+    "sweep_x": ("grid", "grid_twin"),
 }
 
 

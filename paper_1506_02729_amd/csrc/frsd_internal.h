@@ -153,7 +153,7 @@ struct TabSeg {
 
 struct frsd_plan {
   frsd_params p{};
-  frsd_tuning tune{frsd::kTriMfmaBlocks, 4096, frsd::kBinBlocks, frsd::kPairBatch};
+  frsd_tuning tune{frsd::kTriMfmaBlocks, 4096, frsd::kBinBlocks, frsd::kPairBatch, 0};
   int N = 0;
   double h = 0, kf = 0;
   frsd::SlotDesc slots{};

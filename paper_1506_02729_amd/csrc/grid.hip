@@ -103,7 +103,7 @@ struct GridArgs {
                        // m0..n_ell_mom-1 per pass; planes are numbered from m0)
   double ou[3];        // observer in grid units
   long long plane_stride;
-  int sx;              // x-sweep: nodes along x per workgroup (64, 32 or 16)
+  int sx;              // x-sweep: nodes along x per workgroup (16, 32 or 64)
 };
 
 // Add the moment-weighted contribution s of one object to the 16
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(kGThreads) void k_grid(const int *__restrict__ offs
 // grids are separate passes (separate windows and rings).  The ring slots
 // are compile-time indices: the cell loop is unrolled by RING.
 // ---------------------------------------------------------------------------
-constexpr int kSY = 4, kSZ = 32, kSX = 64;
+constexpr int kSY = 4, kSZ = 32, kSX = 64;  // kSX: the longest x run of a workgroup (runs of 16, 32 or 64)
 constexpr int kSThreads = kSY * kSZ;                   // one node column per thread
 constexpr int kSCap = 1024;                            // staged objects per chunk (16 B each)
 constexpr int kSCellsMax = (kSY + 3) * (kSZ + 3);      // slab cells for a ring of 4
@@ -689,10 +689,10 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
                                                  ws_ptr<uint8_t>(ws, L.xmask), ws_ptr<uint8_t>(ws, L.colocc), bt));
   if constexpr (P <= 3) {
     if (N % kSX == 0 && N % kSZ == 0) {
-      // shorter x runs for small meshes, so that the launch (all requests of
-      // a batch) still has >= 2048 workgroups where it can
-      ga.sx = kSX;
-      while (ga.sx > 16 && (long long)(N / ga.sx) * (N / kSY) * (N / kSZ) * bt.n < 2048) ga.sx /= 2;
+      // x nodes per workgroup: the plan's tuning, else 16 (short runs spread
+      // a clustered mock over more workgroups, and small meshes get enough
+      // of them; each run re-stages 3 slabs of its neighbour's)
+      ga.sx = pl->tune.sweep_x ? pl->tune.sweep_x : 16;
       const unsigned nblk = (unsigned)((N / ga.sx) * (N / kSY) * (N / kSZ));
       FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk, bt.n), dim3(kSThreads), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),

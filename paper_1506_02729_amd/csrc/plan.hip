@@ -303,7 +303,8 @@ extern "C" int frsd_plan_set_tuning(frsd_plan *plan, const frsd_tuning *t) {
   clear_error();
   if (!plan || !t) return fail(FRSD_EINVAL, "null argument");
   if (t->tri_wg < 256 || t->tri_wg > kMaxTriWg || t->row_grid < 256 || t->row_grid > kMaxRowGrid ||
-      t->bin_blocks < 256 || t->bin_blocks > kMaxBinBlocks || t->pair_batch < 1 || t->pair_batch > kMaxPairBatch)
+      t->bin_blocks < 256 || t->bin_blocks > kMaxBinBlocks || t->pair_batch < 1 || t->pair_batch > kMaxPairBatch ||
+      (t->sweep_x != 0 && t->sweep_x != 16 && t->sweep_x != 32 && t->sweep_x != 64))
     return fail(FRSD_EINVAL, "tuning value out of range");
   plan->tune = *t;
   return FRSD_OK;

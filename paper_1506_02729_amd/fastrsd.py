@@ -53,7 +53,7 @@ class frsd_params(ctypes.Structure):
 
 
 class frsd_tuning(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_int32) for name in ("tri_wg", "row_grid", "bin_blocks", "pair_batch")]
+    _fields_ = [(name, ctypes.c_int32) for name in ("tri_wg", "row_grid", "bin_blocks", "pair_batch", "sweep_x")]
 
 
 FRSD_DEVICE, FRSD_HOST = 0, 1

@@ -146,11 +146,13 @@ def test_tuning_ranges_and_cache(tmp_path):
     cfg = F.Config(n_grid=64, box=500.0, observer=(-300, -300, -300), order=2, pk_dk=2 * kf, pk_nbins=16,
                    bk_kmin=1.5 * kf, bk_dk=3 * kf, bk_nbins=5, max_objects=1000)
     h = F.frsd_plan_create(cfg.to_c())
-    assert F.frsd_plan_get_tuning(h) == {"tri_wg": 1024, "row_grid": 4096, "bin_blocks": 2048, "pair_batch": 8}
-    good = {"tri_wg": 512, "row_grid": 2048, "bin_blocks": 4096, "pair_batch": 1}
+    assert F.frsd_plan_get_tuning(h) == {"tri_wg": 1024, "row_grid": 4096, "bin_blocks": 2048, "pair_batch": 8,
+                                         "sweep_x": 0}
+    good = {"tri_wg": 512, "row_grid": 2048, "bin_blocks": 4096, "pair_batch": 1, "sweep_x": 32}
     F.frsd_plan_set_tuning(h, good)
     assert F.frsd_plan_get_tuning(h) == good
-    for bad in ({"tri_wg": 4096}, {"row_grid": 100}, {"bin_blocks": 8192}, {"pair_batch": 0}, {"pair_batch": 17}):
+    for bad in ({"tri_wg": 4096}, {"row_grid": 100}, {"bin_blocks": 8192}, {"pair_batch": 0}, {"pair_batch": 17},
+                {"sweep_x": 8}, {"sweep_x": 48}, {"sweep_x": 128}):
         with pytest.raises(F.FrsdError) as ei:
             F.frsd_plan_set_tuning(h, dict(good, **bad))
         assert ei.value.code == F.FRSD_EINVAL
@@ -162,7 +164,7 @@ def test_tuning_ranges_and_cache(tmp_path):
     fake.cfg, fake.bk_grid, fake.handle = cfg, F.frsd_bk_grid(h), h
     path = tmp_path / "tuning.json"
     assert autotune.apply(fake, str(path)) is None
-    want = {"tri_wg": 768, "row_grid": 8192, "bin_blocks": 1024, "pair_batch": 4}
+    want = {"tri_wg": 768, "row_grid": 8192, "bin_blocks": 1024, "pair_batch": 4, "sweep_x": 16}
     path.write_text(json.dumps({autotune.shape_key(cfg, fake.bk_grid): {"tuning": want}}))
     assert autotune.apply(fake, str(path)) == want
     assert F.frsd_plan_get_tuning(h) == want

@@ -270,7 +270,7 @@ def test_random_cache(gpu_lib, precision, N, interlace, ell_max):
 @pytest.mark.parametrize("precision", [32, 64])
 def test_tuned_launch_parameters(gpu_lib, precision):
     """Other launch parameters (contraction, z-pass and binning workgroups,
-    shell pairs per launch) give the same results as the defaults, within
+    shell pairs per launch, x-sweep runs) give the same results as the defaults, within
     rounding (1e-5 of the largest value FP32, 1e-11 FP64), and the oracle's."""
     import torch
     _log(f"case: tuned launch parameters precision={precision}")
@@ -281,9 +281,9 @@ def test_tuned_launch_parameters(gpu_lib, precision):
     base = gpu_lib.Plan(cfg, device=dev).run(g, r, alpha)
     refp, refb = _oracle(gal, ran, alpha, prm)
     close = 1e-5 if precision == 32 else 1e-11
-    for t in ({"tri_wg": 512, "row_grid": 1024, "bin_blocks": 4096, "pair_batch": 1},
-              {"tri_wg": 2048, "row_grid": 16384, "bin_blocks": 256, "pair_batch": 3},
-              {"tri_wg": 768, "row_grid": 2048, "bin_blocks": 1024, "pair_batch": 16}):
+    for t in ({"tri_wg": 512, "row_grid": 1024, "bin_blocks": 4096, "pair_batch": 1, "sweep_x": 64},
+              {"tri_wg": 2048, "row_grid": 16384, "bin_blocks": 256, "pair_batch": 3, "sweep_x": 32},
+              {"tri_wg": 768, "row_grid": 2048, "bin_blocks": 1024, "pair_batch": 16, "sweep_x": 16}):
         plan = gpu_lib.Plan(cfg, device=dev)
         gpu_lib.frsd_plan_set_tuning(plan.handle, t)
         out = plan.run(g, r, alpha)
