@@ -168,7 +168,7 @@ typedef struct {
   int32_t bin_blocks;  /* workgroups of the binning kernel, 256..4096 (2048)               */
   int32_t pair_batch;  /* shell-field pairs per inverse-FFT launch, 1..16 (8)              */
   int32_t sweep_x;     /* x nodes per workgroup of the x-sweep assignment: 16, 32 or 64;
-                          0 (default): 16                                              */
+                          0 (default): 16, or 64 for streamed plans                    */
 } frsd_tuning;
 int frsd_plan_set_tuning(frsd_plan *plan, const frsd_tuning *tuning);
 int frsd_plan_get_tuning(const frsd_plan *plan, frsd_tuning *tuning);

@@ -691,8 +691,10 @@ static int launch_grid(frsd_plan *pl, void *ws, hipStream_t s, int n_ell_mom, in
     if (N % kSX == 0 && N % kSZ == 0) {
       // x nodes per workgroup: the plan's tuning, else 16 (short runs spread
       // a clustered mock over more workgroups, and small meshes get enough
-      // of them; each run re-stages 3 slabs of its neighbour's)
-      ga.sx = pl->tune.sweep_x ? pl->tune.sweep_x : 16;
+      // of them; each run re-stages 3 slabs of its neighbour's), or 64 for
+      // streamed plans, whose passes grid a few moments per visit, so that
+      // the re-staging weighs more
+      ga.sx = pl->tune.sweep_x ? pl->tune.sweep_x : (pl->p.stream_moments ? 64 : 16);
       const unsigned nblk = (unsigned)((N / ga.sx) * (N / kSY) * (N / kSZ));
       FRSD_TIMED("grid", s, hipLaunchKernelGGL((k_grid_sweep<T, P, false>), dim3(nblk, bt.n), dim3(kSThreads), 0, s,
                                                ws_ptr<const int>(ws, L.cnt), ws_ptr<const Rec4<T>>(ws, L.sorted),
