@@ -221,12 +221,13 @@ int frsd_pk_multipoles(frsd_plan *plan, void *ws, const frsd_pk_out *out, void *
 /* Steps a1-a6 for a batch of n requests of one shape, the many-mock case of
  * the paper's covariance use (Sec. III.C): plans[r] and workspaces[r] are n
  * plans created with equal frsd_params, each initialised on its own
- * workspace (distinct).  Per request the steps of frsd_mesh_assign(gal[r],
- * ran[r], alpha[r]) up to the assignment planes (launches of their own,
- * sized by its catalogues); then ONE forward FFT over all n requests' moment
- * meshes and ONE binning over all n (Sec. III.A eqs. (mapFFT),
- * (P0_impl)-(P4_impl)), so that small meshes share launches that fill the
- * device; then P_ell into out[r].  ran == NULL: every plan holds a random
+ * workspace (distinct).  Request r is frsd_mesh_assign(gal[r], ran[r],
+ * alpha[r]) followed by frsd_pk_multipoles into out[r] (Sec. III.A eqs.
+ * (mapFFT), (P0_impl)-(P4_impl)), and every kernel of those steps (ingest,
+ * sort, assignment, each forward FFT pass, binning) is ONE launch over all n
+ * requests, so that small meshes share launches that fill the device
+ * (catalogues of one role that differ in dtype are ingested one request at a
+ * time).  ran == NULL: every plan holds a random
  * cache (frsd_random_cache) and the galaxies are assigned against it, as
  * frsd_mesh_assign_cached.  gal, ran, alpha and out are host arrays of n
  * entries.  Results equal those of n calls of frsd_mesh_assign (or
