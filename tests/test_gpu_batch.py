@@ -86,6 +86,11 @@ def test_batch_matches_alone_and_oracle(gpu_lib, precision, N, interlace, ell_ma
             bk = {"bk_" + key: v.cpu().numpy().copy() for key, v in plans[k].bk().items()}
             _check_bk(bk, refb, prm, precision, plans[k])
         assert plans[k].status() == 0
+    if nbk:
+        # a batch after the bispectrum calls (which took the mesh regions), the requests in reverse order
+        again = gpu_lib.run_batch(plans, gals[::-1], rans[::-1], [a for _, _, a in reqs][::-1])
+        for k in range(n_req):
+            _same(again[k], outs[n_req - 1 - k], CLOSE[precision])
 
 
 @pytest.mark.parametrize("precision", [32, 64])
@@ -151,9 +156,10 @@ def test_largest_batch(gpu_lib):
 
 
 def test_batch_catalogue_dtypes(gpu_lib):
-    """FP32 catalogues in a batch (the ingest reads them as they are), and a
+    """FP32 catalogues in a batch (the ingest reads them as they are), a
     batch mixing FP32 and FP64 catalogues (ingested one request at a time),
-    on FP64 plans; the oracle gets the same FP32-rounded catalogues."""
+    and page-locked host catalogues, on FP64 plans; the oracle gets the same
+    FP32-rounded catalogues."""
     import torch
     dev = torch.device("cuda:0")
     _log("case: batch catalogue dtypes N=48 FP64")
@@ -173,3 +179,9 @@ def test_batch_catalogue_dtypes(gpu_lib):
             if dt == torch.float32:
                 g, r = rounded(g), rounded(r)
             _check_pk(outs[k], est.pk_multipoles(g, r, a, prm), prm, 64)
+    # catalogues in page-locked host memory, read in place by the ingest kernels
+    gals = [gpu_lib.pinned_catalog(g) for g, _, _ in reqs]
+    rans = [gpu_lib.pinned_catalog(r) for _, r, _ in reqs]
+    outs = gpu_lib.run_batch(plans, gals, rans, [a for _, _, a in reqs])
+    for k, (g, r, a) in enumerate(reqs):
+        _check_pk(outs[k], est.pk_multipoles(g, r, a, prm), prm, 64)
