@@ -11,10 +11,9 @@ struct frsd_graph {
   void *ws = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int64_t cap_gal = 0, cap_ran = 0;
-  int n = 1;
+  int n = 1;                  // requests
   void *wss[frsd::kMaxBatch] = {};
-  int64_t cap_g[frsd::kMaxBatch] = {}, cap_r[frsd::kMaxBatch] = {};
+  int64_t cap_g[frsd::kMaxBatch] = {}, cap_r[frsd::kMaxBatch] = {};  // catalogue capacities per request
 };
 
 namespace frsd {
@@ -108,8 +107,6 @@ extern "C" int frsd_graph_create(frsd_plan *plan, void *ws, const frsd_catalog *
   gr->ws = ws;
   gr->graph = g;
   gr->exec = ge;
-  gr->cap_gal = gal->n;
-  gr->cap_ran = ran->n;
   gr->wss[0] = ws;
   gr->cap_g[0] = gal->n;
   gr->cap_r[0] = ran->n;
@@ -121,7 +118,7 @@ extern "C" int frsd_graph_launch(frsd_graph *gr, int64_t n_gal, int64_t n_ran, d
   clear_error();
   if (!gr) return fail(FRSD_EINVAL, "null graph");
   if (gr->n != 1) return fail(FRSD_EINVAL, "a batch graph is replayed with frsd_graph_launch_batch");
-  if (n_gal < 0 || n_ran < 0 || n_gal > gr->cap_gal || n_ran > gr->cap_ran)
+  if (n_gal < 0 || n_ran < 0 || n_gal > gr->cap_g[0] || n_ran > gr->cap_r[0])
     return fail(FRSD_ENOMEM, "catalogue sizes beyond the capacity the graph was captured with");
   if (!std::isfinite(alpha)) return fail(FRSD_EINVAL, "alpha must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -195,8 +192,6 @@ extern "C" int frsd_graph_create_batch(frsd_plan *const *plans, void *const *wor
     gr->cap_g[r] = gd[r].n;
     gr->cap_r[r] = rd[r].n;
   }
-  gr->cap_gal = gd[0].n;
-  gr->cap_ran = rd[0].n;
   *graph = gr;
   return FRSD_OK;
 }
