@@ -1034,12 +1034,12 @@ def main():
     log(f"fp32 plan init (tables + N^T) {time.perf_counter() - t0:.2f} s, {nstream} workspace(s) of "
         f"{plan.ws_bytes / 1e9:.1f} GB")
     from paper_1506_02729_amd import autotune
+    def one(pl, it=iter(range(1 << 30))):  # one request on pl (autotuner runs)
+        g, r, a = dev_mocks[next(it) % len(dev_mocks)]
+        pl.mesh_assign(g, r, a)
+        pl.pk()
+        pl.bk()
     if args.autotune:
-        def one(pl, it=iter(range(1 << 30))):
-            g, r, a = dev_mocks[next(it) % len(dev_mocks)]
-            pl.mesh_assign(g, r, a)
-            pl.pk()
-            pl.bk()
         autotune.tune(plan, one, torch.cuda.synchronize, path=autotune.DEFAULT_CACHE, log=log)
     tuning = None if args.no_tuning else [autotune.apply(pl) for pl in plans][0]
     log(f"tuning: {tuning if tuning else 'library defaults'}")
@@ -1133,6 +1133,10 @@ def main():
     if not args.no_fp64 and args.fp64_steps > 0:
         cfg64 = make_config(F, wl, 64, observer, max_obj)
         plan64 = F.Plan(cfg64, device=dev)
+        if args.autotune:
+            autotune.tune(plan64, one, torch.cuda.synchronize, path=autotune.DEFAULT_CACHE, log=log)
+        tuning64 = None if args.no_tuning else autotune.apply(plan64)
+        log(f"fp64 tuning: {tuning64 if tuning64 else 'library defaults'}")
         run_steps(F, torch, plan64, dev_mocks[last:last + 1], 1, False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -1155,7 +1159,7 @@ def main():
         for ell in (0, 2, 4):
             ref = b64[f"t{ell}"][ok]
             cmp[f"T{ell}_max_rel_vs_max"] = float(np.max(np.abs(b32[f"t{ell}"][ok] - ref)) / np.max(np.abs(ref)))
-        fp64 = {"value": args.fp64_steps / e64, "unit": "mocks/s", "steps": args.fp64_steps,
+        fp64 = {"value": args.fp64_steps / e64, "unit": "mocks/s", "steps": args.fp64_steps, "tuning": tuning64,
                 "ms_per_step": 1e3 * e64 / args.fp64_steps, "fp32_vs_fp64": cmp}
         del plan64
         torch.cuda.empty_cache()
