@@ -67,6 +67,8 @@ def test_h512_against_oracle(h512, precision):
     tol = TOL[precision]
     cfg = h512["bench"].make_config(F, h512["wl"], precision, h512["obs"], h512["n_obj"])
     plan = F.Plan(cfg, device=torch.device("cuda:0"))
+    from paper_1506_02729_amd import autotune
+    _log(f"  launch parameters of the benchmark: {autotune.apply(plan)}")  # as bench.py times them
     out = plan.run(h512["g"], h512["r"], h512["alpha"])
     assert plan.status() == 0
 
