@@ -237,6 +237,19 @@ def test_batch_validation_on_host():
             with pytest.raises(F.FrsdError) as ei:
                 fn()
             assert ei.value.code == code, F.frsd_last_error()
+        # graph capture of a batch: randoms required, an explicit stream required, the batch checks as above
+        with pytest.raises(F.FrsdError) as ei:
+            F._check(F._lib.frsd_graph_create_batch((F._P * 2)(*hs[:2]), (F._P * 2)(*ws[:2]), 2,
+                                                    (F.frsd_catalog * 2)(gal, gal), None,
+                                                    (ctypes.c_double * 2)(1.0, 1.0), (F.frsd_pk_out * 2)(out, out),
+                                                    None, ctypes.byref(F._P())))
+        assert ei.value.code == F.FRSD_EINVAL
+        with pytest.raises(F.FrsdError) as ei:
+            F.frsd_graph_create_batch(hs[:2], ws[:2], [gal] * 2, [gal] * 2, [1.0] * 2, [out] * 2, None)
+        assert ei.value.code == F.FRSD_EINVAL  # null stream
+        with pytest.raises(F.FrsdError) as ei:
+            F.frsd_graph_launch_batch(None, [1], [1], [1.0], None)
+        assert ei.value.code == F.FRSD_EINVAL
         big = [gal] * (F.FRSD_MAX_BATCH + 1)
         with pytest.raises(F.FrsdError) as ei:
             F.frsd_pk_batch([hs[0]] * len(big), [ws[0]] * len(big), big, None, [1.0] * len(big),
