@@ -683,15 +683,17 @@ def batch_study(args, F, torch, synth, dev, log):
 
 
 def batch_serving(args, F, torch, dev, log, dev_mocks, r_dev, observer, box, n_ran):
-    """Continuous batching of small meshes: Poisson arrivals (--batch-rates
-    per second: one rate for 64^3, one for 128^3) of --batch-requests
-    covariance mocks (the batch study's, cycled), served two ways.  Per request:
-    three plans with a stream each; a queued request takes the first free
-    plan (frsd_mesh_assign_cached + frsd_pk_multipoles).  Batched: two groups
-    of 8 plans with a stream each; a free group takes every queued request
-    (up to 8) as one frsd_pk_batch, so requests that arrive while a batch runs
-    form the next one.  Outputs go to page-locked host arrays; latency runs
-    from arrival to the completion event of the request's launch."""
+    """Continuous batching of small meshes (paper_1506_02729_amd/serve.py):
+    Poisson arrivals (--batch-rates per second: one rate for 64^3, one for
+    128^3) of --batch-requests covariance mocks (the batch study's, cycled),
+    served two ways by a BatchServer holding the random catalogue's spectra in
+    every plan: per request (three groups of one plan, a stream each: a
+    queued request takes the first free plan) and batched (two groups of 8
+    plans, a stream each: a free group takes every queued request, up to 8,
+    as one frsd_pk_batch, so requests that arrive while a batch runs form
+    the next one).  Outputs go to page-locked host arrays and are copied out
+    per request; latency runs from arrival to the poll that completes it."""
+    from paper_1506_02729_amd.serve import BatchServer
     out = {}
     R = args.batch_requests
     for N, rate in zip((64, 128), (float(v) for v in args.batch_rates.split(","))):
@@ -702,59 +704,28 @@ def batch_serving(args, F, torch, dev, log, dev_mocks, r_dev, observer, box, n_r
         rng = np.random.Generator(np.random.PCG64(7000 + N))
         arrivals = np.cumsum(rng.exponential(1.0 / rate, R))
         row = {}
-        for mode in ("per_request", "batched"):
-            if mode == "per_request":
-                groups = [[F.Plan(cfg, device=dev, stream=torch.cuda.Stream(dev), host_outputs=True)] for _ in range(3)]
-            else:
-                groups = []
-                for _ in range(2):
-                    st = torch.cuda.Stream(dev)
-                    groups.append([F.Plan(cfg, device=dev, stream=st, host_outputs=True) for _ in range(8)])
-            for grp in groups:
-                for pl in grp:
-                    pl.random_cache(r_dev)
+        for mode, groups, size in (("per_request", 3, 1), ("batched", 2, 8)):
+            server = BatchServer(cfg, groups=groups, group_size=size, device=dev, randoms=r_dev)
             torch.cuda.synchronize()
-            busy = [None] * len(groups)  # (event, request ids) in flight per group
-            done = np.zeros(R)
-            sizes = []
-            nxt = 0
-            queue = []
+            lat = np.zeros(R)
+            nxt = finished = 0
             t0 = time.perf_counter()
-            finished = 0
             while finished < R:
                 now = time.perf_counter() - t0
                 while nxt < R and arrivals[nxt] <= now:
-                    queue.append(nxt)
+                    g, a = dev_mocks[nxt % len(dev_mocks)]
+                    server.submit(g, a).t_submit = t0 + arrivals[nxt]  # latency from the arrival
                     nxt += 1
-                for gi, grp in enumerate(groups):
-                    if busy[gi] is not None and busy[gi][0].query():
-                        tdone = time.perf_counter() - t0
-                        for i in busy[gi][1]:
-                            done[i] = tdone
-                        finished += len(busy[gi][1])
-                        busy[gi] = None
-                    if busy[gi] is None and queue:
-                        take, queue = queue[:len(grp)], queue[len(grp):]
-                        if mode == "per_request":
-                            g, a = dev_mocks[take[0] % len(dev_mocks)]
-                            grp[0].mesh_assign_cached(g, a)
-                            grp[0].pk()
-                        else:
-                            F.pk_batch(grp[:len(take)], [dev_mocks[i % len(dev_mocks)][0] for i in take], None,
-                                       [dev_mocks[i % len(dev_mocks)][1] for i in take])
-                        ev = torch.cuda.Event()
-                        ev.record(grp[0].stream)
-                        busy[gi] = (ev, take)
-                        sizes.append(len(take))
-            lat = 1e3 * (done - arrivals)
-            row[mode] = {"mocks_per_s": R / (done.max() - arrivals[0]), "p50_ms": float(np.percentile(lat, 50)),
-                         "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean(sizes)),
-                         "launch_groups": len(groups)}
+                for req in server.poll():
+                    lat[req.rid] = 1e3 * (req.t_done - req.t_submit)
+                    finished += 1
+            t_end = time.perf_counter() - t0
+            row[mode] = {"mocks_per_s": R / (t_end - arrivals[0]), "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "mean_batch": float(np.mean(server.batch_sizes)),
+                         "launch_groups": groups}
             log(f"batch serving N={N} {mode}: " + ", ".join(f"{k} {v:.4g}" for k, v in row[mode].items()))
-            for grp in groups:
-                for pl in grp:
-                    assert pl.status() == 0
-            del groups
+            assert server.rejected() == 0
+            del server
             torch.cuda.empty_cache()
         out[str(N)] = {"pk_nbins": nb, "arrival_rate_per_s": rate, **row}
     return {"requests": R, "results": out}

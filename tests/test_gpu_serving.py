@@ -91,3 +91,50 @@ def test_mixed_sizes_in_flight(gpu_lib):
         for key in ("p0", "p2", "p4", "p4b", "bk_t0", "bk_t2", "bk_t4"):
             scale = np.max(np.abs(alone[i][key]))
             assert np.max(np.abs(mix[key] - alone[i][key])) <= 1e-5 * scale, (i, key)
+
+
+@pytest.mark.parametrize("precision,cached", [(32, False), (64, True)])
+def test_batch_server_results_same_alone_and_in_the_mix(gpu_lib, precision, cached):
+    """The continuous-batching server (paper_1506_02729_amd/serve.py): ten
+    48^3 requests submitted together to two groups of four plans, so that
+    batches of up to four form while others run, each result equal to the
+    same request alone (within 1e-5 of the largest value for FP32, 1e-11 for
+    FP64) and two of them to the oracle; with cached randoms every request
+    shares one random catalogue."""
+    import torch
+    from paper_1506_02729_amd.serve import BatchServer
+    dev = torch.device("cuda:0")
+    _log(f"case: batch server, 10 requests, precision={precision} cached={cached}")
+    cases = [_bk_case(190 + i, nbk=1, n_gal=1500 + 200 * i, n_ran=9000 + 500 * i) for i in range(10)]
+    prm = cases[0][3]
+    prm.bk_nbins = 0
+    ran0 = cases[0][1]
+    if cached:
+        cases = [(g, ran0, len(g["w"]) / len(ran0["w"]), p) for g, _, _, p in cases]
+    cap = max(len(g["w"]) + len(r["w"]) for g, r, _, _ in cases)
+    cfg = _cfg(gpu_lib, prm, precision, cap)
+    cfg.random_cache = cached
+    r0 = gpu_lib.device_catalog(ran0, dev)
+    server = BatchServer(cfg, groups=2, group_size=4, device=dev, randoms=r0 if cached else None)
+    cats = [(gpu_lib.device_catalog(g, dev), None if cached else gpu_lib.device_catalog(r, dev), a)
+            for g, r, a, _ in cases]
+    torch.cuda.synchronize()
+    reqs = [server.submit(g, a, r) for g, r, a in cats]
+    done = server.drain()
+    assert sorted(r.rid for r in done) == [r.rid for r in reqs]
+    assert max(server.batch_sizes) > 1 and sum(server.batch_sizes) == len(reqs)
+    assert server.rejected() == 0
+    alone = gpu_lib.Plan(cfg, device=dev)
+    if cached:
+        alone.random_cache(r0)
+    close = 1e-5 if precision == 32 else 1e-11
+    for k, (req, (g, r, a)) in enumerate(zip(reqs, cats)):
+        ref = alone.run_cached(g, a, bispectrum=False) if cached else alone.run(g, r, a, bispectrum=False)
+        np.testing.assert_array_equal(req.result["n_modes"], ref["n_modes"])
+        np.testing.assert_allclose(req.result["scalars"], ref["scalars"], rtol=1e-12)
+        for key in ("p0", "p2", "p4", "p4b", "s00"):
+            scale = np.max(np.abs(ref[key]))
+            assert np.max(np.abs(req.result[key] - ref[key])) <= close * scale, (k, key)
+        if k in (0, 7):
+            gh, rh, ah, _ = cases[k]
+            _check_pk(req.result, est.pk_multipoles(gh, rh, ah, prm), prm, precision)
