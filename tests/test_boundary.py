@@ -258,3 +258,19 @@ def test_batch_validation_on_host():
     finally:
         for h in hs + [other]:
             F.frsd_plan_destroy(h)
+
+
+def test_batch_server_arguments():
+    """BatchServer refuses group sizes beyond a batch and a shared random
+    catalogue on a configuration without the random cache (before any
+    device work)."""
+    from paper_1506_02729_amd import fastrsd as F
+    from paper_1506_02729_amd.serve import BatchServer
+    kf = 2 * math.pi / 500.0
+    cfg = F.Config(n_grid=64, box=500.0, observer=(-300, -300, -300), order=2, pk_dk=2 * kf, pk_nbins=16,
+                   max_objects=1000)
+    for size in (0, F.FRSD_MAX_BATCH + 1):
+        with pytest.raises(ValueError):
+            BatchServer(cfg, group_size=size)
+    with pytest.raises(ValueError):
+        BatchServer(cfg, randoms={"pos": None, "w": None, "nbar": None})
